@@ -1,0 +1,198 @@
+/*
+ * sfhe.h -- C ABI of the MI355X (gfx950) library for encrypted matrix
+ * multiplication with unstructured sparsity.
+ *
+ * Method: Ferguson et al., "Exploiting Unstructured Sparsity in Fully
+ * Homomorphic Encrypted DNNs" (EuroMLSys '25).  The operands are matrices of
+ * CKKS ciphertexts, one value per ciphertext (chunk size c = 1, Sec. 3.2);
+ * C = A*B is formed by ciphertext products, relinearisation, rescaling and
+ * accumulation (Algorithm 1), and the zeros of A are skipped through the
+ * plaintext structure of one of the sparse schemes of Sec. 3.3.2 (naive
+ * sparse mask, CSR, ELLPACK), or not at all (naive dense, Sec. 3.3.1).
+ *
+ * Every function returns an int status: SFHE_OK (0) or a negative SFHE_E_*
+ * code; sfhe_last_error() then holds a message (thread-local).  No exception
+ * or abort crosses this boundary; a failed call leaves its output handles NULL
+ * and releases whatever it had allocated.
+ *
+ * Ownership: handles are opaque and owned by the library; the caller destroys
+ * them.  Host arrays passed in are borrowed for the duration of the call only.
+ * Device memory comes from the optional allocation hooks (a caching
+ * allocator), otherwise from hipMalloc.  A `stream` argument is a hipStream_t
+ * (NULL = the default stream); work is enqueued on it and calls that return
+ * host data synchronise it.
+ *
+ * The library plays both parties for benchmarking: the secret key lives in
+ * the context and never leaves it.
+ */
+#ifndef SFHE_H
+#define SFHE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFHE_OK 0
+#define SFHE_E_INVALID_ARG (-1)   /* NULL handle, bad enum, size out of range      */
+#define SFHE_E_PARAMS (-2)        /* parameter set rejected                        */
+#define SFHE_E_SHAPE (-3)         /* A.cols != B.rows, index out of range           */
+#define SFHE_E_LEVEL (-4)         /* no prime left to rescale, level mismatch       */
+#define SFHE_E_SCALE (-5)         /* operand scales differ                         */
+#define SFHE_E_UNSUPPORTED (-6)   /* a sparse-encoded right operand, logN > 14 ... */
+#define SFHE_E_NOMEM (-7)         /* device or host allocation failed               */
+#define SFHE_E_DEVICE (-8)        /* a HIP call failed (its text is in last_error)  */
+#define SFHE_E_STATE (-9)         /* keys not generated yet                        */
+#define SFHE_E_DECRYPT (-10)      /* a decrypted coefficient left the decodable range */
+
+typedef struct sfhe_ctx sfhe_ctx;   /* parameters, tables, keys (device resident) */
+typedef struct sfhe_mat sfhe_mat;   /* an encrypted matrix and its plaintext structure */
+
+/* Encodings of an operand (Sec. 3.3).  DENSE stores and visits every element
+ * (naive dense, Algorithm 1).  NAIVE_SPARSE stores every element, zeros
+ * included, and skips the products whose plaintext mask marks a zero.  CSR
+ * stores the nonzeros only, with plaintext row pointers and column indices.
+ * ELL stores max-nonzeros-per-row values per row, padded with trivial zero
+ * ciphertexts whose plaintext column index is -1; padding is skipped. */
+typedef enum {
+  SFHE_ENC_DENSE = 0,
+  SFHE_ENC_NAIVE_SPARSE = 1,
+  SFHE_ENC_CSR = 2,
+  SFHE_ENC_ELL = 3
+} sfhe_encoding;
+
+/* PER_PRODUCT follows Algorithm 1's order: every ciphertext product is
+ * relinearised and rescaled, then added into its output.  LAZY sums the
+ * degree-2 products of an output first and relinearises and rescales once per
+ * output.  Both are exact up to the noise they add; their ciphertexts differ. */
+typedef enum { SFHE_SCHED_PER_PRODUCT = 0, SFHE_SCHED_LAZY = 1 } sfhe_schedule;
+
+/* An RNS CKKS parameter set (Sec. 3.1).  Primes are generated: for each bit
+ * size in order (data primes q_0..q_{n_q-1}, then the special primes), the
+ * largest prime below 2^bits that is 1 mod 2N and not already taken.  The
+ * special primes form P for hybrid key switching with dnum digits of n_p data
+ * primes each (dnum must equal ceil(n_q / n_p)).  log_n in [10, 14]; bits in
+ * [log_n + 2, 61]; n_q >= 2; n_q + n_p <= 16. */
+typedef struct {
+  uint32_t log_n;
+  uint32_t n_q, n_p, dnum;
+  const uint32_t* q_bits;   /* n_q entries */
+  const uint32_t* p_bits;   /* n_p entries */
+  double log2_scale;        /* integer in [1, 60]: the encoding scale is 2^log2_scale */
+  double sigma;             /* error standard deviation; the sampler clips at |e| <= 19 */
+} sfhe_params;
+
+/* Optional device allocator.  alloc returns device memory or NULL; free
+ * receives the pointer and the size it was allocated with.  Both are called
+ * from the thread that called into the library. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, size_t bytes, void* user);
+  void* user;
+} sfhe_device_hooks;
+
+typedef struct {
+  int32_t rows, cols;
+  int32_t level;            /* index of the last prime in use; limbs = level + 1 */
+  double scale;
+  sfhe_encoding enc;
+  int64_t n_ciphertexts;    /* stored ciphertexts (ELL padding included) */
+  int64_t nnz;              /* nonzero elements (the values that are encrypted) */
+  int32_t ell_width;        /* ELL only, else 0 */
+  uint64_t device_bytes;    /* ciphertext bytes held on the device (Sec. 4.4 memory) */
+} sfhe_mat_info;
+
+typedef struct {
+  double ms;                /* device time of the last sfhe_matmul (hipEvents) */
+  int64_t products;         /* ct x ct tensor products executed */
+  int64_t keyswitches;      /* relinearisations executed */
+  int64_t outputs;          /* output ciphertexts written (trivial zeros included) */
+} sfhe_stats;
+
+/* Create a context: generate the primes, twiddle and conversion tables and
+ * upload them.  hooks may be NULL.  Fails with SFHE_E_PARAMS for an invalid
+ * set and SFHE_E_DEVICE when no gfx950 device is usable. */
+int sfhe_ctx_create(const sfhe_params* params, const sfhe_device_hooks* hooks, sfhe_ctx** out);
+void sfhe_ctx_destroy(sfhe_ctx* ctx);
+
+/* The ring degree N and the basis primes (data primes, then special primes);
+ * cap is the capacity of out in entries. */
+int sfhe_ctx_n(const sfhe_ctx* ctx, int32_t* n);
+int sfhe_ctx_primes(const sfhe_ctx* ctx, uint64_t* out, size_t cap);
+
+/* Generate the ternary secret and the relinearisation key from seed (keys
+ * stay on the device).  Must precede any encryption. */
+int sfhe_keygen(sfhe_ctx* ctx, uint64_t seed);
+
+/* Encrypt a rows x cols row-major fp64 matrix (leading dimension ld >= cols)
+ * with the given encoding: one secret-key ciphertext per stored element,
+ * value in slot 0, at the top level with scale 2^log2_scale.  Element (i, j)
+ * draws its randomness from (seed, operand_id, i, j) only, so an element has
+ * the same ciphertext under every encoding.  An element is zero iff it
+ * compares equal to 0.0.  |value| * 2^(log2_scale + 1 - log_n) must stay
+ * below 2^62. */
+int sfhe_encrypt_matrix(sfhe_ctx* ctx, const double* vals, int32_t rows, int32_t cols, int64_t ld,
+                        sfhe_encoding enc, uint64_t seed, uint32_t operand_id, void* stream,
+                        sfhe_mat** out);
+
+/* C = A * B (Algorithm 1 at c = 1 with A's zeros skipped per its encoding).
+ * A and B must be at the same level (>= 1) with equal scales, B DENSE.  The
+ * result is a DENSE matrix one level lower with scale^2 / q_level.  Outputs
+ * with no nonzero product are trivial zero ciphertexts.  The device time is
+ * reported by sfhe_last_stats. */
+int sfhe_matmul(sfhe_ctx* ctx, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched,
+                void* stream, sfhe_mat** C);
+
+/* Decrypt and decode every element to out (row-major, leading dimension ld).
+ * Elements that an encoding does not store decrypt to 0.0. */
+int sfhe_decrypt_matrix(sfhe_ctx* ctx, const sfhe_mat* m, double* out, int64_t ld, void* stream);
+
+/* Copy one stored ciphertext of element (i, j), in the coefficient domain
+ * with residues in [0, q), to host memory: out[2][level+1][N].  cap is the
+ * capacity in entries.  An element the encoding does not store is an error
+ * (SFHE_E_SHAPE); an ELL padding slot is not addressable. */
+int sfhe_export_ct(sfhe_ctx* ctx, const sfhe_mat* m, int32_t i, int32_t j, uint64_t* out, size_t cap,
+                   void* stream);
+
+int sfhe_matrix_info(const sfhe_mat* m, sfhe_mat_info* out);
+int sfhe_last_stats(const sfhe_ctx* ctx, sfhe_stats* out);
+void sfhe_mat_destroy(sfhe_mat* m);
+const char* sfhe_last_error(void);
+
+/* ---- Primitive steps on caller-owned device buffers --------------------
+ * The steps one ciphertext product goes through (Algorithm 1: multiply,
+ * relinearise, rescale), exposed for testing and composition.  Polynomials
+ * are rows of N uint64 residues in [0, q); "NTT domain" means the negacyclic
+ * transform with index k holding a(psi^(2*brv(k)+1)), psi the smallest
+ * primitive 2N-th root of unity mod q.  Buffers must not overlap unless
+ * stated. */
+
+/* In-place negacyclic NTT (inverse = 0) or inverse NTT (inverse = 1) of
+ * `batch` groups of n_limbs rows laid out [batch][n_limbs][N]; row l of a
+ * group is taken modulo basis prime first_prime + l. */
+int sfhe_ntt(sfhe_ctx* ctx, uint64_t* data, int32_t batch, int32_t n_limbs, int32_t first_prime,
+             int32_t inverse, void* stream);
+
+/* Tensor product of degree-1 ciphertexts at `level`, NTT domain:
+ * a, b [batch][2][level+1][N] -> d [batch][3][level+1][N] with
+ * d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1. */
+int sfhe_tensor(sfhe_ctx* ctx, int32_t level, const uint64_t* a, const uint64_t* b, uint64_t* d,
+                int32_t batch, void* stream);
+
+/* Relinearisation key switch of degree-2 parts at `level`, NTT domain:
+ * d2 [batch][level+1][N] -> out [batch][2][level+1][N] with
+ * out0 + out1*s = d2*s^2 + small.  Needs keys. */
+int sfhe_keyswitch(sfhe_ctx* ctx, int32_t level, const uint64_t* d2, uint64_t* out, int32_t batch,
+                   void* stream);
+
+/* Rescale by the last prime of `level` (level >= 1), NTT domain, with exact
+ * rounding (centered lift): in [batch][2][level+1][N] -> out [batch][2][level][N]. */
+int sfhe_rescale(sfhe_ctx* ctx, int32_t level, const uint64_t* in, uint64_t* out, int32_t batch,
+                 void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFHE_H */

@@ -714,7 +714,7 @@ static void mm_output(const mm_job* J, int i, int j, u64* o) {
           x0[t] += (u128)a0[t] * b0[t];
           x1[t] += (u128)a0[t] * b1[t]; x1[t] += (u128)a1[t] * b0[t];
           x2[t] += (u128)a1[t] * b1[t];
-          if ((n & 63) == 63) { x0[t] %= q; x1[t] %= q; x2[t] %= q; }   /* keep below 2^128 */
+          if ((n & 31) == 31) { x0[t] %= q; x1[t] %= q; x2[t] %= q; }   /* 64 terms < 2^122 stay below 2^128 */
         }
       }
     }

@@ -1,0 +1,791 @@
+// capi.hip -- the C ABI: parameter set-up, keys, encryption of matrices under
+// the encodings of Sec. 3.3, the encrypted product C = A*B in both
+// accumulation orders, decryption, and the primitive steps.
+#include <math.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hostmath.hpp"
+#include "internal.hpp"
+
+namespace sfhe {
+
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+
+void* Alloc::get(size_t bytes) {
+  if (bytes == 0) return nullptr;
+  if (has_hooks) return hooks.alloc(bytes, hooks.user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+void Alloc::put(void* p, size_t bytes) {
+  if (!p) return;
+  if (has_hooks) {
+    hooks.free(p, bytes, hooks.user);
+  } else {
+    // work queued on any stream may still read the buffer
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p);
+  }
+}
+
+static int brv(int x, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) { r = (r << 1) | (x & 1); x >>= 1; }
+  return r;
+}
+
+template <typename T>
+static bool upload(sfhe_ctx* c, DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
+  if (!buf.alloc(&c->alloc, v.size())) return false;
+  if (v.empty()) return true;
+  return hipMemcpyAsync(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s) == hipSuccess;
+}
+
+// ---------------------------------------------------------------- context
+static int build_tables(sfhe_ctx* c) {
+  using namespace hostmath;
+  const int N = c->N, nb = c->nb;
+  std::vector<u64> tab((size_t)nb * 4 * N);
+  for (int r = 0; r < nb; ++r) {
+    const u64 q = c->primes[r];
+    const u64 psi = smallest_primitive_root_2n(q, 2 * (u64)N);
+    const u64 psi_inv = invmod(psi, q);
+    std::vector<u64> pw(N), ipw(N);
+    pw[0] = 1;
+    ipw[0] = 1;
+    for (int k = 1; k < N; ++k) { pw[k] = mulmod(pw[k - 1], psi, q); ipw[k] = mulmod(ipw[k - 1], psi_inv, q); }
+    u64* tw = tab.data() + ((size_t)r * 4 + 0) * N;
+    u64* tws = tab.data() + ((size_t)r * 4 + 1) * N;
+    u64* itw = tab.data() + ((size_t)r * 4 + 2) * N;
+    u64* itws = tab.data() + ((size_t)r * 4 + 3) * N;
+    for (int m = 0; m < N; ++m) {
+      const int e = brv(m, c->logN);
+      tw[m] = pw[e];
+      tws[m] = shoup(tw[m], q);
+      itw[m] = ipw[e];
+      itws[m] = shoup(itw[m], q);
+    }
+    PrimeDev& P = c->dp.pr[r];
+    P.q = q;
+    barrett128(q, &P.mu_hi, &P.mu_lo);
+    P.ninv = invmod((u64)N % q, q);
+    P.ninv_s = shoup(P.ninv, q);
+  }
+  if (!c->d_tables.alloc(&c->alloc, tab.size())) return SFHE_E_NOMEM;
+  SFHE_HIP(hipMemcpy(c->d_tables.ptr, tab.data(), tab.size() * sizeof(u64), hipMemcpyHostToDevice));
+  for (int r = 0; r < nb; ++r) {
+    PrimeDev& P = c->dp.pr[r];
+    P.tw = c->d_tables.ptr + ((size_t)r * 4 + 0) * N;
+    P.tws = c->d_tables.ptr + ((size_t)r * 4 + 1) * N;
+    P.itw = c->d_tables.ptr + ((size_t)r * 4 + 2) * N;
+    P.itws = c->d_tables.ptr + ((size_t)r * 4 + 3) * N;
+  }
+  // slot-0 decoding / encoding weights, from the host libm
+  std::vector<double> cv(N);
+  for (int t = 0; t < N; ++t) cv[t] = cos(M_PI * (double)t / (double)N);
+  if (!c->d_cos.alloc(&c->alloc, N)) return SFHE_E_NOMEM;
+  SFHE_HIP(hipMemcpy(c->d_cos.ptr, cv.data(), N * sizeof(double), hipMemcpyHostToDevice));
+  // discrete Gaussian cumulative table over |e| = 0..19:
+  // T[k] = floor(2^63 P(|e| <= k)), rho(x) = exp(-x^2 / (2 sigma^2))
+  {
+    double rho[kCdtLen];
+    for (int x = 0; x < kCdtLen; ++x) rho[x] = exp(-(double)(x * x) / (2.0 * c->sigma * c->sigma));
+    double total = rho[0];
+    for (int x = 1; x < kCdtLen; ++x) total += 2.0 * rho[x];
+    double run = rho[0];
+    for (int k = 0; k < kCdtLen; ++k) {
+      if (k > 0) run += 2.0 * rho[k];
+      c->cdt[k] = (u64)((run / total) * 9223372036854775808.0);
+    }
+  }
+  // base-conversion constants
+  const int L = c->L, al = c->alpha, dnum = c->dnum;
+  std::vector<ModUpConst> mu((size_t)L * dnum);
+  std::vector<ModDownConst> md(L);
+  std::vector<RescaleConst> rs(L);
+  std::memset(mu.data(), 0, mu.size() * sizeof(ModUpConst));
+  std::memset(md.data(), 0, md.size() * sizeof(ModDownConst));
+  std::memset(rs.data(), 0, rs.size() * sizeof(RescaleConst));
+  auto basis_of = [&](int lev, int e) { return e <= lev ? e : L + (e - lev - 1); };
+  for (int lev = 0; lev < L; ++lev) {
+    const int nl = lev + 1;
+    for (int j = 0; j < dnum; ++j) {
+      ModUpConst& m = mu[(size_t)lev * dnum + j];
+      m.lo = j * al;
+      m.hi = std::min((j + 1) * al, nl);
+      m.ne = nl + al;
+      for (int e = 0; e < m.ne; ++e) m.basis[e] = basis_of(lev, e);
+      if (m.lo >= m.hi) continue;
+      for (int i = m.lo; i < m.hi; ++i) {
+        const u64 qi = c->primes[i];
+        u64 dq = 1;   // (D/q_i) mod q_i
+        for (int i2 = m.lo; i2 < m.hi; ++i2)
+          if (i2 != i) dq = mulmod(dq, c->primes[i2] % qi, qi);
+        m.inv[i - m.lo] = invmod(dq, qi);
+        m.inv_s[i - m.lo] = shoup(m.inv[i - m.lo], qi);
+        for (int e = 0; e < m.ne; ++e) {
+          const u64 qe = c->primes[m.basis[e]];
+          u64 v = 1;  // (D/q_i) mod q_e
+          for (int i2 = m.lo; i2 < m.hi; ++i2)
+            if (i2 != i) v = mulmod(v, c->primes[i2] % qe, qe);
+          m.conv[i - m.lo][e] = v;
+          m.conv_s[i - m.lo][e] = shoup(v, qe);
+        }
+      }
+    }
+    ModDownConst& d = md[lev];
+    for (int k = 0; k < al; ++k) {
+      const u64 pk = c->primes[L + k];
+      u64 v = 1;
+      for (int k2 = 0; k2 < al; ++k2)
+        if (k2 != k) v = mulmod(v, c->primes[L + k2] % pk, pk);
+      d.pinv[k] = invmod(v, pk);
+      d.pinv_s[k] = shoup(d.pinv[k], pk);
+      for (int i = 0; i < nl; ++i) {
+        const u64 qi = c->primes[i];
+        u64 w = 1;
+        for (int k2 = 0; k2 < al; ++k2)
+          if (k2 != k) w = mulmod(w, c->primes[L + k2] % qi, qi);
+        d.conv[k][i] = w;
+        d.conv_s[k][i] = shoup(w, qi);
+      }
+    }
+    for (int i = 0; i < nl; ++i) {
+      const u64 qi = c->primes[i];
+      u64 P = 1;
+      for (int k = 0; k < al; ++k) P = mulmod(P, c->primes[L + k] % qi, qi);
+      d.Pinv[i] = invmod(P, qi);
+      d.Pinv_s[i] = shoup(d.Pinv[i], qi);
+    }
+    RescaleConst& rc = rs[lev];
+    for (int i = 0; i < lev; ++i) {
+      const u64 qi = c->primes[i];
+      rc.qinv[i] = invmod(c->primes[lev] % qi, qi);
+      rc.qinv_s[i] = shoup(rc.qinv[i], qi);
+    }
+  }
+  if (!c->d_modup.alloc(&c->alloc, mu.size()) || !c->d_moddown.alloc(&c->alloc, md.size()) ||
+      !c->d_rescale.alloc(&c->alloc, rs.size()))
+    return SFHE_E_NOMEM;
+  SFHE_HIP(hipMemcpy(c->d_modup.ptr, mu.data(), mu.size() * sizeof(ModUpConst), hipMemcpyHostToDevice));
+  SFHE_HIP(hipMemcpy(c->d_moddown.ptr, md.data(), md.size() * sizeof(ModDownConst), hipMemcpyHostToDevice));
+  SFHE_HIP(hipMemcpy(c->d_rescale.ptr, rs.data(), rs.size() * sizeof(RescaleConst), hipMemcpyHostToDevice));
+  return SFHE_OK;
+}
+
+static int gen_primes(sfhe_ctx* c, const std::vector<uint32_t>& bits) {
+  const u64 two_n = 2 * (u64)c->N;
+  for (size_t r = 0; r < bits.size(); ++r) {
+    const u64 top = 1ull << bits[r];
+    u64 cand = (top - 1) / two_n * two_n + 1;   // largest value = 1 mod 2N below 2^bits
+    if (cand >= top) cand -= two_n;
+    for (;;) {
+      if (cand <= two_n) return SFHE_E_PARAMS;
+      if (std::find(c->primes.begin(), c->primes.end(), cand) == c->primes.end() && hostmath::is_prime(cand)) break;
+      cand -= two_n;
+    }
+    c->primes.push_back(cand);
+  }
+  return SFHE_OK;
+}
+
+// rows visited by row i of A under its encoding
+static int64_t row_visits(const sfhe_mat* A, int i) {
+  switch (A->enc) {
+    case SFHE_ENC_DENSE: return A->cols;
+    case SFHE_ENC_NAIVE_SPARSE: {
+      int64_t n = 0;
+      for (int k = 0; k < A->cols; ++k) {
+        const int64_t e = (int64_t)i * A->cols + k;
+        n += !((A->zero_mask[e >> 5] >> (e & 31)) & 1u);
+      }
+      return n;
+    }
+    case SFHE_ENC_CSR: return A->row_ptr[i + 1] - A->row_ptr[i];
+    case SFHE_ENC_ELL: {
+      int64_t n = 0;
+      for (int s = 0; s < A->ell_w; ++s) n += A->ell_col[(size_t)i * A->ell_w + s] >= 0;
+      return n;
+    }
+  }
+  return 0;
+}
+// the (k, A slot) pairs row i visits, ascending k
+static void row_pairs(const sfhe_mat* A, int i, std::vector<std::pair<int, int64_t>>& out) {
+  out.clear();
+  switch (A->enc) {
+    case SFHE_ENC_DENSE:
+      for (int k = 0; k < A->cols; ++k) out.push_back({k, (int64_t)i * A->cols + k});
+      break;
+    case SFHE_ENC_NAIVE_SPARSE:
+      for (int k = 0; k < A->cols; ++k) {
+        const int64_t e = (int64_t)i * A->cols + k;
+        if (!((A->zero_mask[e >> 5] >> (e & 31)) & 1u)) out.push_back({k, e});
+      }
+      break;
+    case SFHE_ENC_CSR:
+      for (int p = A->row_ptr[i]; p < A->row_ptr[i + 1]; ++p) out.push_back({A->col_idx[p], (int64_t)p});
+      break;
+    case SFHE_ENC_ELL:
+      for (int s = 0; s < A->ell_w; ++s) {
+        const int k = A->ell_col[(size_t)i * A->ell_w + s];
+        if (k >= 0) out.push_back({k, (int64_t)i * A->ell_w + s});
+      }
+      break;
+  }
+}
+
+// stored slot of element (i, j), or -1
+static int64_t slot_of(const sfhe_mat* m, int i, int j) {
+  switch (m->enc) {
+    case SFHE_ENC_DENSE:
+    case SFHE_ENC_NAIVE_SPARSE: return (int64_t)i * m->cols + j;
+    case SFHE_ENC_CSR:
+      for (int p = m->row_ptr[i]; p < m->row_ptr[i + 1]; ++p)
+        if (m->col_idx[p] == j) return p;
+      return -1;
+    case SFHE_ENC_ELL:
+      for (int s = 0; s < m->ell_w; ++s)
+        if (m->ell_col[(size_t)i * m->ell_w + s] == j) return (int64_t)i * m->ell_w + s;
+      return -1;
+  }
+  return -1;
+}
+
+}  // namespace sfhe
+
+using namespace sfhe;
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                   \
+  }                                                                 \
+  catch (const std::bad_alloc&) {                                   \
+    set_error("host allocation failed");                            \
+    return SFHE_E_NOMEM;                                            \
+  }                                                                 \
+  catch (...) {                                                     \
+    set_error("unexpected internal error");                         \
+    return SFHE_E_INVALID_ARG;                                      \
+  }
+
+extern "C" {
+
+const char* sfhe_last_error(void) { return g_err.c_str(); }
+
+int sfhe_ctx_create(const sfhe_params* p, const sfhe_device_hooks* hooks, sfhe_ctx** out) {
+  GUARD_BEGIN
+  if (!out) { set_error("out is NULL"); return SFHE_E_INVALID_ARG; }
+  *out = nullptr;
+  if (!p || !p->q_bits || !p->p_bits) { set_error("params or bit lists are NULL"); return SFHE_E_INVALID_ARG; }
+  if (p->log_n < 10 || p->log_n > 14) { set_error("log_n must be in [10, 14]"); return SFHE_E_PARAMS; }
+  if (p->n_q < 2 || p->n_p < 1 || p->n_q + p->n_p > (uint32_t)kMaxBasis || p->n_p > (uint32_t)kMaxDigit) {
+    set_error("need 2 <= n_q, 1 <= n_p <= 8, n_q + n_p <= 16");
+    return SFHE_E_PARAMS;
+  }
+  if (p->dnum != (p->n_q + p->n_p - 1) / p->n_p) { set_error("dnum must equal ceil(n_q / n_p)"); return SFHE_E_PARAMS; }
+  if (!(p->log2_scale >= 1 && p->log2_scale <= 60 && p->log2_scale == floor(p->log2_scale))) {
+    set_error("log2_scale must be an integer in [1, 60]");
+    return SFHE_E_PARAMS;
+  }
+  if (!(p->sigma > 0 && p->sigma < 100)) { set_error("sigma out of range"); return SFHE_E_PARAMS; }
+  std::vector<uint32_t> bits;
+  for (uint32_t i = 0; i < p->n_q; ++i) bits.push_back(p->q_bits[i]);
+  for (uint32_t i = 0; i < p->n_p; ++i) bits.push_back(p->p_bits[i]);
+  for (uint32_t b : bits)
+    if (b < p->log_n + 2 || b > 61) { set_error("prime bit sizes must be in [log_n + 2, 61]"); return SFHE_E_PARAMS; }
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { set_error("no HIP device"); return SFHE_E_DEVICE; }
+  int dev = 0;
+  SFHE_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  SFHE_HIP(hipGetDeviceProperties(&prop, dev));
+  if (std::string(prop.gcnArchName).find("gfx950") == std::string::npos) {
+    set_error(std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    return SFHE_E_DEVICE;
+  }
+
+  sfhe_ctx* c = new sfhe_ctx();
+  c->device = dev;
+  c->logN = (int)p->log_n;
+  c->N = 1 << c->logN;
+  c->L = (int)p->n_q;
+  c->alpha = (int)p->n_p;
+  c->dnum = (int)p->dnum;
+  c->nb = c->L + c->alpha;
+  c->log2_scale = p->log2_scale;
+  c->sigma = p->sigma;
+  if (hooks) {
+    if (!hooks->alloc || !hooks->free) { delete c; set_error("hooks need alloc and free"); return SFHE_E_INVALID_ARG; }
+    c->alloc.hooks = *hooks;
+    c->alloc.has_hooks = true;
+  }
+  int rc = gen_primes(c, bits);
+  if (rc) { delete c; set_error("not enough NTT primes of the requested sizes"); return rc; }
+  c->dp.N = c->N;
+  c->dp.logN = c->logN;
+  c->dp.L = c->L;
+  c->dp.alpha = c->alpha;
+  c->dp.dnum = c->dnum;
+  c->dp.nb = c->nb;
+  rc = build_tables(c);
+  if (rc) {
+    if (rc == SFHE_E_NOMEM) set_error("device allocation failed while building tables");
+    delete c;
+    return rc;
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    delete c;
+    set_error("hipEventCreate failed");
+    return SFHE_E_DEVICE;
+  }
+  *out = c;
+  return SFHE_OK;
+  GUARD_END
+}
+
+void sfhe_ctx_destroy(sfhe_ctx* c) {
+  if (!c) return;
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+int sfhe_ctx_n(const sfhe_ctx* c, int32_t* n) {
+  if (!c || !n) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  *n = c->N;
+  return SFHE_OK;
+}
+
+int sfhe_ctx_primes(const sfhe_ctx* c, uint64_t* out, size_t cap) {
+  if (!c || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (cap < (size_t)c->nb) { set_error("capacity below the basis size"); return SFHE_E_INVALID_ARG; }
+  for (int r = 0; r < c->nb; ++r) out[r] = c->primes[r];
+  return SFHE_OK;
+}
+
+int sfhe_keygen(sfhe_ctx* c, uint64_t seed) {
+  GUARD_BEGIN
+  if (!c) { set_error("NULL context"); return SFHE_E_INVALID_ARG; }
+  c->has_keys = false;
+  int rc = keygen_device(c, seed, nullptr);
+  if (rc) return rc;
+  c->has_keys = true;
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_encrypt_matrix(sfhe_ctx* c, const double* vals, int32_t rows, int32_t cols, int64_t ld, sfhe_encoding enc,
+                        uint64_t seed, uint32_t operand_id, void* stream, sfhe_mat** out) {
+  GUARD_BEGIN
+  if (!out) { set_error("out is NULL"); return SFHE_E_INVALID_ARG; }
+  *out = nullptr;
+  if (!c || !vals) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
+  if (rows < 1 || cols < 1 || ld < cols) { set_error("bad shape or leading dimension"); return SFHE_E_SHAPE; }
+  if ((int)enc < 0 || (int)enc > 3) { set_error("bad encoding"); return SFHE_E_INVALID_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  const double lim = ldexp(1.0, 62 - ((int)c->log2_scale + 1 - c->logN));
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < cols; ++j) {
+      const double v = vals[(int64_t)i * ld + j];
+      if (!(fabs(v) < lim)) { set_error("value not finite or too large to encode"); return SFHE_E_INVALID_ARG; }
+    }
+  sfhe_mat* m = new sfhe_mat();
+  m->ctx = c;
+  m->rows = rows;
+  m->cols = cols;
+  m->level = c->L - 1;
+  m->scale = ldexp(1.0, (int)c->log2_scale);
+  m->enc = enc;
+  std::vector<int> ei, ej;
+  std::vector<double> z;
+  std::vector<int64_t> slot;
+  auto nz = [&](int i, int j) { return vals[(int64_t)i * ld + j] != 0.0; };
+  int64_t nnz = 0;
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < cols; ++j) nnz += nz(i, j);
+  m->nnz = nnz;
+  auto push = [&](int i, int j, int64_t sl) {
+    ei.push_back(i);
+    ej.push_back(j);
+    z.push_back(vals[(int64_t)i * ld + j]);
+    slot.push_back(sl);
+  };
+  switch (enc) {
+    case SFHE_ENC_DENSE:
+    case SFHE_ENC_NAIVE_SPARSE:
+      m->n_ct = (int64_t)rows * cols;
+      for (int i = 0; i < rows; ++i)
+        for (int j = 0; j < cols; ++j) push(i, j, (int64_t)i * cols + j);
+      if (enc == SFHE_ENC_NAIVE_SPARSE) {
+        m->zero_mask.assign((size_t)((int64_t)rows * cols + 31) / 32, 0u);
+        for (int i = 0; i < rows; ++i)
+          for (int j = 0; j < cols; ++j)
+            if (!nz(i, j)) {
+              const int64_t e = (int64_t)i * cols + j;
+              m->zero_mask[e >> 5] |= 1u << (e & 31);
+            }
+      }
+      break;
+    case SFHE_ENC_CSR:
+      m->row_ptr.assign(rows + 1, 0);
+      for (int i = 0; i < rows; ++i) {
+        m->row_ptr[i] = (int)m->col_idx.size();
+        for (int j = 0; j < cols; ++j)
+          if (nz(i, j)) { push(i, j, (int64_t)m->col_idx.size()); m->col_idx.push_back(j); }
+      }
+      m->row_ptr[rows] = (int)m->col_idx.size();
+      m->n_ct = (int64_t)m->col_idx.size();
+      break;
+    case SFHE_ENC_ELL: {
+      int w = 0;
+      for (int i = 0; i < rows; ++i) {
+        int n = 0;
+        for (int j = 0; j < cols; ++j) n += nz(i, j);
+        w = std::max(w, n);
+      }
+      m->ell_w = w;
+      m->ell_col.assign((size_t)rows * w, -1);
+      for (int i = 0; i < rows; ++i) {
+        int n = 0;
+        for (int j = 0; j < cols; ++j)
+          if (nz(i, j)) { m->ell_col[(size_t)i * w + n] = j; push(i, j, (int64_t)i * w + n); ++n; }
+      }
+      m->n_ct = (int64_t)rows * w;
+      break;
+    }
+  }
+  const int N = c->N, L = c->L;
+  int rc = SFHE_OK;
+  const size_t words = (size_t)m->n_ct * 2 * L * N;
+  if (!m->data.alloc(&c->alloc, words)) { delete m; set_error("device allocation failed for the ciphertexts"); return SFHE_E_NOMEM; }
+  if (enc == SFHE_ENC_ELL) rc = launch_zero(m->data.ptr, (int64_t)words, s);
+  DevBuf<int> d_ei, d_ej;
+  DevBuf<double> d_z;
+  DevBuf<int64_t> d_slot;
+  if (!rc && (!upload(c, d_ei, ei, s) || !upload(c, d_ej, ej, s) || !upload(c, d_z, z, s) || !upload(c, d_slot, slot, s))) {
+    rc = SFHE_E_NOMEM;
+    set_error("device allocation failed");
+  }
+  if (!rc) rc = encrypt_elements(c, m->data.ptr, (int64_t)ei.size(), d_ei.ptr, d_ej.ptr, d_z.ptr, d_slot.ptr, seed,
+                                 operand_id, s);
+  if (!rc) rc = encrypt_finish(c, m->data.ptr, m->n_ct, s);
+  if (!rc && (!upload(c, m->d_row_ptr, m->row_ptr, s) || !upload(c, m->d_col_idx, m->col_idx, s) ||
+              !upload(c, m->d_ell_col, m->ell_col, s) || !upload(c, m->d_mask, m->zero_mask, s))) {
+    rc = SFHE_E_NOMEM;
+    set_error("device allocation failed");
+  }
+  if (!rc && hipStreamSynchronize(s) != hipSuccess) { rc = SFHE_E_DEVICE; set_error("stream synchronize failed"); }
+  if (rc) { delete m; return rc; }
+  *out = m;
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_matrix_info(const sfhe_mat* m, sfhe_mat_info* out) {
+  if (!m || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  out->rows = m->rows;
+  out->cols = m->cols;
+  out->level = m->level;
+  out->scale = m->scale;
+  out->enc = m->enc;
+  out->n_ciphertexts = m->n_ct;
+  out->nnz = m->nnz;
+  out->ell_width = m->ell_w;
+  out->device_bytes = (uint64_t)m->n_ct * 2 * (m->level + 1) * m->ctx->N * sizeof(u64);
+  return SFHE_OK;
+}
+
+void sfhe_mat_destroy(sfhe_mat* m) { delete m; }
+
+int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched, void* stream, sfhe_mat** C) {
+  GUARD_BEGIN
+  if (!C) { set_error("C is NULL"); return SFHE_E_INVALID_ARG; }
+  *C = nullptr;
+  if (!c || !A || !B) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (A->ctx != c || B->ctx != c) { set_error("matrices belong to another context"); return SFHE_E_INVALID_ARG; }
+  if (sched != SFHE_SCHED_PER_PRODUCT && sched != SFHE_SCHED_LAZY) { set_error("bad schedule"); return SFHE_E_INVALID_ARG; }
+  if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
+  if (B->enc != SFHE_ENC_DENSE) { set_error("the right operand must be DENSE"); return SFHE_E_UNSUPPORTED; }
+  if (A->cols != B->rows) { set_error("A.cols != B.rows"); return SFHE_E_SHAPE; }
+  if (A->level != B->level) { set_error("operand levels differ"); return SFHE_E_LEVEL; }
+  if (A->level != c->L - 1) { set_error("operands must be at the top level"); return SFHE_E_LEVEL; }
+  if (A->level < 1) { set_error("no prime left to rescale"); return SFHE_E_LEVEL; }
+  if (A->scale != B->scale) { set_error("operand scales differ"); return SFHE_E_SCALE; }
+  hipStream_t s = (hipStream_t)stream;
+  const int N = c->N, lev = A->level, nl = lev + 1, M = A->rows, Nc = B->cols;
+  SFHE_HIP(hipEventRecord(c->ev0, s));
+  sfhe_mat* out = new sfhe_mat();
+  out->ctx = c;
+  out->rows = M;
+  out->cols = Nc;
+  out->level = lev - 1;
+  out->scale = A->scale * B->scale / (double)c->primes[lev];
+  out->enc = SFHE_ENC_DENSE;
+  out->n_ct = (int64_t)M * Nc;
+  out->nnz = out->n_ct;
+  const int64_t ctw = (int64_t)2 * lev * N;   // words per output ciphertext
+  int rc = SFHE_OK;
+  if (!out->data.alloc(&c->alloc, (size_t)out->n_ct * ctw)) {
+    delete out;
+    set_error("device allocation failed for the result");
+    return SFHE_E_NOMEM;
+  }
+  std::vector<int64_t> visits(M);
+  for (int i = 0; i < M; ++i) visits[i] = row_visits(A, i);
+  int64_t products = 0, keyswitches = 0;
+  // outputs with no product are trivial zeros
+  std::vector<int64_t> empty;
+  for (int i = 0; i < M; ++i)
+    if (visits[i] == 0)
+      for (int j = 0; j < Nc; ++j) empty.push_back((int64_t)i * Nc + j);
+  if (sched == SFHE_SCHED_LAZY) {
+    const int64_t dw = (int64_t)3 * nl * N;
+    const int64_t tile_max = 512;
+    DevBuf<u64> D;
+    DevBuf<int> d_oi, d_oj;
+    std::vector<int> oi, oj;
+    int64_t o = 0;
+    const int64_t total = (int64_t)M * Nc;
+    if (!D.alloc(&c->alloc, (size_t)std::min<int64_t>(tile_max, std::max<int64_t>(total, 1)) * dw)) {
+      rc = SFHE_E_NOMEM;
+      set_error("device allocation failed");
+    }
+    while (!rc && o < total) {
+      // a tile of consecutive non-empty outputs
+      while (o < total && visits[o / Nc] == 0) ++o;
+      if (o >= total) break;
+      oi.clear();
+      oj.clear();
+      const int64_t o0 = o;
+      while (o < total && (int64_t)oi.size() < tile_max && visits[o / Nc] > 0) {
+        oi.push_back((int)(o / Nc));
+        oj.push_back((int)(o % Nc));
+        products += visits[o / Nc];
+        ++o;
+      }
+      const int64_t cnt = (int64_t)oi.size();
+      if (!upload(c, d_oi, oi, s) || !upload(c, d_oj, oj, s)) { rc = SFHE_E_NOMEM; set_error("device allocation failed"); break; }
+      rc = launch_tensor_lazy(c, A, B, d_oi.ptr, d_oj.ptr, cnt, D.ptr, s);
+      if (!rc) rc = keyswitch_batch(c, lev, D.ptr + (int64_t)2 * nl * N, dw, D.ptr, dw, true, cnt, s);
+      if (!rc) rc = rescale_batch(c, lev, D.ptr, dw, out->data.ptr + o0 * ctw, ctw, cnt, s);
+      keyswitches += cnt;
+    }
+  } else {
+    // Algorithm 1 order: every product is relinearised and rescaled, then summed
+    if (!rc) rc = launch_zero(out->data.ptr, out->n_ct * ctw, s);
+    const int64_t tile_max = 512;
+    std::vector<int> aidx, bidx, seg;
+    std::vector<int64_t> oidx;
+    std::vector<std::pair<int, int64_t>> pairs;
+    DevBuf<u64> D, T;
+    DevBuf<int> d_a, d_b, d_seg;
+    DevBuf<int64_t> d_o;
+    if (!D.alloc(&c->alloc, (size_t)tile_max * 3 * nl * N) || !T.alloc(&c->alloc, (size_t)tile_max * ctw)) {
+      rc = SFHE_E_NOMEM;
+      set_error("device allocation failed");
+    }
+    auto flush = [&]() -> int {
+      if (aidx.empty()) return SFHE_OK;
+      seg.push_back((int)aidx.size());
+      const int64_t cnt = (int64_t)aidx.size();
+      if (!upload(c, d_a, aidx, s) || !upload(c, d_b, bidx, s) || !upload(c, d_seg, seg, s) || !upload(c, d_o, oidx, s)) {
+        set_error("device allocation failed");
+        return SFHE_E_NOMEM;
+      }
+      int r = launch_tensor_gather(c, lev, A->data.ptr, B->data.ptr, d_a.ptr, d_b.ptr, D.ptr, cnt, s);
+      const int64_t dw = (int64_t)3 * nl * N;
+      if (!r) r = keyswitch_batch(c, lev, D.ptr + (int64_t)2 * nl * N, dw, D.ptr, dw, true, cnt, s);
+      if (!r) r = rescale_batch(c, lev, D.ptr, dw, T.ptr, ctw, cnt, s);
+      if (!r) r = launch_segment_sum(c, lev, T.ptr, out->data.ptr, d_seg.ptr, d_o.ptr, (int64_t)oidx.size(), s);
+      products += cnt;
+      keyswitches += cnt;
+      aidx.clear();
+      bidx.clear();
+      seg.clear();
+      oidx.clear();
+      return r;
+    };
+    for (int i = 0; i < M && !rc; ++i) {
+      if (visits[i] == 0) continue;
+      row_pairs(A, i, pairs);
+      for (int j = 0; j < Nc && !rc; ++j) {
+        bool opened = false;
+        for (auto& pr : pairs) {
+          if ((int64_t)aidx.size() >= tile_max) {
+            rc = flush();
+            if (rc) break;
+            opened = false;
+          }
+          if (!opened) {
+            seg.push_back((int)aidx.size());
+            oidx.push_back((int64_t)i * Nc + j);
+            opened = true;
+          }
+          aidx.push_back((int)pr.second);
+          bidx.push_back(pr.first * Nc + j);
+        }
+      }
+    }
+    if (!rc) rc = flush();
+  }
+  if (!rc && !empty.empty()) {
+    DevBuf<int64_t> d_e;
+    if (!upload(c, d_e, empty, s)) { rc = SFHE_E_NOMEM; set_error("device allocation failed"); }
+    if (!rc) rc = launch_zero_outputs(out->data.ptr, ctw, d_e.ptr, (int64_t)empty.size(), s);
+  }
+  if (!rc) {
+    hipError_t e = hipEventRecord(c->ev1, s);
+    if (e != hipSuccess) { rc = SFHE_E_DEVICE; set_error(hipGetErrorString(e)); }
+  }
+  if (rc) {
+    (void)hipStreamSynchronize(s);
+    delete out;
+    return rc;
+  }
+  c->stats.products = products;
+  c->stats.keyswitches = keyswitches;
+  c->stats.outputs = out->n_ct;
+  c->stats_pending = true;
+  *C = out;
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_last_stats(const sfhe_ctx* cc, sfhe_stats* out) {
+  if (!cc || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  sfhe_ctx* c = const_cast<sfhe_ctx*>(cc);
+  if (c->stats_pending) {
+    SFHE_HIP(hipEventSynchronize(c->ev1));
+    float ms = 0;
+    SFHE_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->stats.ms = ms;
+    c->stats_pending = false;
+  }
+  *out = c->stats;
+  return SFHE_OK;
+}
+
+int sfhe_decrypt_matrix(sfhe_ctx* c, const sfhe_mat* m, double* out, int64_t ld, void* stream) {
+  GUARD_BEGIN
+  if (!c || !m || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (m->ctx != c) { set_error("matrix belongs to another context"); return SFHE_E_INVALID_ARG; }
+  if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
+  if (ld < m->cols) { set_error("ld < cols"); return SFHE_E_SHAPE; }
+  hipStream_t s = (hipStream_t)stream;
+  const int N = c->N;
+  const int64_t ctw = (int64_t)2 * (m->level + 1) * N;
+  std::vector<double> vals(m->n_ct > 0 ? m->n_ct : 1, 0.0);
+  if (m->n_ct > 0) {
+    DevBuf<double> d_v;
+    DevBuf<int> d_flag;
+    if (!d_v.alloc(&c->alloc, m->n_ct) || !d_flag.alloc(&c->alloc, 1)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
+    SFHE_HIP(hipMemsetAsync(d_flag.ptr, 0, sizeof(int), s));
+    int rc = decrypt_values(c, m->data.ptr, m->n_ct, ctw, m->level, m->scale, d_v.ptr, d_flag.ptr, s);
+    if (rc) return rc;
+    int flag = 0;
+    SFHE_HIP(hipMemcpyAsync(vals.data(), d_v.ptr, m->n_ct * sizeof(double), hipMemcpyDeviceToHost, s));
+    SFHE_HIP(hipMemcpyAsync(&flag, d_flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    SFHE_HIP(hipStreamSynchronize(s));
+    if (flag) { set_error("a decrypted coefficient is outside the decodable range"); return SFHE_E_DECRYPT; }
+  }
+  for (int i = 0; i < m->rows; ++i)
+    for (int j = 0; j < m->cols; ++j) out[(int64_t)i * ld + j] = 0.0;
+  switch (m->enc) {
+    case SFHE_ENC_DENSE:
+    case SFHE_ENC_NAIVE_SPARSE:
+      for (int i = 0; i < m->rows; ++i)
+        for (int j = 0; j < m->cols; ++j) out[(int64_t)i * ld + j] = vals[(int64_t)i * m->cols + j];
+      break;
+    case SFHE_ENC_CSR:
+      for (int i = 0; i < m->rows; ++i)
+        for (int p = m->row_ptr[i]; p < m->row_ptr[i + 1]; ++p) out[(int64_t)i * ld + m->col_idx[p]] = vals[p];
+      break;
+    case SFHE_ENC_ELL:
+      for (int i = 0; i < m->rows; ++i)
+        for (int sl = 0; sl < m->ell_w; ++sl) {
+          const int k = m->ell_col[(size_t)i * m->ell_w + sl];
+          if (k >= 0) out[(int64_t)i * ld + k] = vals[(int64_t)i * m->ell_w + sl];
+        }
+      break;
+  }
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_export_ct(sfhe_ctx* c, const sfhe_mat* m, int32_t i, int32_t j, uint64_t* out, size_t cap, void* stream) {
+  GUARD_BEGIN
+  if (!c || !m || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (i < 0 || i >= m->rows || j < 0 || j >= m->cols) { set_error("index out of range"); return SFHE_E_SHAPE; }
+  const int N = c->N, nl = m->level + 1;
+  const size_t words = (size_t)2 * nl * N;
+  if (cap < words) { set_error("capacity below 2*(level+1)*N"); return SFHE_E_INVALID_ARG; }
+  const int64_t sl = slot_of(m, i, j);
+  if (sl < 0) { set_error("element not stored by this encoding"); return SFHE_E_SHAPE; }
+  hipStream_t s = (hipStream_t)stream;
+  DevBuf<u64> tmp;
+  if (!tmp.alloc(&c->alloc, words)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
+  SFHE_HIP(hipMemcpyAsync(tmp.ptr, m->data.ptr + sl * (int64_t)words, words * sizeof(u64), hipMemcpyDeviceToDevice, s));
+  int pos[2 * kMaxBasis], pr[2 * kMaxBasis];
+  for (int r = 0; r < 2 * nl; ++r) { pos[r] = r; pr[r] = r % nl; }
+  int rc = launch_ntt(c, tmp.ptr, 1, 0, 2 * nl, pos, pr, true, s);
+  if (rc) return rc;
+  SFHE_HIP(hipMemcpyAsync(out, tmp.ptr, words * sizeof(u64), hipMemcpyDeviceToHost, s));
+  SFHE_HIP(hipStreamSynchronize(s));
+  return SFHE_OK;
+  GUARD_END
+}
+
+// ---------------------------------------------------------------- primitives
+int sfhe_ntt(sfhe_ctx* c, uint64_t* data, int32_t batch, int32_t n_limbs, int32_t first_prime, int32_t inverse,
+             void* stream) {
+  GUARD_BEGIN
+  if (!c || !data) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (batch < 0 || n_limbs < 1 || first_prime < 0 || first_prime + n_limbs > c->nb) {
+    set_error("limb range outside the basis");
+    return SFHE_E_INVALID_ARG;
+  }
+  int pos[2 * kMaxBasis], pr[2 * kMaxBasis];
+  for (int r = 0; r < n_limbs; ++r) { pos[r] = r; pr[r] = first_prime + r; }
+  return launch_ntt(c, data, batch, (int64_t)n_limbs * c->N, n_limbs, pos, pr, inverse != 0, (hipStream_t)stream);
+  GUARD_END
+}
+
+int sfhe_tensor(sfhe_ctx* c, int32_t level, const uint64_t* a, const uint64_t* b, uint64_t* d, int32_t batch,
+                void* stream) {
+  GUARD_BEGIN
+  if (!c || !a || !b || !d) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (level < 0 || level >= c->L || batch < 0) { set_error("bad level or batch"); return SFHE_E_LEVEL; }
+  const int64_t nl = level + 1, N = c->N;
+  return launch_tensor_pointwise(c, level, a, 2 * nl * N, b, 2 * nl * N, d, 3 * nl * N, batch, (hipStream_t)stream);
+  GUARD_END
+}
+
+int sfhe_keyswitch(sfhe_ctx* c, int32_t level, const uint64_t* d2, uint64_t* out, int32_t batch, void* stream) {
+  GUARD_BEGIN
+  if (!c || !d2 || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
+  if (level < 0 || level >= c->L || batch < 0) { set_error("bad level or batch"); return SFHE_E_LEVEL; }
+  const int64_t nl = level + 1, N = c->N;
+  return keyswitch_batch(c, level, d2, nl * N, out, 2 * nl * N, false, batch, (hipStream_t)stream);
+  GUARD_END
+}
+
+int sfhe_rescale(sfhe_ctx* c, int32_t level, const uint64_t* in, uint64_t* out, int32_t batch, void* stream) {
+  GUARD_BEGIN
+  if (!c || !in || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (level < 1 || level >= c->L || batch < 0) { set_error("bad level or batch"); return SFHE_E_LEVEL; }
+  const int64_t nl = level + 1, N = c->N;
+  return rescale_batch(c, level, in, 2 * nl * N, out, 2 * level * N, batch, (hipStream_t)stream);
+  GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+// internal.hpp -- host-side runtime structures and kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/sfhe.h"
+#include "device.hpp"
+
+namespace sfhe {
+
+constexpr int kMaxDigit = 8;   // primes per key-switching digit (alpha)
+
+// ---- constants of the base conversions, one block per (level, digit) ----
+// ModUp of digit j at level lev: y_i = [x_i (D/q_i)^-1]_{q_i} for the digit's
+// primes, then target e of the extended basis (data 0..lev, then special)
+// gets sum_i y_i [D/q_i]_{e}.
+struct ModUpConst {
+  int lo, hi;                          // digit primes lo..hi-1 (clipped to the level)
+  int ne;                              // extended basis size = lev + 1 + alpha
+  int basis[kMaxBasis];                // basis index of extended position e
+  u64 inv[kMaxDigit], inv_s[kMaxDigit];
+  u64 conv[kMaxDigit][kMaxBasis], conv_s[kMaxDigit][kMaxBasis];
+};
+// ModDown at level lev: y_k = [acc_{p_k} (P/p_k)^-1]_{p_k};
+// out_i = (acc_i - sum_k y_k [P/p_k]_{q_i}) [P^-1]_{q_i}.
+struct ModDownConst {
+  u64 pinv[kMaxDigit], pinv_s[kMaxDigit];            // (P/p_k)^-1 mod p_k
+  u64 conv[kMaxDigit][kMaxBasis], conv_s[kMaxDigit][kMaxBasis];   // [P/p_k]_{q_i}
+  u64 Pinv[kMaxBasis], Pinv_s[kMaxBasis];            // P^-1 mod q_i
+};
+// Rescale at level lev: q_lev^-1 mod q_i for i < lev.
+struct RescaleConst {
+  u64 qinv[kMaxBasis], qinv_s[kMaxBasis];
+};
+
+// ---- device allocation through the optional hooks ----
+struct Alloc {
+  sfhe_device_hooks hooks{};
+  bool has_hooks = false;
+  void* get(size_t bytes);
+  void put(void* p, size_t bytes);
+};
+
+template <typename T>
+struct DevBuf {
+  Alloc* al = nullptr;
+  T* ptr = nullptr;
+  size_t count = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); al = o.al; ptr = o.ptr; count = o.count; o.ptr = nullptr; o.count = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  bool alloc(Alloc* a, size_t n) {
+    release();
+    al = a;
+    count = n;
+    ptr = n ? (T*)a->get(n * sizeof(T)) : nullptr;
+    return n == 0 || ptr != nullptr;
+  }
+  void release() {
+    if (ptr && al) al->put(ptr, count * sizeof(T));
+    ptr = nullptr;
+    count = 0;
+  }
+};
+
+}  // namespace sfhe
+
+struct sfhe_ctx {
+  // parameters
+  int logN = 0, N = 0, L = 0, alpha = 0, dnum = 0, nb = 0;
+  double log2_scale = 0, sigma = 0;
+  std::vector<sfhe::u64> primes;         // data then special
+  sfhe::DevParams dp{};                  // per-prime constants + table pointers
+  sfhe::Alloc alloc;
+  int device = 0;
+  // device tables
+  sfhe::DevBuf<sfhe::u64> d_tables;      // [nb][4][N]: tw, tws, itw, itws
+  sfhe::DevBuf<double> d_cos;            // cos(pi t / N)
+  sfhe::DevBuf<sfhe::ModUpConst> d_modup;      // [L][dnum]
+  sfhe::DevBuf<sfhe::ModDownConst> d_moddown;  // [L]
+  sfhe::DevBuf<sfhe::RescaleConst> d_rescale;  // [L]
+  sfhe::u64 cdt[sfhe::kCdtLen];
+  // keys
+  bool has_keys = false;
+  sfhe::DevBuf<sfhe::u64> d_s;           // secret, NTT domain [nb][N]
+  sfhe::DevBuf<sfhe::u64> d_rlk;         // relinearisation key, NTT domain [dnum][2][nb][N]
+  // last matmul
+  sfhe_stats stats{};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool stats_pending = false;
+};
+
+struct sfhe_mat {
+  sfhe_ctx* ctx = nullptr;
+  int rows = 0, cols = 0, level = 0;
+  double scale = 0;
+  sfhe_encoding enc = SFHE_ENC_DENSE;
+  int64_t n_ct = 0, nnz = 0;
+  sfhe::DevBuf<sfhe::u64> data;          // [n_ct][2][level+1][N], NTT domain
+  // plaintext structure (Sec. 3.3.2), host and device copies
+  std::vector<int> row_ptr, col_idx;     // CSR
+  int ell_w = 0;
+  std::vector<int> ell_col;              // ELL [rows][ell_w], -1 = padding
+  std::vector<uint32_t> zero_mask;       // naive sparse: bit (i*cols + k) set iff A_ik == 0
+  sfhe::DevBuf<int> d_row_ptr, d_col_idx, d_ell_col;
+  sfhe::DevBuf<uint32_t> d_mask;
+};
+
+namespace sfhe {
+
+// ---- errors ----
+void set_error(const std::string& msg);
+#define SFHE_HIP(call)                                                               \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      ::sfhe::set_error(std::string(#call) + ": " + hipGetErrorString(e_));          \
+      return SFHE_E_DEVICE;                                                          \
+    }                                                                                \
+  } while (0)
+
+// ---- launchers (each returns SFHE_OK or an error code) ----
+// NTT of `batch` groups of `nrow` rows: row r of group b starts at
+// base + b*bstride + pos[r]*N and is reduced mod basis prime prime[r].
+int launch_ntt(const sfhe_ctx* c, u64* base, int64_t batch, int64_t bstride, int nrow, const int* pos,
+               const int* prime, bool inverse, hipStream_t s);
+
+// fill n words with zero
+int launch_zero(u64* p, int64_t n, hipStream_t s);
+
+// encryption of `count` elements (coordinates ei, ej, values z) into
+// ct[elem_slot[x]][2][L][N]; NTT domain on return.
+int encrypt_elements(sfhe_ctx* c, u64* ct, int64_t count, const int* d_ei, const int* d_ej,
+                     const double* d_z, const int64_t* d_slot, u64 seed, u64 operand, hipStream_t s);
+// NTT of every slot, then c0 <- c0 - c1 s
+int encrypt_finish(sfhe_ctx* c, u64* ct, int64_t nct, hipStream_t s);
+int keygen_device(sfhe_ctx* c, u64 seed, hipStream_t s);
+// decrypt + decode: values[x] for ciphertexts ct[x] (stride ctstride words) at level lev
+int decrypt_values(sfhe_ctx* c, const u64* ct, int64_t count, int64_t ctstride, int lev, double scale,
+                   double* d_out, int* d_flag, hipStream_t s);
+
+// tensor products
+int launch_tensor_pointwise(const sfhe_ctx* c, int lev, const u64* a, int64_t astride, const u64* b,
+                            int64_t bstride, u64* d, int64_t dstride, int64_t batch, hipStream_t s);
+// gathered product list: product p multiplies A ciphertext a_idx[p] by B ciphertext b_idx[p]
+int launch_tensor_gather(const sfhe_ctx* c, int lev, const u64* A, const u64* B, const int* d_aidx,
+                         const int* d_bidx, u64* d, int64_t count, hipStream_t s);
+// lazy sum over the visited k of output list (oi, oj)
+int launch_tensor_lazy(const sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, const int* d_oi,
+                       const int* d_oj, int64_t count, u64* d, hipStream_t s);
+
+// key switch of d2 rows (batch stride d2stride), result added into out
+// (batch stride ostride, [2][nl][N]) if add_in, else written.
+int keyswitch_batch(sfhe_ctx* c, int lev, const u64* d2, int64_t d2stride, u64* out, int64_t ostride,
+                    bool add_in, int64_t batch, hipStream_t s);
+int rescale_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, u64* out, int64_t ostride,
+                  int64_t batch, hipStream_t s);
+// out[o] += sum of t[p] for p in seg[o] .. seg[o+1]-1 (rows [2][nl][N])
+int launch_segment_sum(const sfhe_ctx* c, int nl, const u64* t, u64* out, const int* d_seg,
+                       const int64_t* d_oidx, int64_t nout, hipStream_t s);
+int launch_zero_outputs(u64* out, int64_t ctwords, const int64_t* d_oidx, int64_t n, hipStream_t s);
+
+}  // namespace sfhe

@@ -1,0 +1,273 @@
+"""Python binding of the gfx950 library (ctypes over the C ABI in include/sfhe.h).
+
+Argument marshalling only: every step of the encrypted product runs in the
+library's HIP kernels.  PyTorch supplies device memory (its caching
+allocator, through the library's allocation hooks) and the current stream.
+Loading fails loudly when the built library is missing -- there is no
+fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfhe.so")
+
+ENC = {"dense": 0, "naive": 1, "csr": 2, "ell": 3}
+SCHED = {"per_product": 0, "lazy": 1}
+
+ERRORS = {
+    -1: "SFHE_E_INVALID_ARG", -2: "SFHE_E_PARAMS", -3: "SFHE_E_SHAPE", -4: "SFHE_E_LEVEL",
+    -5: "SFHE_E_SCALE", -6: "SFHE_E_UNSUPPORTED", -7: "SFHE_E_NOMEM", -8: "SFHE_E_DEVICE",
+    -9: "SFHE_E_STATE", -10: "SFHE_E_DECRYPT",
+}
+
+EXPORTED = [
+    "sfhe_ctx_create", "sfhe_ctx_destroy", "sfhe_ctx_n", "sfhe_ctx_primes", "sfhe_keygen",
+    "sfhe_encrypt_matrix", "sfhe_matmul", "sfhe_decrypt_matrix", "sfhe_export_ct",
+    "sfhe_matrix_info", "sfhe_last_stats", "sfhe_mat_destroy", "sfhe_last_error",
+    "sfhe_ntt", "sfhe_tensor", "sfhe_keyswitch", "sfhe_rescale",
+]
+
+
+class SfheError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("n_p", ctypes.c_uint32),
+                ("dnum", ctypes.c_uint32), ("q_bits", ctypes.POINTER(ctypes.c_uint32)),
+                ("p_bits", ctypes.POINTER(ctypes.c_uint32)), ("log2_scale", ctypes.c_double),
+                ("sigma", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class Hooks(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class MatInfo(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("cols", ctypes.c_int32), ("level", ctypes.c_int32),
+                ("scale", ctypes.c_double), ("enc", ctypes.c_int), ("n_ciphertexts", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("ell_width", ctypes.c_int32), ("device_bytes", ctypes.c_uint64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("products", ctypes.c_int64), ("keyswitches", ctypes.c_int64),
+                ("outputs", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsfhe.so is not built (run __graft_entry__.build()); no fallback exists")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        L.sfhe_ctx_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Hooks), ctypes.POINTER(vp)]
+        L.sfhe_ctx_destroy.argtypes = [vp]
+        L.sfhe_ctx_destroy.restype = None
+        L.sfhe_ctx_n.argtypes = [vp, ctypes.POINTER(i32)]
+        L.sfhe_ctx_primes.argtypes = [vp, ctypes.POINTER(u64), ctypes.c_size_t]
+        L.sfhe_keygen.argtypes = [vp, u64]
+        L.sfhe_encrypt_matrix.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, i32, i64, ctypes.c_int, u64,
+                                          ctypes.c_uint32, vp, ctypes.POINTER(vp)]
+        L.sfhe_matmul.argtypes = [vp, vp, vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.sfhe_decrypt_matrix.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), i64, vp]
+        L.sfhe_export_ct.argtypes = [vp, vp, i32, i32, ctypes.POINTER(u64), ctypes.c_size_t, vp]
+        L.sfhe_matrix_info.argtypes = [vp, ctypes.POINTER(MatInfo)]
+        L.sfhe_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.sfhe_mat_destroy.argtypes = [vp]
+        L.sfhe_mat_destroy.restype = None
+        L.sfhe_last_error.restype = ctypes.c_char_p
+        L.sfhe_ntt.argtypes = [vp, vp, i32, i32, i32, i32, vp]
+        L.sfhe_tensor.argtypes = [vp, i32, vp, vp, vp, i32, vp]
+        L.sfhe_keyswitch.argtypes = [vp, i32, vp, vp, i32, vp]
+        L.sfhe_rescale.argtypes = [vp, i32, vp, vp, i32, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise SfheError(rc, lib().sfhe_last_error().decode())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Matrix:
+    """An encrypted matrix (library handle)."""
+
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        out = MatInfo()
+        _check(lib().sfhe_matrix_info(self._h, ctypes.byref(out)))
+        return out
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().sfhe_mat_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """Parameters, tables and keys on the current device."""
+
+    def __init__(self, log_n, q_bits, p_bits, dnum, log2_scale=40.0, sigma=3.2, torch_allocator=True):
+        import torch
+        self._torch = torch
+        self.device = torch.cuda.current_device()
+        qb = (ctypes.c_uint32 * len(q_bits))(*q_bits)
+        pb = (ctypes.c_uint32 * len(p_bits))(*p_bits)
+        self._params = Params(int(log_n), len(q_bits), len(p_bits), int(dnum), qb, pb, float(log2_scale), float(sigma))
+        self._keep = [qb, pb]
+        hooks_p = None
+        if torch_allocator:
+            def _alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, torch.cuda.current_stream())
+                except Exception:
+                    return None
+
+            def _free(ptr, nbytes, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc_cb = ALLOC_FN(_alloc)
+            self._free_cb = FREE_FN(_free)
+            self._hooks = Hooks(self._alloc_cb, self._free_cb, None)
+            hooks_p = ctypes.byref(self._hooks)
+        h = ctypes.c_void_p()
+        _check(lib().sfhe_ctx_create(ctypes.byref(self._params), hooks_p, ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int32()
+        _check(lib().sfhe_ctx_n(self._h, ctypes.byref(n)))
+        self.n = n.value
+        self.L = len(q_bits)
+        self.alpha = len(p_bits)
+        buf = (ctypes.c_uint64 * (self.L + self.alpha))()
+        _check(lib().sfhe_ctx_primes(self._h, buf, self.L + self.alpha))
+        self.primes = [int(x) for x in buf]
+        self.log2_scale = float(log2_scale)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sfhe_ctx_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- keys, matrices --------------------------------------------------
+    def keygen(self, seed):
+        _check(lib().sfhe_keygen(self._h, ctypes.c_uint64(seed)))
+
+    def encrypt(self, vals, enc, seed, operand, stream=None):
+        v = np.ascontiguousarray(vals, dtype=np.float64)
+        rows, cols = v.shape
+        h = ctypes.c_void_p()
+        _check(lib().sfhe_encrypt_matrix(self._h, v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), rows, cols,
+                                         cols, ENC[enc], ctypes.c_uint64(seed), int(operand),
+                                         _stream_handle(stream), ctypes.byref(h)))
+        return Matrix(self, h)
+
+    def matmul(self, A, B, sched, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().sfhe_matmul(self._h, A.handle, B.handle, SCHED[sched], _stream_handle(stream),
+                                 ctypes.byref(h)))
+        return Matrix(self, h)
+
+    def last_stats(self):
+        s = Stats()
+        _check(lib().sfhe_last_stats(self._h, ctypes.byref(s)))
+        return s
+
+    def decrypt(self, M, stream=None):
+        info = M.info()
+        out = np.zeros((info.rows, info.cols), dtype=np.float64)
+        _check(lib().sfhe_decrypt_matrix(self._h, M.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         info.cols, _stream_handle(stream)))
+        return out
+
+    def export_ct(self, M, i, j, stream=None):
+        info = M.info()
+        nl = info.level + 1
+        out = np.zeros((2, nl, self.n), dtype=np.uint64)
+        _check(lib().sfhe_export_ct(self._h, M.handle, int(i), int(j),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), out.size,
+                                    _stream_handle(stream)))
+        return out
+
+    # ---- primitives on device buffers --------------------------------------
+    def to_device(self, arr):
+        a = np.ascontiguousarray(arr, dtype=np.uint64)
+        return self._torch.from_numpy(a.view(np.int64)).to("cuda")
+
+    @staticmethod
+    def to_host(t):
+        return t.cpu().numpy().view(np.uint64)
+
+    def ntt(self, t, n_limbs, first_prime=0, inverse=False, stream=None):
+        """In place on a device tensor of shape [batch, n_limbs, N] (int64 view of uint64)."""
+        assert t.is_cuda and t.is_contiguous() and t.numel() % (n_limbs * self.n) == 0
+        batch = t.numel() // (n_limbs * self.n)
+        _check(lib().sfhe_ntt(self._h, ctypes.c_void_p(t.data_ptr()), batch, n_limbs, first_prime,
+                              1 if inverse else 0, _stream_handle(stream)))
+        return t
+
+    def tensor(self, level, a, b, stream=None):
+        nl = level + 1
+        assert a.is_contiguous() and b.is_contiguous() and a.numel() == b.numel()
+        batch = a.numel() // (2 * nl * self.n)
+        d = self._torch.empty(batch * 3 * nl * self.n, dtype=self._torch.int64, device="cuda")
+        _check(lib().sfhe_tensor(self._h, level, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                 ctypes.c_void_p(d.data_ptr()), batch, _stream_handle(stream)))
+        return d.view(batch, 3, nl, self.n)
+
+    def keyswitch(self, level, d2, stream=None):
+        nl = level + 1
+        assert d2.is_contiguous()
+        batch = d2.numel() // (nl * self.n)
+        out = self._torch.empty(batch * 2 * nl * self.n, dtype=self._torch.int64, device="cuda")
+        _check(lib().sfhe_keyswitch(self._h, level, ctypes.c_void_p(d2.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    batch, _stream_handle(stream)))
+        return out.view(batch, 2, nl, self.n)
+
+    def rescale(self, level, ct, stream=None):
+        nl = level + 1
+        assert ct.is_contiguous()
+        batch = ct.numel() // (2 * nl * self.n)
+        out = self._torch.empty(batch * 2 * level * self.n, dtype=self._torch.int64, device="cuda")
+        _check(lib().sfhe_rescale(self._h, level, ctypes.c_void_p(ct.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  batch, _stream_handle(stream)))
+        return out.view(batch, 2, level, self.n)

@@ -1,0 +1,285 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Ciphertext residues are compared bit for bit in the coefficient domain
+(integer work: exact); decrypted values against the fp64 product within the
+bound the noise analysis gives.  Every call goes through the C ABI.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2503_09184_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HYB_SMALL = dict(log_n=10, q_bits=[60, 40, 40, 40, 40], p_bits=[60, 60, 60], dnum=2)
+SINGLE_SMALL = dict(log_n=11, q_bits=[60, 40, 40], p_bits=[60], dnum=3)
+
+
+def note(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+_ctx_cache = {}
+_orc_cache = {}
+
+
+def pair(params, seed):
+    """(library context, oracle) with keys from the same seed."""
+    from paper_2503_09184_amd import sfhe
+    key = (tuple(sorted((k, tuple(v) if isinstance(v, list) else v) for k, v in params.items())), seed)
+    if key not in _ctx_cache:
+        note("ctx %s seed %d" % (params, seed))
+        ctx = sfhe.Context(**params)
+        ctx.keygen(seed)
+        orc = Oracle(**params)
+        orc.keygen(seed)
+        _ctx_cache[key] = ctx
+        _orc_cache[key] = orc
+    return _ctx_cache[key], _orc_cache[key]
+
+
+# ---------------------------------------------------------------- primitives
+@pytest.mark.parametrize("name", list(W.PARAMS))
+def test_primes_match_oracle(torch_cuda, name):
+    ctx, orc = pair(W.PARAMS[name], 1)
+    assert ctx.primes == [int(x) for x in orc.primes]
+
+
+@pytest.mark.parametrize("name", list(W.PARAMS))
+def test_ntt_matches_oracle(torch_cuda, name):
+    ctx, orc = pair(W.PARAMS[name], 1)
+    rng = np.random.default_rng(11)
+    nb = len(ctx.primes)
+    x = np.stack([rng.integers(0, q, size=ctx.n, dtype=np.uint64) for q in ctx.primes])[None]
+    note("ntt forward %s" % name)
+    t = ctx.to_device(x)
+    ctx.ntt(t, nb, 0, inverse=False)
+    got = ctx.to_host(t).reshape(nb, ctx.n)
+    for r in range(nb):
+        assert np.array_equal(got[r], orc.ntt(r, x[0, r])), r
+    note("ntt inverse %s" % name)
+    ctx.ntt(t, nb, 0, inverse=True)
+    assert np.array_equal(ctx.to_host(t).reshape(nb, ctx.n), x[0])
+
+
+def _rand_ct(rng, qs, n, polys=2):
+    return np.stack([np.stack([rng.integers(0, q, size=n, dtype=np.uint64) for q in qs]) for _ in range(polys)])
+
+
+def _to_ntt(ctx, arr, nl):
+    """coefficient [batch][polys][nl][N] -> device NTT domain"""
+    t = ctx.to_device(arr)
+    ctx.ntt(t, nl, 0, inverse=False)
+    return t
+
+
+def _from_ntt(ctx, t, nl):
+    t = t.contiguous()
+    ctx.ntt(t, nl, 0, inverse=True)
+    return ctx.to_host(t)
+
+
+@pytest.mark.parametrize("params", [HYB_SMALL, SINGLE_SMALL, W.PARAMS["realistic_n16384"]])
+def test_tensor_keyswitch_rescale_match_oracle(torch_cuda, params):
+    ctx, orc = pair(params, 5)
+    rng = np.random.default_rng(12)
+    n, L = ctx.n, ctx.L
+    lev = L - 1
+    qs = ctx.primes[:L]
+    a = _rand_ct(rng, qs, n)
+    b = _rand_ct(rng, qs, n)
+    note("tensor %s" % params)
+    d = ctx.tensor(lev, _to_ntt(ctx, a[None], L), _to_ntt(ctx, b[None], L))
+    d_host = _from_ntt(ctx, d, L).reshape(3, L, n)
+    assert np.array_equal(d_host, orc.tensor(lev, a, b))
+    note("keyswitch %s" % params)
+    d2 = np.stack([rng.integers(0, q, size=n, dtype=np.uint64) for q in qs])
+    ks = ctx.keyswitch(lev, _to_ntt(ctx, d2[None], L))
+    assert np.array_equal(_from_ntt(ctx, ks, L).reshape(2, L, n), orc.keyswitch(lev, d2))
+    note("rescale %s" % params)
+    for lv in range(1, L):
+        ct = _rand_ct(rng, qs[:lv + 1], n)
+        out = ctx.rescale(lv, _to_ntt(ctx, ct[None], lv + 1))
+        assert np.array_equal(_from_ntt(ctx, out, lv).reshape(2, lv, n), orc.rescale(lv, ct))
+
+
+def test_keyswitch_lower_levels_match_oracle(torch_cuda):
+    ctx, orc = pair(HYB_SMALL, 6)
+    rng = np.random.default_rng(13)
+    for lev in (0, 1, 2, 3):
+        qs = ctx.primes[:lev + 1]
+        d2 = np.stack([rng.integers(0, q, size=ctx.n, dtype=np.uint64) for q in qs])
+        note("keyswitch level %d" % lev)
+        ks = ctx.keyswitch(lev, _to_ntt(ctx, d2[None], lev + 1))
+        assert np.array_equal(_from_ntt(ctx, ks, lev + 1).reshape(2, lev + 1, ctx.n), orc.keyswitch(lev, d2))
+
+
+def test_batched_primitives_match_single(torch_cuda):
+    """A batch of 5 gives the same rows as 5 single calls."""
+    ctx, orc = pair(HYB_SMALL, 6)
+    rng = np.random.default_rng(14)
+    L, n = ctx.L, ctx.n
+    qs = ctx.primes[:L]
+    d2 = np.stack([np.stack([rng.integers(0, q, size=n, dtype=np.uint64) for q in qs]) for _ in range(5)])
+    note("keyswitch batch 5")
+    ks = _from_ntt(ctx, ctx.keyswitch(L - 1, _to_ntt(ctx, d2, L)), L).reshape(5, 2, L, n)
+    for x in range(5):
+        assert np.array_equal(ks[x], orc.keyswitch(L - 1, d2[x]))
+
+
+# ---------------------------------------------------------------- encryption
+@pytest.mark.parametrize("enc", ["dense", "csr", "ell", "naive"])
+def test_encryption_matches_oracle(torch_cuda, enc):
+    ctx, orc = pair(HYB_SMALL, 7)
+    A = W.sparse_matrix(5, 6, 0.4, 3)
+    note("encrypt %s" % enc)
+    M = ctx.encrypt(A, enc, seed=99, operand=0)
+    for i in range(5):
+        for j in range(6):
+            if enc in ("csr", "ell") and A[i, j] == 0.0:
+                continue
+            got = ctx.export_ct(M, i, j)
+            want = orc.encrypt(A[i, j], 99, 0, i, j)
+            assert np.array_equal(got, want), (i, j)
+    info = M.info()
+    assert info.nnz == np.count_nonzero(A)
+
+
+def test_decrypt_roundtrip(torch_cuda):
+    ctx, orc = pair(SINGLE_SMALL, 7)
+    A = W.sparse_matrix(7, 9, 0.3, 4)
+    note("decrypt roundtrip")
+    M = ctx.encrypt(A, "ell", seed=5, operand=0)
+    back = ctx.decrypt(M)
+    assert np.max(np.abs(back - A)) < 1e-9
+    assert np.all(back[A == 0.0] == 0.0)
+
+
+# ---------------------------------------------------------------- matmul, all outputs
+def _all_outputs_equal(ctx, C, cts, M, Nc, tag):
+    for i in range(M):
+        for j in range(Nc):
+            got = ctx.export_ct(C, i, j)
+            assert np.array_equal(got, cts[i * Nc + j]), (tag, i, j)
+
+
+@pytest.mark.parametrize("sched", ["lazy", "per_product"])
+@pytest.mark.parametrize("enc", ["csr", "dense", "naive", "ell"])
+def test_matmul_toy_all_outputs(torch_cuda, enc, sched):
+    """8x8x8 at N = 2^10, Bernoulli(0.5) zeros in A: every output bit-exact."""
+    P = W.PARAMS["toy_n1024"]
+    ctx, orc = pair(P, W.key_seed(1))
+    A, B = W.operands(8, 8, 8, 0.5, W.workload_seed(1))
+    sa, sb = W.enc_seed(1, 0), W.enc_seed(1, 1)
+    note("toy matmul %s %s" % (enc, sched))
+    EA = ctx.encrypt(A, enc, sa, 0)
+    EB = ctx.encrypt(B, "dense", sb, 1)
+    C = ctx.matmul(EA, EB, sched)
+    cts, vals, _ = orc.matmul(A, B, enc, sched, sa, sb, threads=4)
+    _all_outputs_equal(ctx, C, cts, 8, 8, enc + sched)
+    dec = ctx.decrypt(C)
+    assert np.max(np.abs(dec.ravel() - vals)) < 1e-9
+    assert np.max(np.abs(dec - A @ B)) < 1e-3
+
+
+@pytest.mark.parametrize("sched", ["lazy", "per_product"])
+@pytest.mark.parametrize("enc", ["csr", "ell", "naive", "dense"])
+def test_matmul_ragged_hybrid_all_outputs(torch_cuda, enc, sched):
+    """9x13x7 with an empty row and a full row, hybrid key switching (dnum = 2)."""
+    ctx, orc = pair(HYB_SMALL, 21)
+    A, B = W.operands(9, 13, 7, 0.6, 31)
+    A[3, :] = 0.0
+    A[5, :] = W.uniform_matrix(1, 13, 2)[0]
+    note("ragged matmul %s %s" % (enc, sched))
+    EA = ctx.encrypt(A, enc, 1234, 0)
+    EB = ctx.encrypt(B, "dense", 4321, 1)
+    C = ctx.matmul(EA, EB, sched)
+    cts, _, _ = orc.matmul(A, B, enc, sched, 1234, 4321, threads=4)
+    _all_outputs_equal(ctx, C, cts, 9, 7, enc + sched)
+    dec = ctx.decrypt(C)
+    assert np.all(dec[3] == 0.0)
+    assert np.max(np.abs(dec - A @ B)) < 1e-6
+
+
+def test_all_zero_left_operand(torch_cuda):
+    ctx, orc = pair(HYB_SMALL, 21)
+    A = np.zeros((3, 4))
+    B = W.uniform_matrix(4, 2, 9)
+    for enc in ("csr", "ell", "naive"):
+        note("zero A %s" % enc)
+        C = ctx.matmul(ctx.encrypt(A, enc, 1, 0), ctx.encrypt(B, "dense", 2, 1), "lazy")
+        assert np.all(ctx.decrypt(C) == 0.0)
+        assert not ctx.export_ct(C, 2, 1).any()
+
+
+def test_one_by_one(torch_cuda):
+    ctx, orc = pair(SINGLE_SMALL, 3)
+    A = np.array([[0.75]])
+    B = np.array([[-0.5]])
+    for sched in ("lazy", "per_product"):
+        note("1x1x1 %s" % sched)
+        C = ctx.matmul(ctx.encrypt(A, "csr", 1, 0), ctx.encrypt(B, "dense", 2, 1), sched)
+        cts, _, _ = orc.matmul(A, B, "csr", sched, 1, 2)
+        assert np.array_equal(ctx.export_ct(C, 0, 0), cts[0])
+
+
+def test_errors_are_reported(torch_cuda):
+    from paper_2503_09184_amd import sfhe
+    ctx, _ = pair(SINGLE_SMALL, 3)
+    A = ctx.encrypt(np.ones((2, 3)), "csr", 1, 0)
+    B = ctx.encrypt(np.ones((2, 2)), "dense", 1, 1)
+    with pytest.raises(sfhe.SfheError) as e:
+        ctx.matmul(A, B, "lazy")
+    assert e.value.code == -3
+    Bs = ctx.encrypt(np.ones((3, 2)), "csr", 1, 1)
+    with pytest.raises(sfhe.SfheError) as e:
+        ctx.matmul(A, Bs, "lazy")
+    assert e.value.code == -6
+    with pytest.raises(sfhe.SfheError) as e:
+        ctx.encrypt(np.full((1, 1), np.inf), "csr", 1, 0)
+    assert e.value.code == -1
+    with pytest.raises(sfhe.SfheError) as e:
+        sfhe.Context(log_n=15, q_bits=[60, 40], p_bits=[60], dnum=2)
+    assert e.value.code == -2
+
+
+# ---------------------------------------------------------------- sweep size (N = 2^13, 64 x 64)
+@pytest.mark.parametrize("sparsity", [0.0, 0.5, 0.9])
+def test_sweep_n8192_sampled_outputs_and_cross_encoding(torch_cuda, sparsity):
+    P = W.PARAMS["sweep_n8192"]
+    ctx, orc = pair(P, W.key_seed(2))
+    A, B = W.operands(64, 64, 64, sparsity, W.workload_seed(2))
+    sa, sb = W.enc_seed(2, 0), W.enc_seed(2, 1)
+    EB = ctx.encrypt(B, "dense", sb, 1)
+    outs = {}
+    rng = np.random.default_rng(int(sparsity * 100))
+    sample = sorted({(int(rng.integers(64)), int(rng.integers(64))) for _ in range(6)})
+    for enc in ("csr", "ell", "naive", "dense"):
+        note("sweep %.2f %s lazy" % (sparsity, enc))
+        EA = ctx.encrypt(A, enc, sa, 0)
+        C = ctx.matmul(EA, EB, "lazy")
+        outs[enc] = [ctx.export_ct(C, i, j) for (i, j) in sample]
+        dec = ctx.decrypt(C)
+        assert np.max(np.abs(dec - A @ B)) < 1e-6, enc
+    for enc in ("ell", "naive"):
+        for x, y in zip(outs["csr"], outs[enc]):
+            assert np.array_equal(x, y)
+    if sparsity == 0.0:
+        for x, y in zip(outs["csr"], outs["dense"]):
+            assert np.array_equal(x, y)
+    cts, _, _ = orc.matmul(A, B, "csr", "lazy", sa, sb, outputs=sample, threads=8)
+    for n, o in enumerate(outs["csr"]):
+        assert np.array_equal(o, cts[n]), sample[n]
