@@ -1,0 +1,236 @@
+"""Benchmark: encrypted 128x128x128 matrix product with unstructured sparsity.
+
+One step = one encrypted C = A*B (N = 2^14; five data primes of 60/40/40/40/40
+bits and three 60-bit special primes; hybrid key switching with dnum = 2;
+scale 2^40) with A 128x128 at 50% unstructured sparsity in CSR and B 128x128
+dense: every nonzero ciphertext product (tensor), one key switch and one
+rescale per output (the lazy, batched form).  Inputs are encrypted and
+resident in HBM before the timed region; setup, key generation, encryption and
+decryption are excluded, as in the paper's profiling procedure (Sec. 4.1).
+
+Prints one JSON line.  `value` is ct-mults/s: executed ciphertext products
+per second of the headline step.  Beside it: the same at 90% sparsity, the
+naive dense schedule on the same operands, the per-product (Algorithm 1 order)
+form, the other two sparse encodings, the dominant kernel's roofline, and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+# 64-bit modular multiply-add peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# 32-bit lane-ops/s, each 64x64 product needing 4 32x32->64 multiplies at
+# quarter rate (16 issue cycles) plus >= 4 full-rate adds for the 128-bit
+# accumulation: 20 lane-cycles per multiply-add.
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+MULADD_CYCLES = 20.0
+MULADD_PEAK = VALU_LANE_OPS / MULADD_CYCLES   # 64-bit modular multiply-adds / s
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def timed(ctx, torch, A, B, sched, steps, warmup, keep_last=False):
+    """Run warmup + steps matmuls; return (ms per step list, stats of the last, last C or None)."""
+    stream = torch.cuda.current_stream()
+    C = None
+    for _ in range(warmup):
+        C = ctx.matmul(A, B, sched)
+        C.close()
+    torch.cuda.synchronize()
+    times = []
+    stats = None
+    for s in range(steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        C = ctx.matmul(A, B, sched)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+        stats = ctx.last_stats()
+        if not (keep_last and s == steps - 1):
+            C.close()
+            C = None
+    return times, stats, C
+
+
+def cpu_baseline(P, A, Bm, seed, threads, target_s=15.0):
+    """The oracle on a bounded sample of outputs of the same workload (lazy, CSR).
+
+    The oracle assigns output (i, j) to thread (i*cols + j) mod T, so a sample
+    of every row times a multiple of T columns keeps the threads balanced."""
+    from oracle.oracle import Oracle
+    from paper_2503_09184_amd import workloads as W
+    orc = Oracle(**P)
+    orc.keygen(W.key_seed(seed))
+    sa, sb = W.enc_seed(seed, 0), W.enc_seed(seed, 1)
+    M, Nc = A.shape[0], Bm.shape[1]
+    probe = [(0, j) for j in range(threads)]
+    _, _, t_probe = orc.matmul(A, Bm, "csr", "lazy", sa, sb, outputs=probe, threads=threads, decrypt=False)
+    per_output_thread = max(t_probe, 1e-4)            # one output per thread
+    want_outputs = target_s / per_output_thread * threads
+    cols = int(min(Nc, max(threads, round(want_outputs / M / threads) * threads)))
+    outs = [(i, j) for i in range(M) for j in range(cols)]
+    _, _, secs = orc.matmul(A, Bm, "csr", "lazy", sa, sb, outputs=outs, threads=threads, decrypt=False)
+    products = sum(int(np.count_nonzero(A[i])) for (i, _) in outs)
+    return {"value": products / secs, "unit": "ct-mults/s", "cores": threads, "kind": "oracle",
+            "sample": "%d outputs (all %d rows x columns 0-%d) of the 50%%-sparse CSR lazy product: %d ct "
+                      "products, %.1f s on %d threads" % (len(outs), M, cols - 1, products, secs, threads),
+            "seconds": secs, "products": products}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sparsity", type=float, default=0.5)
+    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--only", default="", help="comma list of extra legs to run (default all): "
+                    "s90,dense,ell,naive,per_product,cpu")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pp-size", type=int, default=128, help="row count of A for the per-product leg")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the product shards by output rows; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2503_09184_amd import sfhe
+    from paper_2503_09184_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg_id = 3
+    P = W.PARAMS["realistic_n16384"]
+    n = args.size
+    log("setup: context N=2^14, keys")
+    ctx = sfhe.Context(**P)
+    ctx.keygen(W.key_seed(cfg_id))
+    A, Bm = W.operands(n, n, n, args.sparsity, W.workload_seed(cfg_id))
+    sa, sb = W.enc_seed(cfg_id, 0), W.enc_seed(cfg_id, 1)
+    log("encrypt B (%dx%d dense) and A (CSR, %.0f%% zeros)" % (n, n, 100 * args.sparsity))
+    EB = ctx.encrypt(Bm, "dense", sb, 1)
+    EA = ctx.encrypt(A, "csr", sa, 0)
+    torch.cuda.synchronize()
+
+    log("headline: %d warmup + %d timed steps" % (args.warmup, args.steps))
+    ctx.set_profiling(False)
+    times, st, C = timed(ctx, torch, EA, EB, "lazy", args.steps, args.warmup, keep_last=True)
+    ms = float(np.mean(times))
+    products = st.products
+    value = products / (ms / 1e3)
+    log("headline %.2f ms/step, %d products, %.4g ct-mults/s" % (ms, products, value))
+    # decrypted error of the headline result (outside the timed region)
+    dec = ctx.decrypt(C)
+    err = float(np.max(np.abs(dec - A @ Bm)))
+    C.close()
+
+    # per-step breakdown and the dominant kernel's live timing
+    ctx.set_profiling(True)
+    ptimes, pst, _ = timed(ctx, torch, EA, EB, "lazy", 1, 0)
+    ctx.set_profiling(False)
+    L, N = ctx.L, ctx.n
+    # tensor step: algorithmic multiply-adds and bytes per launch
+    muladds = 4.0 * products * L * N
+    t_ms = pst.tensor_ms
+    achieved = muladds / (t_ms / 1e3) / 1e12
+    peak = MULADD_PEAK / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T mod-muladd/s",
+                "frac": achieved / peak, "traffic": None,
+                "kernel": "tensor_lazy_kernel", "kernel_ms_per_step": t_ms,
+                "launches_per_step": int(pst.tensor_launches),
+                "kernel_ms_per_launch": t_ms / max(1, pst.tensor_launches)}
+    breakdown = {"tensor_ms": pst.tensor_ms, "keyswitch_ms": pst.keyswitch_ms, "rescale_ms": pst.rescale_ms,
+                 "total_ms": ptimes[0]}
+    log("breakdown %s" % json.dumps(breakdown))
+
+    legs = {}
+    want = set(x for x in args.only.split(",") if x) if args.only else None
+
+    def run(name):
+        return (not args.no_extras) and (want is None or name in want)
+
+    def leg(name, Amat, enc, sched, steps):
+        EAx = ctx.encrypt(Amat, enc, sa, 0)
+        tt, stx, _ = timed(ctx, torch, EAx, EB, sched, steps, 1 if steps > 1 else 0)
+        m = float(np.mean(tt))
+        legs[name] = {"ms": m, "products": int(stx.products), "ct_mults_per_s": stx.products / (m / 1e3),
+                      "keyswitches": int(stx.keyswitches)}
+        EAx.close()
+        log("%s: %.2f ms, %d products" % (name, m, stx.products))
+
+    if run("ell"):
+        leg("lazy_ell_50", A, "ell", "lazy", args.steps)
+    if run("naive"):
+        leg("lazy_naive_50", A, "naive", "lazy", args.steps)
+    if run("dense"):
+        leg("lazy_dense_same_operands", A, "dense", "lazy", args.steps)
+    if run("s90"):
+        A90, _ = W.operands(n, n, n, 0.9, W.workload_seed(cfg_id))
+        leg("lazy_csr_90", A90, "csr", "lazy", args.steps)
+        if run("dense"):
+            leg("lazy_dense_90_operands", A90, "dense", "lazy", 1)
+    if run("per_product"):
+        leg("per_product_csr_50", A, "csr", "per_product", 1)
+
+    cpu = None
+    if not args.no_cpu and run("cpu"):
+        threads = len(os.sched_getaffinity(0))
+        threads = max(1, min(threads, 16))
+        log("cpu baseline: oracle on %d threads" % threads)
+        cpu = cpu_baseline(P, A, Bm, cfg_id, threads)
+        log("cpu baseline %.4g ct-mults/s" % cpu["value"])
+
+    speedups = {}
+    if "lazy_dense_same_operands" in legs:
+        speedups["sparse50_over_dense"] = legs["lazy_dense_same_operands"]["ms"] / ms
+    if "lazy_csr_90" in legs and "lazy_dense_90_operands" in legs:
+        speedups["sparse90_over_dense"] = legs["lazy_dense_90_operands"]["ms"] / legs["lazy_csr_90"]["ms"]
+    if "per_product_csr_50" in legs:
+        speedups["lazy_over_per_product_50"] = legs["per_product_csr_50"]["ms"] / ms
+
+    out = {
+        "metric": "ms per encrypted 128x128x128 matmul @50%/90% sparsity; ct-mults/s vs dense",
+        "value": value,
+        "unit": "ct-mults/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "encrypted %dx%dx%d matmul, A %.0f%% unstructured sparsity (CSR), B dense, "
+                               "RNS-CKKS N=2^14, 5 data + 3 special primes, dnum=2, lazy relinearisation"
+                               % (n, n, n, 100 * args.sparsity),
+                   "products_per_step": int(products), "parallelism": "single GPU"},
+        "max_abs_err_vs_fp64": err,
+        "breakdown_ms": breakdown,
+        "legs": legs,
+        "speedups": speedups,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

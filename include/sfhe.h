@@ -109,6 +109,12 @@ typedef struct {
   int64_t products;         /* ct x ct tensor products executed */
   int64_t keyswitches;      /* relinearisations executed */
   int64_t outputs;          /* output ciphertexts written (trivial zeros included) */
+  /* with profiling on (sfhe_set_profiling): device time per step, from
+   * hipEvents recorded around each launch group on the call's stream */
+  double tensor_ms;         /* tensor products (and the lazy sums)              */
+  double keyswitch_ms;      /* ModUp, key products, ModDown, their NTTs         */
+  double rescale_ms;        /* rescale and per-product accumulation             */
+  int64_t tensor_launches;  /* launches of the tensor kernel                    */
 } sfhe_stats;
 
 /* Create a context: generate the primes, twiddle and conversion tables and
@@ -158,6 +164,12 @@ int sfhe_export_ct(sfhe_ctx* ctx, const sfhe_mat* m, int32_t i, int32_t j, uint6
 
 int sfhe_matrix_info(const sfhe_mat* m, sfhe_mat_info* out);
 int sfhe_last_stats(const sfhe_ctx* ctx, sfhe_stats* out);
+
+/* Per-step device timing of sfhe_matmul (off by default): with on != 0 the
+ * library records a hipEvent pair around each launch group of the tensor,
+ * key-switch and rescale steps; sfhe_last_stats sums them.  The events
+ * serialise nothing beyond the stream order the launches already have. */
+int sfhe_set_profiling(sfhe_ctx* ctx, int32_t on);
 void sfhe_mat_destroy(sfhe_mat* m);
 const char* sfhe_last_error(void);
 

@@ -48,6 +48,40 @@ static bool upload(sfhe_ctx* c, DevBuf<T>& buf, const std::vector<T>& v, hipStre
   return hipMemcpyAsync(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s) == hipSuccess;
 }
 
+// ---------------------------------------------------------------- timing
+enum { kCatTensor = 0, kCatKeyswitch = 1, kCatRescale = 2 };
+
+// brackets a launch group with an event pair when profiling is on
+struct StepTimer {
+  sfhe_ctx* c;
+  hipStream_t s;
+  hipEvent_t stop = nullptr;
+  StepTimer(sfhe_ctx* ctx, hipStream_t st, int cat) : c(ctx), s(st) {
+    if (!c->profiling) return;
+    hipEvent_t a = c->prof_event(), b = c->prof_event();
+    if (!a || !b) return;
+    (void)hipEventRecord(a, s);
+    c->prof_cat.push_back(cat);
+    stop = b;
+  }
+  ~StepTimer() {
+    if (stop) (void)hipEventRecord(stop, s);
+  }
+};
+
+}  // namespace sfhe
+
+hipEvent_t sfhe_ctx::prof_event() {
+  if (prof_used == prof_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    prof_pool.push_back(e);
+  }
+  return prof_pool[prof_used++];
+}
+
+namespace sfhe {
+
 // ---------------------------------------------------------------- context
 static int build_tables(sfhe_ctx* c) {
   using namespace hostmath;
@@ -351,8 +385,15 @@ int sfhe_ctx_create(const sfhe_params* p, const sfhe_device_hooks* hooks, sfhe_c
   GUARD_END
 }
 
+int sfhe_set_profiling(sfhe_ctx* c, int32_t on) {
+  if (!c) { set_error("NULL context"); return SFHE_E_INVALID_ARG; }
+  c->profiling = on != 0;
+  return SFHE_OK;
+}
+
 void sfhe_ctx_destroy(sfhe_ctx* c) {
   if (!c) return;
+  for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;
@@ -541,7 +582,9 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
   }
   std::vector<int64_t> visits(M);
   for (int i = 0; i < M; ++i) visits[i] = row_visits(A, i);
-  int64_t products = 0, keyswitches = 0;
+  int64_t products = 0, keyswitches = 0, tensor_launches = 0;
+  c->prof_used = 0;
+  c->prof_cat.clear();
   // outputs with no product are trivial zeros
   std::vector<int64_t> empty;
   for (int i = 0; i < M; ++i)
@@ -574,9 +617,19 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
       }
       const int64_t cnt = (int64_t)oi.size();
       if (!upload(c, d_oi, oi, s) || !upload(c, d_oj, oj, s)) { rc = SFHE_E_NOMEM; set_error("device allocation failed"); break; }
-      rc = launch_tensor_lazy(c, A, B, d_oi.ptr, d_oj.ptr, cnt, D.ptr, s);
-      if (!rc) rc = keyswitch_batch(c, lev, D.ptr + (int64_t)2 * nl * N, dw, D.ptr, dw, true, cnt, s);
-      if (!rc) rc = rescale_batch(c, lev, D.ptr, dw, out->data.ptr + o0 * ctw, ctw, cnt, s);
+      {
+        StepTimer tm(c, s, kCatTensor);
+        rc = launch_tensor_lazy(c, A, B, d_oi.ptr, d_oj.ptr, cnt, D.ptr, s);
+      }
+      ++tensor_launches;
+      if (!rc) {
+        StepTimer tm(c, s, kCatKeyswitch);
+        rc = keyswitch_batch(c, lev, D.ptr + (int64_t)2 * nl * N, dw, D.ptr, dw, true, cnt, s);
+      }
+      if (!rc) {
+        StepTimer tm(c, s, kCatRescale);
+        rc = rescale_batch(c, lev, D.ptr, dw, out->data.ptr + o0 * ctw, ctw, cnt, s);
+      }
       keyswitches += cnt;
     }
   } else {
@@ -601,11 +654,22 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
         set_error("device allocation failed");
         return SFHE_E_NOMEM;
       }
-      int r = launch_tensor_gather(c, lev, A->data.ptr, B->data.ptr, d_a.ptr, d_b.ptr, D.ptr, cnt, s);
+      int r;
+      {
+        StepTimer tm(c, s, kCatTensor);
+        r = launch_tensor_gather(c, lev, A->data.ptr, B->data.ptr, d_a.ptr, d_b.ptr, D.ptr, cnt, s);
+      }
+      ++tensor_launches;
       const int64_t dw = (int64_t)3 * nl * N;
-      if (!r) r = keyswitch_batch(c, lev, D.ptr + (int64_t)2 * nl * N, dw, D.ptr, dw, true, cnt, s);
-      if (!r) r = rescale_batch(c, lev, D.ptr, dw, T.ptr, ctw, cnt, s);
-      if (!r) r = launch_segment_sum(c, lev, T.ptr, out->data.ptr, d_seg.ptr, d_o.ptr, (int64_t)oidx.size(), s);
+      if (!r) {
+        StepTimer tm(c, s, kCatKeyswitch);
+        r = keyswitch_batch(c, lev, D.ptr + (int64_t)2 * nl * N, dw, D.ptr, dw, true, cnt, s);
+      }
+      if (!r) {
+        StepTimer tm(c, s, kCatRescale);
+        r = rescale_batch(c, lev, D.ptr, dw, T.ptr, ctw, cnt, s);
+        if (!r) r = launch_segment_sum(c, lev, T.ptr, out->data.ptr, d_seg.ptr, d_o.ptr, (int64_t)oidx.size(), s);
+      }
       products += cnt;
       keyswitches += cnt;
       aidx.clear();
@@ -651,9 +715,11 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
     delete out;
     return rc;
   }
+  c->stats = sfhe_stats{};
   c->stats.products = products;
   c->stats.keyswitches = keyswitches;
   c->stats.outputs = out->n_ct;
+  c->stats.tensor_launches = tensor_launches;
   c->stats_pending = true;
   *C = out;
   return SFHE_OK;
@@ -668,6 +734,15 @@ int sfhe_last_stats(const sfhe_ctx* cc, sfhe_stats* out) {
     float ms = 0;
     SFHE_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->stats.ms = ms;
+    double cat[3] = {0, 0, 0};
+    for (size_t x = 0; x < c->prof_cat.size(); ++x) {
+      float e = 0;
+      SFHE_HIP(hipEventElapsedTime(&e, c->prof_pool[2 * x], c->prof_pool[2 * x + 1]));
+      cat[c->prof_cat[x]] += e;
+    }
+    c->stats.tensor_ms = cat[kCatTensor];
+    c->stats.keyswitch_ms = cat[kCatKeyswitch];
+    c->stats.rescale_ms = cat[kCatRescale];
     c->stats_pending = false;
   }
   *out = c->stats;

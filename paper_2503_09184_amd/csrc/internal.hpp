@@ -97,6 +97,12 @@ struct sfhe_ctx {
   sfhe_stats stats{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool stats_pending = false;
+  // per-step timing: event pairs (start, stop) with a category each
+  bool profiling = false;
+  std::vector<hipEvent_t> prof_pool;
+  size_t prof_used = 0;
+  std::vector<int> prof_cat;
+  hipEvent_t prof_event();
 };
 
 struct sfhe_mat {

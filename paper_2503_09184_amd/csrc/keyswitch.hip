@@ -15,7 +15,9 @@
 
 namespace sfhe {
 
+// rows >= 1 (callers return early on empty work)
 static void grid_rows(int64_t rows, unsigned& gy, unsigned& gz) {
+  if (rows < 1) rows = 1;
   gy = rows < 65535 ? (unsigned)rows : 65535u;
   gz = (unsigned)((rows + gy - 1) / gy);
 }

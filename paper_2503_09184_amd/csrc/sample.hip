@@ -56,7 +56,9 @@ __global__ void enc_finish_kernel(u64* ct, int64_t nct, const u64* s_ntt, DevPar
   c0[t] = sub_mod(c0[t], as, P.q);
 }
 
+// rows >= 1 (callers return early on empty work)
 static void grid_rows(int64_t rows, unsigned& gy, unsigned& gz) {
+  if (rows < 1) rows = 1;
   gy = rows < 65535 ? (unsigned)rows : 65535u;
   gz = (unsigned)((rows + gy - 1) / gy);
 }
@@ -79,6 +81,7 @@ int encrypt_elements(sfhe_ctx* c, u64* ct, int64_t count, const int* d_ei, const
 }
 
 int encrypt_finish(sfhe_ctx* c, u64* ct, int64_t nct, hipStream_t s) {
+  if (nct <= 0) return SFHE_OK;
   const int N = c->N, L = c->L;
   int pos[2 * kMaxBasis], pr[2 * kMaxBasis];
   for (int r = 0; r < 2 * L; ++r) { pos[r] = r; pr[r] = r % L; }

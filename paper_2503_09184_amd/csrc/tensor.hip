@@ -169,7 +169,9 @@ __global__ void __launch_bounds__(256) tensor_lazy_kernel(LeftStruct S, const u6
   dx[(int64_t)2 * L * N] = reduce_wide(s2, P.q, P.mu_hi, P.mu_lo);
 }
 
+// rows >= 1 (callers return early on empty work)
 static void grid_rows(int64_t rows, unsigned& gy, unsigned& gz) {
+  if (rows < 1) rows = 1;
   gy = rows < 65535 ? (unsigned)rows : 65535u;
   gz = (unsigned)((rows + gy - 1) / gy);
 }

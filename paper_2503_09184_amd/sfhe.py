@@ -26,7 +26,7 @@ ERRORS = {
 EXPORTED = [
     "sfhe_ctx_create", "sfhe_ctx_destroy", "sfhe_ctx_n", "sfhe_ctx_primes", "sfhe_keygen",
     "sfhe_encrypt_matrix", "sfhe_matmul", "sfhe_decrypt_matrix", "sfhe_export_ct",
-    "sfhe_matrix_info", "sfhe_last_stats", "sfhe_mat_destroy", "sfhe_last_error",
+    "sfhe_matrix_info", "sfhe_last_stats", "sfhe_set_profiling", "sfhe_mat_destroy", "sfhe_last_error",
     "sfhe_ntt", "sfhe_tensor", "sfhe_keyswitch", "sfhe_rescale",
 ]
 
@@ -60,7 +60,8 @@ class MatInfo(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double), ("products", ctypes.c_int64), ("keyswitches", ctypes.c_int64),
-                ("outputs", ctypes.c_int64)]
+                ("outputs", ctypes.c_int64), ("tensor_ms", ctypes.c_double), ("keyswitch_ms", ctypes.c_double),
+                ("rescale_ms", ctypes.c_double), ("tensor_launches", ctypes.c_int64)]
 
 
 _lib = None
@@ -87,6 +88,7 @@ def lib():
         L.sfhe_export_ct.argtypes = [vp, vp, i32, i32, ctypes.POINTER(u64), ctypes.c_size_t, vp]
         L.sfhe_matrix_info.argtypes = [vp, ctypes.POINTER(MatInfo)]
         L.sfhe_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.sfhe_set_profiling.argtypes = [vp, i32]
         L.sfhe_mat_destroy.argtypes = [vp]
         L.sfhe_mat_destroy.restype = None
         L.sfhe_last_error.restype = ctypes.c_char_p
@@ -206,6 +208,9 @@ class Context:
         _check(lib().sfhe_matmul(self._h, A.handle, B.handle, SCHED[sched], _stream_handle(stream),
                                  ctypes.byref(h)))
         return Matrix(self, h)
+
+    def set_profiling(self, on):
+        _check(lib().sfhe_set_profiling(self._h, 1 if on else 0))
 
     def last_stats(self):
         s = Stats()

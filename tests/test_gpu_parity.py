@@ -210,7 +210,8 @@ def test_matmul_ragged_hybrid_all_outputs(torch_cuda, enc, sched):
     cts, _, _ = orc.matmul(A, B, enc, sched, 1234, 4321, threads=4)
     _all_outputs_equal(ctx, C, cts, 9, 7, enc + sched)
     dec = ctx.decrypt(C)
-    assert np.all(dec[3] == 0.0)
+    if enc != "dense":            # dense multiplies encryptions of zero: noise, not 0
+        assert np.all(dec[3] == 0.0)
     assert np.max(np.abs(dec - A @ B)) < 1e-6
 
 
