@@ -508,17 +508,25 @@ int sfhe_encrypt_matrix(sfhe_ctx* c, const double* vals, int32_t rows, int32_t c
   int rc = SFHE_OK;
   const size_t words = (size_t)m->n_ct * 2 * L * N;
   if (!m->data.alloc(&c->alloc, words)) { delete m; set_error("device allocation failed for the ciphertexts"); return SFHE_E_NOMEM; }
-  if (enc == SFHE_ENC_ELL) rc = launch_zero(m->data.ptr, (int64_t)words, s);
+  if (enc == SFHE_ENC_ELL) rc = launch_zero(m->data.ptr, (int64_t)words, s);   // padding: trivial zeros
   DevBuf<int> d_ei, d_ej;
   DevBuf<double> d_z;
   DevBuf<int64_t> d_slot;
-  if (!rc && (!upload(c, d_ei, ei, s) || !upload(c, d_ej, ej, s) || !upload(c, d_z, z, s) || !upload(c, d_slot, slot, s))) {
+  DevBuf<u64> tmp;
+  const int64_t count = (int64_t)ei.size();
+  const int64_t chunk = std::min<int64_t>(std::max<int64_t>(count, 1), 1024);
+  if (!rc && (!upload(c, d_ei, ei, s) || !upload(c, d_ej, ej, s) || !upload(c, d_z, z, s) || !upload(c, d_slot, slot, s) ||
+              !tmp.alloc(&c->alloc, (size_t)chunk * 2 * L * N))) {
     rc = SFHE_E_NOMEM;
     set_error("device allocation failed");
   }
-  if (!rc) rc = encrypt_elements(c, m->data.ptr, (int64_t)ei.size(), d_ei.ptr, d_ej.ptr, d_z.ptr, d_slot.ptr, seed,
-                                 operand_id, s);
-  if (!rc) rc = encrypt_finish(c, m->data.ptr, m->n_ct, s);
+  // per chunk of elements: sample, NTT, c0 -= c1 s, then store in the chunked layout
+  for (int64_t x0 = 0; x0 < count && !rc; x0 += chunk) {
+    const int64_t n = std::min(chunk, count - x0);
+    rc = encrypt_elements(c, tmp.ptr, n, d_ei.ptr + x0, d_ej.ptr + x0, d_z.ptr + x0, seed, operand_id, s);
+    if (!rc) rc = encrypt_finish(c, tmp.ptr, n, s);
+    if (!rc) rc = launch_to_chunked(c, tmp.ptr, (int64_t)2 * L * N, L, n, m->data.ptr, m->n_ct, d_slot.ptr + x0, 0, s);
+  }
   if (!rc && (!upload(c, m->d_row_ptr, m->row_ptr, s) || !upload(c, m->d_col_idx, m->col_idx, s) ||
               !upload(c, m->d_ell_col, m->ell_col, s) || !upload(c, m->d_mask, m->zero_mask, s))) {
     rc = SFHE_E_NOMEM;
@@ -591,35 +599,69 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
     if (visits[i] == 0)
       for (int j = 0; j < Nc; ++j) empty.push_back((int64_t)i * Nc + j);
   if (sched == SFHE_SCHED_LAZY) {
+    // batches: runs of consecutive non-empty rows, about 2048 outputs each
     const int64_t dw = (int64_t)3 * nl * N;
-    const int64_t tile_max = 512;
+    int rb = (int)std::max<int64_t>(kTileRows, (2048 / std::max(Nc, 1)) / kTileRows * kTileRows);
+    struct Batch { int r0, nr, t0, nt; };
+    std::vector<Batch> batches;
+    std::vector<int> tstart, ek, emask, eslot;
+    std::vector<std::pair<int, int64_t>> pairs;
+    std::vector<int> kmask(A->cols);
+    std::vector<int> kslot((size_t)A->cols * kTileRows);
+    for (int i = 0; i < M;) {
+      if (visits[i] == 0) { ++i; continue; }
+      int nr = 0;
+      while (i + nr < M && nr < rb && visits[i + nr] > 0) ++nr;
+      Batch bt{i, nr, (int)tstart.size(), 0};
+      for (int g = 0; g * kTileRows < nr; ++g) {
+        std::fill(kmask.begin(), kmask.end(), 0);
+        for (int r = 0; r < kTileRows && g * kTileRows + r < nr; ++r) {
+          row_pairs(A, i + g * kTileRows + r, pairs);
+          for (auto& pr : pairs) {
+            kmask[pr.first] |= 1 << r;
+            kslot[(size_t)pr.first * kTileRows + r] = (int)pr.second;
+          }
+        }
+        tstart.push_back((int)ek.size());
+        for (int k = 0; k < A->cols; ++k) {
+          if (!kmask[k]) continue;
+          ek.push_back(k);
+          emask.push_back(kmask[k]);
+          for (int r = 0; r < kTileRows; ++r) eslot.push_back((kmask[k] >> r) & 1 ? kslot[(size_t)k * kTileRows + r] : -1);
+        }
+        ++bt.nt;
+      }
+      batches.push_back(bt);
+      for (int r = 0; r < nr; ++r) products += visits[i + r] * (int64_t)Nc;
+      i += nr;
+    }
+    tstart.push_back((int)ek.size());
+    DevBuf<int> d_ts, d_ek, d_em, d_es;
     DevBuf<u64> D;
-    DevBuf<int> d_oi, d_oj;
-    std::vector<int> oi, oj;
-    int64_t o = 0;
-    const int64_t total = (int64_t)M * Nc;
-    if (!D.alloc(&c->alloc, (size_t)std::min<int64_t>(tile_max, std::max<int64_t>(total, 1)) * dw)) {
+    int64_t max_out = 0;
+    for (auto& bt : batches) max_out = std::max<int64_t>(max_out, (int64_t)bt.nr * Nc);
+    if (!upload(c, d_ts, tstart, s) || !upload(c, d_ek, ek, s) || !upload(c, d_em, emask, s) ||
+        !upload(c, d_es, eslot, s) || !D.alloc(&c->alloc, (size_t)std::max<int64_t>(max_out, 1) * dw)) {
       rc = SFHE_E_NOMEM;
       set_error("device allocation failed");
     }
-    while (!rc && o < total) {
-      // a tile of consecutive non-empty outputs
-      while (o < total && visits[o / Nc] == 0) ++o;
-      if (o >= total) break;
-      oi.clear();
-      oj.clear();
-      const int64_t o0 = o;
-      while (o < total && (int64_t)oi.size() < tile_max && visits[o / Nc] > 0) {
-        oi.push_back((int)(o / Nc));
-        oj.push_back((int)(o % Nc));
-        products += visits[o / Nc];
-        ++o;
-      }
-      const int64_t cnt = (int64_t)oi.size();
-      if (!upload(c, d_oi, oi, s) || !upload(c, d_oj, oj, s)) { rc = SFHE_E_NOMEM; set_error("device allocation failed"); break; }
+    for (size_t bi = 0; bi < batches.size() && !rc; ++bi) {
+      const Batch& bt = batches[bi];
+      TileList tl;
+      tl.tstart = d_ts.ptr + bt.t0;
+      tl.ek = d_ek.ptr;
+      tl.emask = d_em.ptr;
+      tl.eslot = d_es.ptr;
+      tl.n_row_tiles = bt.nt;
+      tl.n_col_tiles = 0;
+      tl.rows = bt.nr;
+      tl.Nc = Nc;
+      tl.nA = A->n_ct;
+      tl.nB = B->n_ct;
+      const int64_t cnt = (int64_t)bt.nr * Nc;
       {
         StepTimer tm(c, s, kCatTensor);
-        rc = launch_tensor_lazy(c, A, B, d_oi.ptr, d_oj.ptr, cnt, D.ptr, s);
+        rc = launch_tensor_tiles(c, tl, A->data.ptr, B->data.ptr, D.ptr, s);
       }
       ++tensor_launches;
       if (!rc) {
@@ -628,7 +670,8 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
       }
       if (!rc) {
         StepTimer tm(c, s, kCatRescale);
-        rc = rescale_batch(c, lev, D.ptr, dw, out->data.ptr + o0 * ctw, ctw, cnt, s);
+        rc = rescale_batch(c, lev, D.ptr, dw, OutLayout{out->data.ptr, 0, true, out->n_ct, (int64_t)bt.r0 * Nc}, cnt,
+                           s);
       }
       keyswitches += cnt;
     }
@@ -657,7 +700,7 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
       int r;
       {
         StepTimer tm(c, s, kCatTensor);
-        r = launch_tensor_gather(c, lev, A->data.ptr, B->data.ptr, d_a.ptr, d_b.ptr, D.ptr, cnt, s);
+        r = launch_tensor_gather(c, lev, A->data.ptr, A->n_ct, B->data.ptr, B->n_ct, d_a.ptr, d_b.ptr, D.ptr, cnt, s);
       }
       ++tensor_launches;
       const int64_t dw = (int64_t)3 * nl * N;
@@ -667,8 +710,9 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
       }
       if (!r) {
         StepTimer tm(c, s, kCatRescale);
-        r = rescale_batch(c, lev, D.ptr, dw, T.ptr, ctw, cnt, s);
-        if (!r) r = launch_segment_sum(c, lev, T.ptr, out->data.ptr, d_seg.ptr, d_o.ptr, (int64_t)oidx.size(), s);
+        r = rescale_batch(c, lev, D.ptr, dw, OutLayout{T.ptr, ctw, false, 0, 0}, cnt, s);
+        if (!r)
+          r = launch_segment_sum(c, lev, T.ptr, out->data.ptr, out->n_ct, d_seg.ptr, d_o.ptr, (int64_t)oidx.size(), s);
       }
       products += cnt;
       keyswitches += cnt;
@@ -704,7 +748,7 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
   if (!rc && !empty.empty()) {
     DevBuf<int64_t> d_e;
     if (!upload(c, d_e, empty, s)) { rc = SFHE_E_NOMEM; set_error("device allocation failed"); }
-    if (!rc) rc = launch_zero_outputs(out->data.ptr, ctw, d_e.ptr, (int64_t)empty.size(), s);
+    if (!rc) rc = launch_zero_outputs(c, out->data.ptr, out->n_ct, lev, d_e.ptr, (int64_t)empty.size(), s);
   }
   if (!rc) {
     hipError_t e = hipEventRecord(c->ev1, s);
@@ -756,15 +800,13 @@ int sfhe_decrypt_matrix(sfhe_ctx* c, const sfhe_mat* m, double* out, int64_t ld,
   if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
   if (ld < m->cols) { set_error("ld < cols"); return SFHE_E_SHAPE; }
   hipStream_t s = (hipStream_t)stream;
-  const int N = c->N;
-  const int64_t ctw = (int64_t)2 * (m->level + 1) * N;
   std::vector<double> vals(m->n_ct > 0 ? m->n_ct : 1, 0.0);
   if (m->n_ct > 0) {
     DevBuf<double> d_v;
     DevBuf<int> d_flag;
     if (!d_v.alloc(&c->alloc, m->n_ct) || !d_flag.alloc(&c->alloc, 1)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
     SFHE_HIP(hipMemsetAsync(d_flag.ptr, 0, sizeof(int), s));
-    int rc = decrypt_values(c, m->data.ptr, m->n_ct, ctw, m->level, m->scale, d_v.ptr, d_flag.ptr, s);
+    int rc = decrypt_values(c, m->data.ptr, m->n_ct, m->level, m->scale, d_v.ptr, d_flag.ptr, s);
     if (rc) return rc;
     int flag = 0;
     SFHE_HIP(hipMemcpyAsync(vals.data(), d_v.ptr, m->n_ct * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -808,10 +850,11 @@ int sfhe_export_ct(sfhe_ctx* c, const sfhe_mat* m, int32_t i, int32_t j, uint64_
   hipStream_t s = (hipStream_t)stream;
   DevBuf<u64> tmp;
   if (!tmp.alloc(&c->alloc, words)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
-  SFHE_HIP(hipMemcpyAsync(tmp.ptr, m->data.ptr + sl * (int64_t)words, words * sizeof(u64), hipMemcpyDeviceToDevice, s));
+  int rc = launch_from_chunked(c, m->data.ptr, m->n_ct, nl, 1, nullptr, sl, tmp.ptr, (int64_t)words, s);
+  if (rc) return rc;
   int pos[2 * kMaxBasis], pr[2 * kMaxBasis];
   for (int r = 0; r < 2 * nl; ++r) { pos[r] = r; pr[r] = r % nl; }
-  int rc = launch_ntt(c, tmp.ptr, 1, 0, 2 * nl, pos, pr, true, s);
+  rc = launch_ntt(c, tmp.ptr, 1, 0, 2 * nl, pos, pr, true, s);
   if (rc) return rc;
   SFHE_HIP(hipMemcpyAsync(out, tmp.ptr, words * sizeof(u64), hipMemcpyDeviceToHost, s));
   SFHE_HIP(hipStreamSynchronize(s));
@@ -859,7 +902,7 @@ int sfhe_rescale(sfhe_ctx* c, int32_t level, const uint64_t* in, uint64_t* out, 
   if (!c || !in || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
   if (level < 1 || level >= c->L || batch < 0) { set_error("bad level or batch"); return SFHE_E_LEVEL; }
   const int64_t nl = level + 1, N = c->N;
-  return rescale_batch(c, level, in, 2 * nl * N, out, 2 * level * N, batch, (hipStream_t)stream);
+  return rescale_batch(c, level, in, 2 * nl * N, OutLayout{out, 2 * level * N, false, 0, 0}, batch, (hipStream_t)stream);
   GUARD_END
 }
 

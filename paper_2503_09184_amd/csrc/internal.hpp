@@ -111,7 +111,7 @@ struct sfhe_mat {
   double scale = 0;
   sfhe_encoding enc = SFHE_ENC_DENSE;
   int64_t n_ct = 0, nnz = 0;
-  sfhe::DevBuf<sfhe::u64> data;          // [n_ct][2][level+1][N], NTT domain
+  sfhe::DevBuf<sfhe::u64> data;          // chunked layout (see chunk_index), NTT domain
   // plaintext structure (Sec. 3.3.2), host and device copies
   std::vector<int> row_ptr, col_idx;     // CSR
   int ell_w = 0;
@@ -122,6 +122,16 @@ struct sfhe_mat {
 };
 
 namespace sfhe {
+
+// Storage layout of an encrypted matrix: residue t of poly p (0, 1) of prime
+// i of stored ciphertext e sits at ((i * (N/64) + t/64) * 2 + p) * n_ct * 64
+// + e * 64 + t % 64.  For one prime and one 64-coefficient chunk every
+// ciphertext of the matrix is contiguous (n_ct * 1 KiB), so the tensor
+// kernel's working set for a chunk is one contiguous region instead of one
+// page per ciphertext; a 64-lane wavefront still reads 512 contiguous bytes.
+__host__ __device__ __forceinline__ int64_t chunk_index(int64_t e, int p, int i, int t, int64_t n_ct, int nchunk) {
+  return (((int64_t)i * nchunk + (t >> 6)) * 2 + p) * n_ct * 64 + e * 64 + (t & 63);
+}
 
 // ---- errors ----
 void set_error(const std::string& msg);
@@ -143,36 +153,67 @@ int launch_ntt(const sfhe_ctx* c, u64* base, int64_t batch, int64_t bstride, int
 // fill n words with zero
 int launch_zero(u64* p, int64_t n, hipStream_t s);
 
-// encryption of `count` elements (coordinates ei, ej, values z) into
-// ct[elem_slot[x]][2][L][N]; NTT domain on return.
-int encrypt_elements(sfhe_ctx* c, u64* ct, int64_t count, const int* d_ei, const int* d_ej,
-                     const double* d_z, const int64_t* d_slot, u64 seed, u64 operand, hipStream_t s);
-// NTT of every slot, then c0 <- c0 - c1 s
-int encrypt_finish(sfhe_ctx* c, u64* ct, int64_t nct, hipStream_t s);
+// coefficient-domain parts of `count` elements (coordinates ei, ej, values z):
+// tmp[x][2][L][N] = (e + m, a)
+int encrypt_elements(sfhe_ctx* c, u64* tmp, int64_t count, const int* d_ei, const int* d_ej,
+                     const double* d_z, u64 seed, u64 operand, hipStream_t s);
+// NTT of every row of tmp[count][2][L][N], then c0 <- c0 - c1 s
+int encrypt_finish(sfhe_ctx* c, u64* tmp, int64_t count, hipStream_t s);
+// layout conversions between limb-major rows src[x * sstride + (p * nl + i) * N + t]
+// and the chunked matrix layout, element elem[x] (or elem_base + x when elem is NULL)
+int launch_to_chunked(const sfhe_ctx* c, const u64* src, int64_t sstride, int nl, int64_t count, u64* dst,
+                      int64_t n_ct, const int64_t* elem, int64_t elem_base, hipStream_t s);
+int launch_from_chunked(const sfhe_ctx* c, const u64* src, int64_t n_ct, int nl, int64_t count, const int64_t* elem,
+                        int64_t elem_base, u64* dst, int64_t dstride, hipStream_t s);
 int keygen_device(sfhe_ctx* c, u64 seed, hipStream_t s);
-// decrypt + decode: values[x] for ciphertexts ct[x] (stride ctstride words) at level lev
-int decrypt_values(sfhe_ctx* c, const u64* ct, int64_t count, int64_t ctstride, int lev, double scale,
-                   double* d_out, int* d_flag, hipStream_t s);
+// decrypt + decode: values[e] for every ciphertext of a chunked matrix at level lev
+int decrypt_values(sfhe_ctx* c, const u64* data, int64_t n_ct, int lev, double scale, double* d_out, int* d_flag,
+                   hipStream_t s);
 
 // tensor products
 int launch_tensor_pointwise(const sfhe_ctx* c, int lev, const u64* a, int64_t astride, const u64* b,
                             int64_t bstride, u64* d, int64_t dstride, int64_t batch, hipStream_t s);
-// gathered product list: product p multiplies A ciphertext a_idx[p] by B ciphertext b_idx[p]
-int launch_tensor_gather(const sfhe_ctx* c, int lev, const u64* A, const u64* B, const int* d_aidx,
-                         const int* d_bidx, u64* d, int64_t count, hipStream_t s);
-// lazy sum over the visited k of output list (oi, oj)
-int launch_tensor_lazy(const sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, const int* d_oi,
-                       const int* d_oj, int64_t count, u64* d, hipStream_t s);
+// gathered product list: product p multiplies A ciphertext a_idx[p] by B
+// ciphertext b_idx[p] (chunked matrices with nA, nB ciphertexts), d limb-major
+int launch_tensor_gather(const sfhe_ctx* c, int lev, const u64* A, int64_t nA, const u64* B, int64_t nB,
+                         const int* d_aidx, const int* d_bidx, u64* d, int64_t count, hipStream_t s);
+// Row tiles of the lazy tensor: for tile g of kTileRows consecutive output
+// rows of the batch, entries tstart[g] .. tstart[g+1]-1, each a visited k
+// (ascending), a bit mask of the tile rows that visit it and, per tile row,
+// the A ciphertext slot (or -1).
+constexpr int kTileRows = 16;
+struct TileList {
+  const int* tstart;
+  const int* ek;
+  const int* emask;
+  const int* eslot;     // [entries][kTileRows]
+  int n_row_tiles;
+  int n_col_tiles;      // set per kernel from its TJ
+  int rows;             // output rows in the batch
+  int Nc;               // output columns (= B columns)
+  int64_t nA, nB;       // ciphertexts stored by A and B (chunked layout)
+};
+// D[pos * Nc + j][3][L][N] = sum over the visited k of tensor(A[row pos, k], B[k, j])
+int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, const u64* B, u64* D, hipStream_t s);
 
 // key switch of d2 rows (batch stride d2stride), result added into out
 // (batch stride ostride, [2][nl][N]) if add_in, else written.
 int keyswitch_batch(sfhe_ctx* c, int lev, const u64* d2, int64_t d2stride, u64* out, int64_t ostride,
                     bool add_in, int64_t batch, hipStream_t s);
-int rescale_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, u64* out, int64_t ostride,
-                  int64_t batch, hipStream_t s);
-// out[o] += sum of t[p] for p in seg[o] .. seg[o+1]-1 (rows [2][nl][N])
-int launch_segment_sum(const sfhe_ctx* c, int nl, const u64* t, u64* out, const int* d_seg,
+// where rescale writes: limb-major rows (stride words apart) or ciphertexts
+// elem_base + b of a chunked matrix holding n_ct ciphertexts
+struct OutLayout {
+  u64* base;
+  int64_t stride;
+  bool chunked;
+  int64_t n_ct, elem_base;
+};
+int rescale_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, OutLayout out, int64_t batch, hipStream_t s);
+// chunked out[oidx[o]] += sum of limb-major t[p] for p in seg[o] .. seg[o+1]-1 (rows [2][nl][N])
+int launch_segment_sum(const sfhe_ctx* c, int nl, const u64* t, u64* out, int64_t n_ct, const int* d_seg,
                        const int64_t* d_oidx, int64_t nout, hipStream_t s);
-int launch_zero_outputs(u64* out, int64_t ctwords, const int64_t* d_oidx, int64_t n, hipStream_t s);
+// zero ciphertexts oidx[0..n) of a chunked matrix at nl primes
+int launch_zero_outputs(const sfhe_ctx* c, u64* out, int64_t n_ct, int nl, const int64_t* d_oidx, int64_t n,
+                        hipStream_t s);
 
 }  // namespace sfhe

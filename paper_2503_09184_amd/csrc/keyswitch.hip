@@ -223,9 +223,8 @@ __global__ void rescale_lift_kernel(const u64* last, int lev, u64* R, int64_t ba
 }
 
 // out[b][p][i] = (in_i - R_i) q_lev^-1
-__global__ void rescale_finish_kernel(const u64* in, int64_t istride, int lev, const u64* R, u64* out,
-                                      int64_t ostride, const RescaleConst* __restrict__ rc, int64_t batch,
-                                      DevParams dp) {
+__global__ void rescale_finish_kernel(const u64* in, int64_t istride, int lev, const u64* R, OutLayout ol,
+                                      const RescaleConst* __restrict__ rc, int64_t batch, DevParams dp) {
   const int N = dp.N;
   const int nl = lev + 1;
   const int64_t row = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;   // (b, p, i)
@@ -238,11 +237,14 @@ __global__ void rescale_finish_kernel(const u64* in, int64_t istride, int lev, c
   const u64 qi = dp.pr[i].q;
   const u64 x = in[b * istride + ((int64_t)p * nl + i) * N + t];
   const u64 y = R[((b * 2 + p) * lev + i) * N + t];
-  out[b * ostride + ((int64_t)p * lev + i) * N + t] = mul_shoup(sub_mod(x, y, qi), rc->qinv[i], rc->qinv_s[i], qi);
+  const u64 v = mul_shoup(sub_mod(x, y, qi), rc->qinv[i], rc->qinv_s[i], qi);
+  if (ol.chunked)
+    ol.base[chunk_index(ol.elem_base + b, p, i, t, ol.n_ct, N >> 6)] = v;
+  else
+    ol.base[b * ol.stride + ((int64_t)p * lev + i) * N + t] = v;
 }
 
-int rescale_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, u64* out, int64_t ostride, int64_t batch,
-                  hipStream_t s) {
+int rescale_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, OutLayout out, int64_t batch, hipStream_t s) {
   if (batch <= 0) return SFHE_OK;
   if (lev < 1) { set_error("rescale: level 0 has no prime to drop"); return SFHE_E_LEVEL; }
   const int N = c->N, nl = lev + 1;
@@ -268,15 +270,15 @@ int rescale_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, u64* out
   if (rc) return rc;
   grid_rows(batch * 2 * lev, gy, gz);
   hipLaunchKernelGGL(rescale_finish_kernel, dim3((N + 255) / 256, gy, gz), dim3(256), 0, s, in, istride, lev, R.ptr,
-                     out, ostride, c->d_rescale.ptr + lev, batch, c->dp);
+                     out, c->d_rescale.ptr + lev, batch, c->dp);
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;
 }
 
 // ---------------------------------------------------------------- accumulation
-// out[oidx[o]] += sum_{p in seg[o]..seg[o+1]-1} t[p], rows [2][nl][N]
-__global__ void segment_sum_kernel(int nl, const u64* tv, u64* out, const int* seg, const int64_t* oidx, int64_t nout,
-                                   DevParams dp) {
+// chunked out[oidx[o]] += sum_{p in seg[o]..seg[o+1]-1} t[p], t limb-major [2][nl][N]
+__global__ void segment_sum_kernel(int nl, const u64* tv, u64* out, int64_t n_ct, const int* seg, const int64_t* oidx,
+                                   int64_t nout, DevParams dp) {
   const int N = dp.N;
   const int64_t row = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;   // (o, p, i)
   if (row >= nout * 2 * nl) return;
@@ -284,38 +286,43 @@ __global__ void segment_sum_kernel(int nl, const u64* tv, u64* out, const int* s
   if (t >= N) return;
   const int64_t o = row / (2 * nl);
   const int rem = (int)(row % (2 * nl));
-  const int i = rem % nl;
+  const int p = rem / nl, i = rem % nl;
   const u64 q = dp.pr[i].q;
   const int64_t cw = (int64_t)2 * nl * N;
-  u64 acc = out[oidx[o] * cw + (int64_t)rem * N + t];
-  for (int p = seg[o]; p < seg[o + 1]; ++p) acc = add_mod(acc, tv[(int64_t)p * cw + (int64_t)rem * N + t], q);
-  out[oidx[o] * cw + (int64_t)rem * N + t] = acc;
+  u64* dst = out + chunk_index(oidx[o], p, i, t, n_ct, N >> 6);
+  u64 acc = *dst;
+  for (int x = seg[o]; x < seg[o + 1]; ++x) acc = add_mod(acc, tv[(int64_t)x * cw + (int64_t)rem * N + t], q);
+  *dst = acc;
 }
 
-int launch_segment_sum(const sfhe_ctx* c, int nl, const u64* t, u64* out, const int* d_seg, const int64_t* d_oidx,
-                       int64_t nout, hipStream_t s) {
+int launch_segment_sum(const sfhe_ctx* c, int nl, const u64* t, u64* out, int64_t n_ct, const int* d_seg,
+                       const int64_t* d_oidx, int64_t nout, hipStream_t s) {
   if (nout <= 0) return SFHE_OK;
   unsigned gy, gz;
   grid_rows(nout * 2 * nl, gy, gz);
-  hipLaunchKernelGGL(segment_sum_kernel, dim3((c->N + 255) / 256, gy, gz), dim3(256), 0, s, nl, t, out, d_seg, d_oidx,
-                     nout, c->dp);
+  hipLaunchKernelGGL(segment_sum_kernel, dim3((c->N + 255) / 256, gy, gz), dim3(256), 0, s, nl, t, out, n_ct, d_seg,
+                     d_oidx, nout, c->dp);
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;
 }
 
-__global__ void zero_outputs_kernel(u64* out, int64_t ctwords, const int64_t* oidx, int64_t n) {
-  const int64_t o = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
-  if (o >= n) return;
-  u64* p = out + oidx[o] * ctwords;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < ctwords; x += (int64_t)gridDim.x * blockDim.x)
-    p[x] = 0;
+__global__ void zero_outputs_kernel(u64* out, int64_t n_ct, int nl, const int64_t* oidx, int64_t n, int N) {
+  const int64_t row = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;   // (o, p, i)
+  if (row >= n * 2 * nl) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const int64_t o = row / (2 * nl);
+  const int rem = (int)(row % (2 * nl));
+  out[chunk_index(oidx[o], rem / nl, rem % nl, t, n_ct, N >> 6)] = 0;
 }
 
-int launch_zero_outputs(u64* out, int64_t ctwords, const int64_t* d_oidx, int64_t n, hipStream_t s) {
+int launch_zero_outputs(const sfhe_ctx* c, u64* out, int64_t n_ct, int nl, const int64_t* d_oidx, int64_t n,
+                        hipStream_t s) {
   if (n <= 0) return SFHE_OK;
   unsigned gy, gz;
-  grid_rows(n, gy, gz);
-  hipLaunchKernelGGL(zero_outputs_kernel, dim3(64, gy, gz), dim3(256), 0, s, out, ctwords, d_oidx, n);
+  grid_rows(n * 2 * nl, gy, gz);
+  hipLaunchKernelGGL(zero_outputs_kernel, dim3((c->N + 255) / 256, gy, gz), dim3(256), 0, s, out, n_ct, nl, d_oidx, n,
+                     c->N);
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;
 }

@@ -129,4 +129,58 @@ int launch_zero(u64* p, int64_t n, hipStream_t s) {
   return SFHE_OK;
 }
 
+// ---- layout conversions (limb-major rows <-> chunked matrix layout) ----
+__global__ void to_chunked_kernel(const u64* src, int64_t sstride, int nl, int64_t count, u64* dst, int64_t n_ct,
+                                  const int64_t* elem, int64_t elem_base, int N) {
+  const int64_t row = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;   // (x, p, i)
+  if (row >= count * 2 * nl) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const int64_t x = row / (2 * nl);
+  const int pi = (int)(row % (2 * nl));
+  const int p = pi / nl, i = pi % nl;
+  const int64_t e = elem ? elem[x] : elem_base + x;
+  dst[chunk_index(e, p, i, t, n_ct, N >> 6)] = src[x * sstride + (int64_t)pi * N + t];
+}
+__global__ void from_chunked_kernel(const u64* src, int64_t n_ct, int nl, int64_t count, const int64_t* elem,
+                                    int64_t elem_base, u64* dst, int64_t dstride, int N) {
+  const int64_t row = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
+  if (row >= count * 2 * nl) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const int64_t x = row / (2 * nl);
+  const int pi = (int)(row % (2 * nl));
+  const int p = pi / nl, i = pi % nl;
+  const int64_t e = elem ? elem[x] : elem_base + x;
+  dst[x * dstride + (int64_t)pi * N + t] = src[chunk_index(e, p, i, t, n_ct, N >> 6)];
+}
+
+static void grid_rows(int64_t rows, unsigned& gy, unsigned& gz) {
+  if (rows < 1) rows = 1;
+  gy = rows < 65535 ? (unsigned)rows : 65535u;
+  gz = (unsigned)((rows + gy - 1) / gy);
+}
+
+int launch_to_chunked(const sfhe_ctx* c, const u64* src, int64_t sstride, int nl, int64_t count, u64* dst,
+                      int64_t n_ct, const int64_t* elem, int64_t elem_base, hipStream_t s) {
+  if (count <= 0) return SFHE_OK;
+  unsigned gy, gz;
+  grid_rows(count * 2 * nl, gy, gz);
+  hipLaunchKernelGGL(to_chunked_kernel, dim3((c->N + 255) / 256, gy, gz), dim3(256), 0, s, src, sstride, nl, count,
+                     dst, n_ct, elem, elem_base, c->N);
+  SFHE_HIP(hipGetLastError());
+  return SFHE_OK;
+}
+
+int launch_from_chunked(const sfhe_ctx* c, const u64* src, int64_t n_ct, int nl, int64_t count, const int64_t* elem,
+                        int64_t elem_base, u64* dst, int64_t dstride, hipStream_t s) {
+  if (count <= 0) return SFHE_OK;
+  unsigned gy, gz;
+  grid_rows(count * 2 * nl, gy, gz);
+  hipLaunchKernelGGL(from_chunked_kernel, dim3((c->N + 255) / 256, gy, gz), dim3(256), 0, s, src, n_ct, nl, count,
+                     elem, elem_base, dst, dstride, c->N);
+  SFHE_HIP(hipGetLastError());
+  return SFHE_OK;
+}
+
 }  // namespace sfhe

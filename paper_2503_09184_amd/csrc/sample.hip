@@ -17,9 +17,8 @@ struct SampleArgs {
 
 // ---------------------------------------------------------------- encryption
 // Coefficient-domain parts of element x: c1[r] = a_r, c0[r] = e + m.
-__global__ void enc_sample_kernel(u64* ct, int64_t count, const int* ei, const int* ej, const double* zv,
-                                  const int64_t* slot, u64 seed, u64 operand, double pow2,
-                                  const double* cosv, SampleArgs sa, DevParams dp) {
+__global__ void enc_sample_kernel(u64* ct, int64_t count, const int* ei, const int* ej, const double* zv, u64 seed,
+                                  u64 operand, double pow2, const double* cosv, SampleArgs sa, DevParams dp) {
   const int N = dp.N, L = dp.L;
   const int64_t x = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
   if (x >= count) return;
@@ -31,7 +30,7 @@ __global__ void enc_sample_kernel(u64* ct, int64_t count, const int* ei, const i
   const u64 ke = sm_field(sm_field(sm_field(sm_key(seed, kTagEncE), operand), i), j);
   const i64 e = cdt_sample(sa.cdt, sm_word(ke, (u64)t));
   const u64 ka0 = sm_field(sm_field(sm_field(sm_key(seed, kTagEncA), operand), i), j);
-  u64* base = ct + slot[x] * (int64_t)(2 * L) * N;
+  u64* base = ct + x * (int64_t)(2 * L) * N;
   for (int r = 0; r < L; ++r) {
     const PrimeDev& P = dp.pr[r];
     const u64 ka = sm_field(ka0, (u64)r);
@@ -40,7 +39,7 @@ __global__ void enc_sample_kernel(u64* ct, int64_t count, const int* ei, const i
   }
 }
 
-// NTT domain: c0 <- c0 - c1 * s, over all n_ct slots (padding slots are zero and stay zero).
+// NTT domain: c0 <- c0 - c1 * s
 __global__ void enc_finish_kernel(u64* ct, int64_t nct, const u64* s_ntt, DevParams dp) {
   const int N = dp.N, L = dp.L;
   const int64_t row = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;   // (slot, limb)
@@ -63,8 +62,8 @@ static void grid_rows(int64_t rows, unsigned& gy, unsigned& gz) {
   gz = (unsigned)((rows + gy - 1) / gy);
 }
 
-int encrypt_elements(sfhe_ctx* c, u64* ct, int64_t count, const int* d_ei, const int* d_ej,
-                     const double* d_z, const int64_t* d_slot, u64 seed, u64 operand, hipStream_t s) {
+int encrypt_elements(sfhe_ctx* c, u64* ct, int64_t count, const int* d_ei, const int* d_ej, const double* d_z,
+                     u64 seed, u64 operand, hipStream_t s) {
   const int N = c->N;
   if (count > 0) {
     SampleArgs sa;
@@ -73,8 +72,8 @@ int encrypt_elements(sfhe_ctx* c, u64* ct, int64_t count, const int* d_ei, const
     unsigned gy, gz;
     grid_rows(count, gy, gz);
     dim3 grid((N + 255) / 256, gy, gz);
-    hipLaunchKernelGGL(enc_sample_kernel, grid, dim3(256), 0, s, ct, count, d_ei, d_ej, d_z, d_slot, seed,
-                       operand, pow2, c->d_cos.ptr, sa, c->dp);
+    hipLaunchKernelGGL(enc_sample_kernel, grid, dim3(256), 0, s, ct, count, d_ei, d_ej, d_z, seed, operand, pow2,
+                       c->d_cos.ptr, sa, c->dp);
     SFHE_HIP(hipGetLastError());
   }
   return SFHE_OK;
@@ -226,12 +225,14 @@ __global__ void __launch_bounds__(256) dec_decode_kernel(const u64* m, int nl, i
   if (threadIdx.x == 0) out[x] = red[0] * inv_scale;
 }
 
-int decrypt_values(sfhe_ctx* c, const u64* ct, int64_t count, int64_t ctstride, int lev, double scale,
-                   double* d_out, int* d_flag, hipStream_t s) {
+int decrypt_values(sfhe_ctx* c, const u64* data, int64_t n_ct, int lev, double scale, double* d_out, int* d_flag,
+                   hipStream_t s) {
   const int N = c->N, nl = lev + 1;
   const int64_t chunk = 512;
-  DevBuf<u64> m;
-  if (!m.alloc(&c->alloc, (size_t)std::min<int64_t>(chunk, count) * nl * N)) {
+  const int64_t ctw = (int64_t)2 * nl * N;
+  DevBuf<u64> ct, m;
+  const size_t cap = (size_t)std::min<int64_t>(chunk, n_ct);
+  if (!ct.alloc(&c->alloc, cap * ctw) || !m.alloc(&c->alloc, cap * nl * N)) {
     set_error("decrypt: allocation failed");
     return SFHE_E_NOMEM;
   }
@@ -240,14 +241,16 @@ int decrypt_values(sfhe_ctx* c, const u64* ct, int64_t count, int64_t ctstride, 
     if (c->primes[r] > c->primes[big]) big = r;
   int pos[2 * kMaxBasis], pr[2 * kMaxBasis];
   for (int r = 0; r < nl; ++r) { pos[r] = r; pr[r] = r; }
-  for (int64_t x0 = 0; x0 < count; x0 += chunk) {
-    const int64_t n = std::min(chunk, count - x0);
+  for (int64_t x0 = 0; x0 < n_ct; x0 += chunk) {
+    const int64_t n = std::min(chunk, n_ct - x0);
+    int rc = launch_from_chunked(c, data, n_ct, nl, n, nullptr, x0, ct.ptr, ctw, s);
+    if (rc) return rc;
     unsigned gy, gz;
     grid_rows(n * nl, gy, gz);
-    hipLaunchKernelGGL(dec_phase_kernel, dim3((N + 255) / 256, gy, gz), dim3(256), 0, s, ct + x0 * ctstride, n,
-                       ctstride, nl, m.ptr, c->d_s.ptr, c->dp);
+    hipLaunchKernelGGL(dec_phase_kernel, dim3((N + 255) / 256, gy, gz), dim3(256), 0, s, ct.ptr, n, ctw, nl, m.ptr,
+                       c->d_s.ptr, c->dp);
     SFHE_HIP(hipGetLastError());
-    int rc = launch_ntt(c, m.ptr, n, (int64_t)nl * N, nl, pos, pr, true, s);
+    rc = launch_ntt(c, m.ptr, n, (int64_t)nl * N, nl, pos, pr, true, s);
     if (rc) return rc;
     hipLaunchKernelGGL(dec_decode_kernel, dim3((unsigned)n), dim3(256), 0, s, m.ptr, nl, big, 1.0 / scale,
                        c->d_cos.ptr, d_out + x0, d_flag, c->dp);

@@ -1,18 +1,10 @@
 // tensor.hip -- ciphertext tensor products in the NTT domain (the multiply
 // step of Algorithm 1): d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 per prime
-// and coefficient.
-//
-// The lazy form sums the tensors of every visited k of an output before any
-// reduction: 128-bit accumulators (each product < 2^122, folded every 32
-// products), one Barrett reduction at the end.  The visited k come straight
-// from the left operand's plaintext structure (Sec. 3.3.2): every k (naive
-// dense), the k whose zero-mask bit is clear (naive sparse), the CSR column
-// list of the row, or the row's ELLPACK columns other than -1.
+// and coefficient, one product at a time (per-product form) or summed over
+// every visited k of an output before any reduction (lazy form).
 #include "internal.hpp"
 
 namespace sfhe {
-
-__device__ __forceinline__ void fold(U128& a, const PrimeDev& P) { a = U128{reduce_wide(a, P.q, P.mu_hi, P.mu_lo), 0}; }
 
 // d[p][l][t] for `batch` pairs, strides in words
 __global__ void tensor_pointwise_kernel(int nl, const u64* a, int64_t as, const u64* b, int64_t bs, u64* d,
@@ -37,9 +29,10 @@ __global__ void tensor_pointwise_kernel(int nl, const u64* a, int64_t as, const 
   dx[(int64_t)(2 * nl + l) * N + t] = mul_mod(a1, b1, P);
 }
 
-// gathered: product x multiplies A ciphertext aidx[x] by B ciphertext bidx[x] (top level, L limbs)
-__global__ void tensor_gather_kernel(int nl, const u64* A, const u64* B, const int* aidx, const int* bidx, u64* d,
-                                     int64_t count, DevParams dp) {
+// gathered: product x multiplies A ciphertext aidx[x] by B ciphertext bidx[x]
+// (chunked matrices, top level, L primes); d limb-major
+__global__ void tensor_gather_kernel(int nl, const u64* A, int64_t nA, const u64* B, int64_t nB, const int* aidx,
+                                     const int* bidx, u64* d, int64_t count, DevParams dp) {
   const int N = dp.N;
   const int64_t row = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
   if (row >= count * nl) return;
@@ -48,11 +41,9 @@ __global__ void tensor_gather_kernel(int nl, const u64* A, const u64* B, const i
   const int64_t x = row / nl;
   const int l = (int)(row % nl);
   const PrimeDev& P = dp.pr[l];
-  const int64_t cts = (int64_t)2 * nl * N;
-  const u64* ax = A + (int64_t)aidx[x] * cts;
-  const u64* bx = B + (int64_t)bidx[x] * cts;
-  const u64 a0 = ax[(int64_t)l * N + t], a1 = ax[(int64_t)(nl + l) * N + t];
-  const u64 b0 = bx[(int64_t)l * N + t], b1 = bx[(int64_t)(nl + l) * N + t];
+  const int C = N >> 6;
+  const u64 a0 = A[chunk_index(aidx[x], 0, l, t, nA, C)], a1 = A[chunk_index(aidx[x], 1, l, t, nA, C)];
+  const u64 b0 = B[chunk_index(bidx[x], 0, l, t, nB, C)], b1 = B[chunk_index(bidx[x], 1, l, t, nB, C)];
   U128 m = mul_wide(a0, b1);
   add_wide(m, mul_wide(a1, b0));
   u64* dx = d + x * (int64_t)3 * nl * N;
@@ -61,115 +52,274 @@ __global__ void tensor_gather_kernel(int nl, const u64* A, const u64* B, const i
   dx[(int64_t)(2 * nl + l) * N + t] = mul_mod(a1, b1, P);
 }
 
-// ---- the left operand's visiting order, per encoding ----
-struct LeftStruct {
-  int K, cols_b;
-  const int* row_ptr;    // CSR
-  const int* col_idx;
-  const int* ell_col;    // ELL
-  int ell_w;
-  const uint32_t* mask;  // naive sparse
+// ---- lazy sums over a row tile's visited k ----
+// The host turns the left operand's plaintext structure (Sec. 3.3.2: every k
+// for naive dense, the unmasked k for naive sparse, the CSR column list, the
+// ELLPACK columns other than -1) into, for each tile of kTileRows consecutive
+// output rows, the ascending union of their visited k with a bit mask of the
+// rows that visit it and each such row's A ciphertext slot.  Mask tests are
+// uniform across a wavefront, so a zero of A costs no multiply.
+//
+// Block order is XCD-aware: consecutive blocks go to the 8 XCDs in turn, so
+// block b takes 64-coefficient chunk (b mod 8) of a 512-coefficient slab; a
+// slab's A and B stay resident in the Infinity Cache while every output tile
+// of the slab is computed, and each XCD's L2 sees one 64-coefficient chunk.
+
+// fp64 residue product: a*b - k*q exactly, with k = rint(a*b/q); |result| <= 1.5 q.
+// Exact for integers a, b < 2^44 and q < 2^42 (2Prod via fma; h - k q and
+// the sum with the rounding error are integers below 2^53).
+__device__ __forceinline__ double fp_mulmod_lazy(double a, double b, double q, double qinv) {
+  const double h = a * b;
+  const double l = fma(a, b, -h);
+  const double k = rint(h * qinv);
+  return fma(-k, q, h) + l;
+}
+// reduce an exact integer-valued double |x| < 2^53 to [0, q)
+__device__ __forceinline__ u64 fp_final(double x, double q, double qinv) {
+  const double k = floor(x * qinv);
+  double r = fma(-k, q, x);
+  r = r < 0.0 ? r + q : r;
+  r = r >= q ? r - q : r;
+  return (u64)r;
+}
+// |x| < 2^53 exact integer -> congruent value of magnitude <= q / 2 + 1
+__device__ __forceinline__ double fp_fold(double x, double q, double qinv) { return fma(-rint(x * qinv), q, x); }
+
+struct FpLimb {
+  int limb;
+  double q, qinv;
 };
 
-template <int ENC>
-struct RowIter;
+struct FpLimbs {
+  int n;
+  FpLimb l[kMaxBasis];
+};
 
-template <>
-struct RowIter<SFHE_ENC_DENSE> {
-  int i, n, pos;
-  const LeftStruct& S;
-  __device__ RowIter(const LeftStruct& s, int row) : i(row), n(s.K), pos(0), S(s) {}
-  __device__ bool next(int& k, int64_t& aslot) {
-    if (pos >= n) return false;
-    k = pos;
-    aslot = (int64_t)i * S.K + pos;
-    ++pos;
-    return true;
+constexpr int kWavesPerBlock = 8;
+constexpr int kSegEntries = 128;   // tile entries held in LDS at a time
+static_assert(kTileRows == 2 * kWavesPerBlock, "each wave stages two tile rows");
+
+struct ArithFp {   // q < 2^42: fp64 residues, Karatsuba middle term
+  typedef double Val;
+  struct Acc {
+    double d0, d2, ss;   // sums of a0 b0, a1 b1, (a0 + a1)(b0 + b1)
+  };
+  double q, qinv;
+  __device__ ArithFp(const FpLimb& F, const PrimeDev&) : q(F.q), qinv(F.qinv) {}
+  __device__ static Val load(u64 x) { return (double)x; }
+  __device__ static void zero(Acc& a) { a.d0 = a.d2 = a.ss = 0.0; }
+  __device__ static Val sum(Val x, Val y) { return x + y; }
+  __device__ void mac(Acc& a, Val a0, Val a1, Val as, Val b0, Val b1, Val bs) const {
+    a.d0 += fp_mulmod_lazy(a0, b0, q, qinv);
+    a.d2 += fp_mulmod_lazy(a1, b1, q, qinv);
+    a.ss += fp_mulmod_lazy(as, bs, q, qinv);
+  }
+  static constexpr int kFold = 1024;   // each product adds < 1.5 q to a sum: stay below 2^53
+  __device__ void fold(Acc& a) const {
+    a.d0 = fp_fold(a.d0, q, qinv);
+    a.d2 = fp_fold(a.d2, q, qinv);
+    a.ss = fp_fold(a.ss, q, qinv);
+  }
+  // d1 = (a0 + a1)(b0 + b1) - a0 b0 - a1 b1, formed once per output
+  __device__ void final(const Acc& a, u64& d0, u64& d1, u64& d2) const {
+    const double x0 = fp_fold(a.d0, q, qinv), x2 = fp_fold(a.d2, q, qinv);
+    const double x1 = fp_fold(a.ss, q, qinv) - x0 - x2;
+    d0 = fp_final(x0, q, qinv);
+    d1 = fp_final(x1, q, qinv);
+    d2 = fp_final(x2, q, qinv);
   }
 };
 
-template <>
-struct RowIter<SFHE_ENC_NAIVE_SPARSE> {
-  int i, pos;
-  const LeftStruct& S;
-  __device__ RowIter(const LeftStruct& s, int row) : i(row), pos(0), S(s) {}
-  __device__ bool next(int& k, int64_t& aslot) {
-    while (pos < S.K) {
-      const int64_t e = (int64_t)i * S.K + pos;
-      const bool zero = (S.mask[e >> 5] >> (e & 31)) & 1u;
-      ++pos;
-      if (!zero) { k = pos - 1; aslot = e; return true; }
-    }
-    return false;
-  }
-};
-
-template <>
-struct RowIter<SFHE_ENC_CSR> {
-  int p, end;
-  const LeftStruct& S;
-  __device__ RowIter(const LeftStruct& s, int row) : p(s.row_ptr[row]), end(s.row_ptr[row + 1]), S(s) {}
-  __device__ bool next(int& k, int64_t& aslot) {
-    if (p >= end) return false;
-    k = S.col_idx[p];
-    aslot = p;
-    ++p;
-    return true;
-  }
-};
-
-template <>
-struct RowIter<SFHE_ENC_ELL> {
-  int i, s;
-  const LeftStruct& S;
-  __device__ RowIter(const LeftStruct& st, int row) : i(row), s(0), S(st) {}
-  __device__ bool next(int& k, int64_t& aslot) {
-    while (s < S.ell_w) {
-      const int64_t e = (int64_t)i * S.ell_w + s;
-      const int kk = S.ell_col[e];
-      ++s;
-      if (kk >= 0) { k = kk; aslot = e; return true; }
-    }
-    return false;
-  }
-};
-
-// one block = one output (oi, oj), one prime l, 256 coefficients
-template <int ENC>
-__global__ void __launch_bounds__(256) tensor_lazy_kernel(LeftStruct S, const u64* A, const u64* B, const int* oi,
-                                                          const int* oj, int64_t count, u64* d, DevParams dp) {
-  const int N = dp.N, L = dp.L;
-  const int64_t o = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
-  if (o >= count) return;
-  const int tiles = N / 256;
-  const int l = blockIdx.x / tiles;
-  const int t = (blockIdx.x % tiles) * 256 + threadIdx.x;
-  const PrimeDev& P = dp.pr[l];
-  const int i = oi[o], j = oj[o];
-  const int64_t cts = (int64_t)2 * L * N;
-  U128 s0{0, 0}, s1{0, 0}, s2{0, 0};
-  RowIter<ENC> it(S, i);
-  int k;
-  int64_t aslot;
-  int n = 0;
-  while (it.next(k, aslot)) {
-    const u64* a = A + aslot * cts + (int64_t)l * N + t;
-    const u64* b = B + ((int64_t)k * S.cols_b + j) * cts + (int64_t)l * N + t;
-    const u64 a0 = a[0], a1 = a[(int64_t)L * N];
-    const u64 b0 = b[0], b1 = b[(int64_t)L * N];
-    add_wide(s0, mul_wide(a0, b0));
-    add_wide(s1, mul_wide(a0, b1));
-    add_wide(s1, mul_wide(a1, b0));
-    add_wide(s2, mul_wide(a1, b1));
-    if ((++n & 31) == 0) { fold(s0, P); fold(s1, P); fold(s2, P); }   // sums stay below 2^128
-  }
-  u64* dx = d + o * (int64_t)3 * L * N + (int64_t)l * N + t;
-  dx[0] = reduce_wide(s0, P.q, P.mu_hi, P.mu_lo);
-  dx[(int64_t)L * N] = reduce_wide(s1, P.q, P.mu_hi, P.mu_lo);
-  dx[(int64_t)2 * L * N] = reduce_wide(s2, P.q, P.mu_hi, P.mu_lo);
+// a*b added to a 128-bit sum from four 32x32 -> 64 products
+__device__ __forceinline__ void mac_wide(U128& acc, u64 a, u64 b) {
+  const u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
+  const u64 p00 = (u64)a0 * b0, p01 = (u64)a0 * b1, p10 = (u64)a1 * b0, p11 = (u64)a1 * b1;
+  const u64 mid = (p00 >> 32) + (u64)(u32)p01 + (u64)(u32)p10;
+  const u64 lo = (mid << 32) | (u64)(u32)p00;
+  const u64 hi = p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+  add_wide(acc, U128{lo, hi});
 }
 
-// rows >= 1 (callers return early on empty work)
+struct ArithInt {   // any q < 2^62: 128-bit integer sums
+  typedef u64 Val;
+  struct Acc {
+    U128 d0, d1, d2;
+  };
+  u64 q, mu_hi, mu_lo;
+  __device__ ArithInt(const FpLimb&, const PrimeDev& P) : q(P.q), mu_hi(P.mu_hi), mu_lo(P.mu_lo) {}
+  __device__ static Val load(u64 x) { return x; }
+  __device__ static void zero(Acc& a) { a.d0 = a.d1 = a.d2 = U128{0, 0}; }
+  __device__ static Val sum(Val, Val) { return 0; }
+  __device__ void mac(Acc& a, Val a0, Val a1, Val, Val b0, Val b1, Val) const {
+    mac_wide(a.d0, a0, b0);
+    mac_wide(a.d1, a0, b1);
+    mac_wide(a.d1, a1, b0);
+    mac_wide(a.d2, a1, b1);
+  }
+  static constexpr int kFold = 32;     // 64 terms below 2^122 stay below 2^128
+  __device__ void fold(Acc& a) const {
+    a.d0 = U128{reduce_wide(a.d0, q, mu_hi, mu_lo), 0};
+    a.d1 = U128{reduce_wide(a.d1, q, mu_hi, mu_lo), 0};
+    a.d2 = U128{reduce_wide(a.d2, q, mu_hi, mu_lo), 0};
+  }
+  __device__ void final(const Acc& a, u64& d0, u64& d1, u64& d2) const {
+    d0 = reduce_wide(a.d0, q, mu_hi, mu_lo);
+    d1 = reduce_wide(a.d1, q, mu_hi, mu_lo);
+    d2 = reduce_wide(a.d2, q, mu_hi, mu_lo);
+  }
+};
+
+// Block kernel: 8 waves share one 64-coefficient chunk of one prime and a
+// tile of kTileRows output rows.  Wave w owns output column h * kCols + w %
+// kCols for RPW rows: with RPW = kTileRows every wave sees the same rows, so
+// the work per visited k is identical across waves and the barrier costs no
+// imbalance; RPW = kTileRows / 2 splits the rows into two halves for the
+// 128-bit arithmetic's register budget.  Per visited k, the A values of the
+// tile rows that visit it are staged once through LDS (double-buffered) and
+// used by every column; each wave loads its own B[k, column] directly.
+// Global loads run two entries ahead of the multiplies.
+template <typename Arith, int RPW>
+__global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const u64* A, const u64* B, u64* D,
+                                                             FpLimbs fl, DevParams dp) {
+  typedef typename Arith::Val Val;
+  constexpr int kHalves = kTileRows / RPW;
+  constexpr int kCols = kWavesPerBlock / kHalves;
+  __shared__ Val sa[2][kTileRows][2][64];
+  __shared__ int s_ek[kSegEntries], s_em[kSegEntries];
+  __shared__ int s_es[kSegEntries][kTileRows];
+  const int N = dp.N, L = dp.L;
+  const int n_tiles = tl.n_row_tiles * tl.n_col_tiles;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int tile, li, tbase;
+  {
+    const int64_t b = blockIdx.x;
+    const int x = (int)(b & 7);
+    int64_t rest = b >> 3;
+    tile = (int)(rest % n_tiles);
+    rest /= n_tiles;
+    const int chunks512 = N / 512;
+    const int c512 = (int)(rest % chunks512);
+    li = (int)(rest / chunks512);
+    tbase = (c512 * 8 + x) * 64;
+  }
+  const int h = tile % tl.n_col_tiles, g = tile / tl.n_col_tiles;
+  const FpLimb& F = fl.l[li];
+  const int l = F.limb;
+  const Arith ar(F, dp.pr[l]);
+  const int Nc = tl.Nc;
+  // chunked layout: poly 0 of ciphertext e at base + e * 64, poly 1 one n_ct * 64 further
+  const int64_t cidx = (int64_t)l * (N >> 6) + (tbase >> 6);
+  const u64* Ab = A + cidx * 2 * tl.nA * 64 + lane;
+  const u64* Bb = B + cidx * 2 * tl.nB * 64 + lane;
+  const int64_t pA = tl.nA * 64, pB = tl.nB * 64;
+  const int half = wave / kCols;
+  const int j = h * kCols + (wave % kCols);
+  const int rbase = half * RPW;
+  const int arow0 = 2 * wave, arow1 = 2 * wave + 1;   // the rows this wave stages
+  typename Arith::Acc acc[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) Arith::zero(acc[r]);
+
+  const int e0 = tl.tstart[g], e1 = tl.tstart[g + 1];
+  struct Stage {
+    u64 b0, b1, a00, a01, a10, a11;
+    int mask;
+  };
+  // the tile's entry list goes through LDS in segments, so that the loads two
+  // entries ahead need no scalar memory round trip
+  auto fetch = [&](int x, int xend, Stage& st) {
+    st.mask = 0;
+    if (x >= xend) return;
+    const int k = s_ek[x];
+    st.mask = s_em[x];
+    st.b0 = st.b1 = 0;
+    if (j < Nc && ((st.mask >> rbase) & ((1 << RPW) - 1))) {
+      const u64* bp = Bb + ((int64_t)k * Nc + j) * 64;
+      st.b0 = bp[0];
+      st.b1 = bp[pB];
+    }
+    if ((st.mask >> arow0) & 1) {
+      const u64* ap = Ab + (int64_t)s_es[x][arow0] * 64;
+      st.a00 = ap[0];
+      st.a01 = ap[pA];
+    }
+    if ((st.mask >> arow1) & 1) {
+      const u64* ap = Ab + (int64_t)s_es[x][arow1] * 64;
+      st.a10 = ap[0];
+      st.a11 = ap[pA];
+    }
+  };
+  auto put = [&](const Stage& st, int bf) {
+    if ((st.mask >> arow0) & 1) {
+      sa[bf][arow0][0][lane] = Arith::load(st.a00);
+      sa[bf][arow0][1][lane] = Arith::load(st.a01);
+    }
+    if ((st.mask >> arow1) & 1) {
+      sa[bf][arow1][0][lane] = Arith::load(st.a10);
+      sa[bf][arow1][1][lane] = Arith::load(st.a11);
+    }
+  };
+  auto compute = [&](const Stage& st, int bf) {
+    const int wmask = (st.mask >> rbase) & ((1 << RPW) - 1);
+    if (!wmask) return;
+    const Val b0 = Arith::load(st.b0), b1 = Arith::load(st.b1);
+    const Val bs = Arith::sum(b0, b1);
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      if (wmask & (1 << r)) {
+        const Val a0 = sa[bf][rbase + r][0][lane], a1 = sa[bf][rbase + r][1][lane];
+        ar.mac(acc[r], a0, a1, Arith::sum(a0, a1), b0, b1, bs);
+      }
+    }
+  };
+  int cnt = 0;
+  for (int sg = e0; sg < e1; sg += kSegEntries) {
+    const int n = min(kSegEntries, e1 - sg);
+    __syncthreads();   // the previous segment's entries are no longer read
+    for (int x = threadIdx.x; x < n; x += blockDim.x) {
+      s_ek[x] = tl.ek[sg + x];
+      s_em[x] = tl.emask[sg + x];
+    }
+    for (int x = threadIdx.x; x < n * kTileRows; x += blockDim.x) s_es[x / kTileRows][x % kTileRows] = tl.eslot[(int64_t)sg * kTileRows + x];
+    __syncthreads();
+    Stage sA, sB;
+    fetch(0, n, sA);
+    fetch(1, n, sB);
+    for (int x = 0; x < n; x += 2) {
+      put(sA, 0);
+      __syncthreads();
+      const Stage cA = sA;
+      fetch(x + 2, n, sA);
+      compute(cA, 0);
+      if (x + 1 < n) {
+        put(sB, 1);
+        __syncthreads();
+        const Stage cB = sB;
+        fetch(x + 3, n, sB);
+        compute(cB, 1);
+      }
+      cnt += 2;
+      if (cnt >= Arith::kFold) {
+        cnt = 0;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) ar.fold(acc[r]);
+      }
+    }
+  }
+  if (j >= Nc) return;
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int pos = g * kTileRows + rbase + r;
+    if (pos >= tl.rows) continue;
+    u64* dp_ = D + ((int64_t)pos * Nc + j) * (int64_t)3 * L * N + (int64_t)l * N + tbase + lane;
+    u64 d0, d1, d2;
+    ar.final(acc[r], d0, d1, d2);
+    dp_[0] = d0;
+    dp_[(int64_t)L * N] = d1;
+    dp_[(int64_t)2 * L * N] = d2;
+  }
+}
+
 static void grid_rows(int64_t rows, unsigned& gy, unsigned& gz) {
   if (rows < 1) rows = 1;
   gy = rows < 65535 ? (unsigned)rows : 65535u;
@@ -188,52 +338,49 @@ int launch_tensor_pointwise(const sfhe_ctx* c, int lev, const u64* a, int64_t as
   return SFHE_OK;
 }
 
-int launch_tensor_gather(const sfhe_ctx* c, int lev, const u64* A, const u64* B, const int* d_aidx,
-                         const int* d_bidx, u64* d, int64_t count, hipStream_t s) {
+int launch_tensor_gather(const sfhe_ctx* c, int lev, const u64* A, int64_t nA, const u64* B, int64_t nB,
+                         const int* d_aidx, const int* d_bidx, u64* d, int64_t count, hipStream_t s) {
   if (count <= 0) return SFHE_OK;
   const int nl = lev + 1;
   unsigned gy, gz;
   grid_rows(count * nl, gy, gz);
-  hipLaunchKernelGGL(tensor_gather_kernel, dim3((c->N + 255) / 256, gy, gz), dim3(256), 0, s, nl, A, B, d_aidx,
-                     d_bidx, d, count, c->dp);
+  hipLaunchKernelGGL(tensor_gather_kernel, dim3((c->N + 255) / 256, gy, gz), dim3(256), 0, s, nl, A, nA, B, nB,
+                     d_aidx, d_bidx, d, count, c->dp);
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;
 }
 
-int launch_tensor_lazy(const sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, const int* d_oi, const int* d_oj,
-                       int64_t count, u64* d, hipStream_t s) {
-  if (count <= 0) return SFHE_OK;
-  LeftStruct S;
-  S.K = A->cols;
-  S.cols_b = B->cols;
-  S.row_ptr = A->d_row_ptr.ptr;
-  S.col_idx = A->d_col_idx.ptr;
-  S.ell_col = A->d_ell_col.ptr;
-  S.ell_w = A->ell_w;
-  S.mask = A->d_mask.ptr;
-  unsigned gy, gz;
-  grid_rows(count, gy, gz);
-  dim3 grid((unsigned)((c->N / 256) * c->L), gy, gz);
-  switch (A->enc) {
-    case SFHE_ENC_DENSE:
-      hipLaunchKernelGGL(tensor_lazy_kernel<SFHE_ENC_DENSE>, grid, dim3(256), 0, s, S, A->data.ptr, B->data.ptr, d_oi,
-                         d_oj, count, d, c->dp);
-      break;
-    case SFHE_ENC_NAIVE_SPARSE:
-      hipLaunchKernelGGL(tensor_lazy_kernel<SFHE_ENC_NAIVE_SPARSE>, grid, dim3(256), 0, s, S, A->data.ptr,
-                         B->data.ptr, d_oi, d_oj, count, d, c->dp);
-      break;
-    case SFHE_ENC_CSR:
-      hipLaunchKernelGGL(tensor_lazy_kernel<SFHE_ENC_CSR>, grid, dim3(256), 0, s, S, A->data.ptr, B->data.ptr, d_oi,
-                         d_oj, count, d, c->dp);
-      break;
-    case SFHE_ENC_ELL:
-      hipLaunchKernelGGL(tensor_lazy_kernel<SFHE_ENC_ELL>, grid, dim3(256), 0, s, S, A->data.ptr, B->data.ptr, d_oi,
-                         d_oj, count, d, c->dp);
-      break;
-  }
+template <typename Arith, int RPW>
+static int launch_block(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl, const u64* A, const u64* B, u64* D,
+                        hipStream_t s) {
+  if (fl.n == 0) return SFHE_OK;
+  constexpr int kCols = kWavesPerBlock / (kTileRows / RPW);
+  TileList t2 = tl;
+  t2.n_col_tiles = (tl.Nc + kCols - 1) / kCols;
+  const int64_t blocks = (int64_t)fl.n * (c->N / 64) * tl.n_row_tiles * t2.n_col_tiles;
+  if (blocks > 0x7FFFFFFF) { set_error("tensor: grid too large"); return SFHE_E_INVALID_ARG; }
+  hipLaunchKernelGGL((tensor_block_kernel<Arith, RPW>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, t2, A,
+                     B, D, fl, c->dp);
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;
+}
+
+int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, const u64* B, u64* D, hipStream_t s) {
+  if (tl.rows <= 0) return SFHE_OK;
+  // primes below 2^42 use the fp64 residue arithmetic, the others 128-bit integers
+  FpLimbs ffp{}, fint{};
+  for (int l = 0; l < c->L; ++l) {
+    const u64 q = c->primes[l];
+    FpLimb F{};
+    F.limb = l;
+    F.q = (double)q;
+    F.qinv = 1.0 / (double)q;
+    FpLimbs& dst = q < (1ull << 42) ? ffp : fint;
+    dst.l[dst.n++] = F;
+  }
+  int rc = launch_block<ArithFp, kTileRows / 2>(c, tl, ffp, A, B, D, s);
+  if (!rc) rc = launch_block<ArithInt, kTileRows / 4>(c, tl, fint, A, B, D, s);
+  return rc;
 }
 
 }  // namespace sfhe

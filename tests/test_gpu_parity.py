@@ -215,6 +215,32 @@ def test_matmul_ragged_hybrid_all_outputs(torch_cuda, enc, sched):
     assert np.max(np.abs(dec - A @ B)) < 1e-6
 
 
+@pytest.mark.parametrize("sched", ["lazy", "per_product"])
+def test_matmul_mixed_prime_sizes_all_outputs(torch_cuda, sched):
+    """61-, 50- and 41-bit data primes: each size takes a different tensor
+    arithmetic (128-bit integer, 20-bit fp64 pieces, fp64 residues)."""
+    P = dict(log_n=10, q_bits=[61, 50, 41], p_bits=[61, 61], dnum=2)
+    ctx, orc = pair(P, 17)
+    A, B = W.operands(6, 21, 5, 0.3, 41)
+    note("mixed primes %s" % sched)
+    C = ctx.matmul(ctx.encrypt(A, "csr", 5, 0), ctx.encrypt(B, "dense", 6, 1), sched)
+    cts, _, _ = orc.matmul(A, B, "csr", sched, 5, 6, threads=4)
+    _all_outputs_equal(ctx, C, cts, 6, 5, sched)
+
+
+def test_long_rows_fold_the_sums(torch_cuda):
+    """K = 600 dense: every lazy sum crosses the fold points of all three
+    tensor arithmetics (32, 256 and 512 products)."""
+    P = dict(log_n=10, q_bits=[61, 59, 40], p_bits=[61, 61], dnum=2)
+    ctx, orc = pair(P, 18)
+    A, B = W.operands(3, 600, 2, 0.0, 42)
+    note("K=600 lazy")
+    C = ctx.matmul(ctx.encrypt(A, "dense", 7, 0), ctx.encrypt(B, "dense", 8, 1), "lazy")
+    cts, _, _ = orc.matmul(A, B, "dense", "lazy", 7, 8, outputs=[(0, 0), (2, 1)], threads=2)
+    assert np.array_equal(ctx.export_ct(C, 0, 0), cts[0])
+    assert np.array_equal(ctx.export_ct(C, 2, 1), cts[1])
+
+
 def test_all_zero_left_operand(torch_cuda):
     ctx, orc = pair(HYB_SMALL, 21)
     A = np.zeros((3, 4))
