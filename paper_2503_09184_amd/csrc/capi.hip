@@ -114,12 +114,22 @@ static int build_tables(sfhe_ctx* c) {
   }
   if (!c->d_tables.alloc(&c->alloc, tab.size())) return SFHE_E_NOMEM;
   SFHE_HIP(hipMemcpy(c->d_tables.ptr, tab.data(), tab.size() * sizeof(u64), hipMemcpyHostToDevice));
+  std::vector<double> tabd((size_t)nb * 2 * N);
+  for (int r = 0; r < nb; ++r)
+    for (int m = 0; m < N; ++m) {
+      tabd[((size_t)r * 2 + 0) * N + m] = (double)tab[((size_t)r * 4 + 0) * N + m];
+      tabd[((size_t)r * 2 + 1) * N + m] = (double)tab[((size_t)r * 4 + 2) * N + m];
+    }
+  if (!c->d_tables_d.alloc(&c->alloc, tabd.size())) return SFHE_E_NOMEM;
+  SFHE_HIP(hipMemcpy(c->d_tables_d.ptr, tabd.data(), tabd.size() * sizeof(double), hipMemcpyHostToDevice));
   for (int r = 0; r < nb; ++r) {
     PrimeDev& P = c->dp.pr[r];
     P.tw = c->d_tables.ptr + ((size_t)r * 4 + 0) * N;
     P.tws = c->d_tables.ptr + ((size_t)r * 4 + 1) * N;
     P.itw = c->d_tables.ptr + ((size_t)r * 4 + 2) * N;
     P.itws = c->d_tables.ptr + ((size_t)r * 4 + 3) * N;
+    P.twd = c->d_tables_d.ptr + ((size_t)r * 2 + 0) * N;
+    P.itwd = c->d_tables_d.ptr + ((size_t)r * 2 + 1) * N;
   }
   // slot-0 decoding / encoding weights, from the host libm
   std::vector<double> cv(N);

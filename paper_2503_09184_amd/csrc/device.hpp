@@ -29,6 +29,8 @@ struct PrimeDev {
   const u64* tws;         // Shoup quotients of tw
   const u64* itw;         // psi^-brv(m)
   const u64* itws;
+  const double* twd;       // tw and itw as doubles (exact below 2^53)
+  const double* itwd;
 };
 
 struct DevParams {

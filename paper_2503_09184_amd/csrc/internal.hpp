@@ -84,6 +84,7 @@ struct sfhe_ctx {
   int device = 0;
   // device tables
   sfhe::DevBuf<sfhe::u64> d_tables;      // [nb][4][N]: tw, tws, itw, itws
+  sfhe::DevBuf<double> d_tables_d;       // [nb][2][N]: tw, itw as doubles
   sfhe::DevBuf<double> d_cos;            // cos(pi t / N)
   sfhe::DevBuf<sfhe::ModUpConst> d_modup;      // [L][dnum]
   sfhe::DevBuf<sfhe::ModDownConst> d_moddown;  // [L]
