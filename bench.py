@@ -28,13 +28,38 @@ import numpy as np
 
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
-# 64-bit modular multiply-add peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# 32-bit lane-ops/s, each 64x64 product needing 4 32x32->64 multiplies at
-# quarter rate (16 issue cycles) plus >= 4 full-rate adds for the 128-bit
-# accumulation: 20 lane-cycles per multiply-add.
-VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
-MULADD_CYCLES = 20.0
-MULADD_PEAK = VALU_LANE_OPS / MULADD_CYCLES   # 64-bit modular multiply-adds / s
+# VALU lane-op peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-op/s,
+# the issue rate of full-rate VALU instructions (fp64 FMA/MUL/RNDNE,
+# v_mad_u64_u32), i.e. the published 78.6 TFLOP/s fp64 vector peak / 2.
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
+# Algorithmic VALU ops per ciphertext product per prime and coefficient in the
+# fp64 residue arithmetic (primes below 2^42): three exact products
+# a*b - rint(a*b/q)*q (mul, fma, mul, rndne, fma, add) for a0 b0, a1 b1 and
+# the Karatsuba (a0+a1)(b0+b1), plus three accumulating adds.
+FP_OPS_PER_PRODUCT = 21
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tensor_fp_traffic.json")
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2503_09184_amd", "csrc", "tensor.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fp64 tensor kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE measurement, if it was taken on this
+    kernel source (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("tensor_hip_sha256_16") != source_digest():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def log(msg):
@@ -102,7 +127,9 @@ def main():
                     "s90,dense,ell,naive,per_product,cpu")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--pp-size", type=int, default=128, help="row count of A for the per-product leg")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size kernel for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -119,6 +146,15 @@ def main():
     cfg_id = 3
     P = W.PARAMS["realistic_n16384"]
     n = args.size
+    if args.calib_copy_mib:
+        n_words = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n_words, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read, %d MiB written" % (args.calib_copy_mib, args.calib_copy_mib))
+        del src, dst
     log("setup: context N=2^14, keys")
     ctx = sfhe.Context(**P)
     ctx.keygen(W.key_seed(cfg_id))
@@ -141,23 +177,25 @@ def main():
     err = float(np.max(np.abs(dec - A @ Bm)))
     C.close()
 
-    # per-step breakdown and the dominant kernel's live timing
+    # per-step breakdown and the dominant kernel's live timing (hipEvents on the
+    # library's stream, around each launch of the fp64 tensor kernel)
     ctx.set_profiling(True)
     ptimes, pst, _ = timed(ctx, torch, EA, EB, "lazy", 1, 0)
     ctx.set_profiling(False)
     L, N = ctx.L, ctx.n
-    # tensor step: algorithmic multiply-adds and bytes per launch
-    muladds = 4.0 * products * L * N
-    t_ms = pst.tensor_ms
-    achieved = muladds / (t_ms / 1e3) / 1e12
-    peak = MULADD_PEAK / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T mod-muladd/s",
-                "frac": achieved / peak, "traffic": None,
-                "kernel": "tensor_lazy_kernel", "kernel_ms_per_step": t_ms,
-                "launches_per_step": int(pst.tensor_launches),
-                "kernel_ms_per_launch": t_ms / max(1, pst.tensor_launches)}
-    breakdown = {"tensor_ms": pst.tensor_ms, "keyswitch_ms": pst.keyswitch_ms, "rescale_ms": pst.rescale_ms,
-                 "total_ms": ptimes[0]}
+    fp_ms = pst.tensor_fp_ms
+    launches = max(1, int(pst.tensor_fp_launches))
+    ops = float(products) * N * pst.tensor_fp_primes * FP_OPS_PER_PRODUCT
+    achieved = ops / (fp_ms / 1e3) / 1e12
+    peak = VALU_PEAK / 1e12
+    traffic = measured_traffic()
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T VALU-op/s",
+                "frac": achieved / peak, "traffic": traffic,
+                "kernel": "tensor_block_kernel<ArithFp> (primes below 2^42)",
+                "launches_per_step": launches, "ms_per_launch": fp_ms / launches,
+                "ops_per_launch": ops / launches, "primes": int(pst.tensor_fp_primes)}
+    breakdown = {"tensor_ms": pst.tensor_ms, "tensor_fp_ms": fp_ms, "keyswitch_ms": pst.keyswitch_ms,
+                 "rescale_ms": pst.rescale_ms, "total_ms": ptimes[0]}
     log("breakdown %s" % json.dumps(breakdown))
 
     legs = {}
@@ -216,7 +254,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64",
+        "dtype": "u64/f64",
         "data": "synthetic",
         "config": {"workload": "encrypted %dx%dx%d matmul, A %.0f%% unstructured sparsity (CSR), B dense, "
                                "RNS-CKKS N=2^14, 5 data + 3 special primes, dnum=2, lazy relinearisation"

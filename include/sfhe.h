@@ -111,10 +111,14 @@ typedef struct {
   int64_t outputs;          /* output ciphertexts written (trivial zeros included) */
   /* with profiling on (sfhe_set_profiling): device time per step, from
    * hipEvents recorded around each launch group on the call's stream */
-  double tensor_ms;         /* tensor products (and the lazy sums)              */
+  double tensor_ms;         /* tensor products and lazy sums, all primes        */
   double keyswitch_ms;      /* ModUp, key products, ModDown, their NTTs         */
   double rescale_ms;        /* rescale and per-product accumulation             */
-  int64_t tensor_launches;  /* launches of the tensor kernel                    */
+  int64_t tensor_launches;  /* launch groups of the tensor step                 */
+  double tensor_fp_ms;      /* the part of tensor_ms spent on primes below 2^42 */
+  int64_t tensor_fp_launches; /* launches of that kernel                        */
+  int32_t tensor_fp_primes; /* primes it covers                                 */
+  int32_t reserved;
 } sfhe_stats;
 
 /* Create a context: generate the primes, twiddle and conversion tables and

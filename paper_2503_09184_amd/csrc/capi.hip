@@ -49,7 +49,7 @@ static bool upload(sfhe_ctx* c, DevBuf<T>& buf, const std::vector<T>& v, hipStre
 }
 
 // ---------------------------------------------------------------- timing
-enum { kCatTensor = 0, kCatKeyswitch = 1, kCatRescale = 2 };
+enum { kCatTensor = 0, kCatKeyswitch = 1, kCatRescale = 2, kCatTensorFp = 3 };
 
 // brackets a launch group with an event pair when profiling is on
 struct StepTimer {
@@ -600,7 +600,7 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
   }
   std::vector<int64_t> visits(M);
   for (int i = 0; i < M; ++i) visits[i] = row_visits(A, i);
-  int64_t products = 0, keyswitches = 0, tensor_launches = 0;
+  int64_t products = 0, keyswitches = 0, tensor_launches = 0, tensor_fp_launches = 0;
   c->prof_used = 0;
   c->prof_cat.clear();
   // outputs with no product are trivial zeros
@@ -609,9 +609,13 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
     if (visits[i] == 0)
       for (int j = 0; j < Nc; ++j) empty.push_back((int64_t)i * Nc + j);
   if (sched == SFHE_SCHED_LAZY) {
-    // batches: runs of consecutive non-empty rows, about 2048 outputs each
+    // batches: runs of consecutive non-empty rows whose degree-2 sums D fit a
+    // 32 GiB budget (all 128 rows at N = 2^14, L = 5); one tensor launch per
+    // batch, then key switching and rescaling in slices of ~2048 outputs
     const int64_t dw = (int64_t)3 * nl * N;
-    int rb = (int)std::max<int64_t>(kTileRows, (2048 / std::max(Nc, 1)) / kTileRows * kTileRows);
+    const int64_t d_budget = (int64_t)32 << 30;
+    int rb = (int)std::max<int64_t>(kTileRows, d_budget / ((int64_t)std::max(Nc, 1) * dw * 8) / kTileRows * kTileRows);
+    const int64_t ks_slice = std::max<int64_t>(1, 2048);
     struct Batch { int r0, nr, t0, nt; };
     std::vector<Batch> batches;
     std::vector<int> tstart, ek, emask, eslot;
@@ -671,17 +675,28 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
       const int64_t cnt = (int64_t)bt.nr * Nc;
       {
         StepTimer tm(c, s, kCatTensor);
-        rc = launch_tensor_tiles(c, tl, A->data.ptr, B->data.ptr, D.ptr, s);
+        hipEvent_t f0 = nullptr, f1 = nullptr;
+        if (c->profiling) {
+          f0 = c->prof_event();
+          f1 = c->prof_event();
+          if (f0 && f1) c->prof_cat.push_back(kCatTensorFp);
+          else f0 = f1 = nullptr;
+        }
+        rc = launch_tensor_tiles(c, tl, A->data.ptr, B->data.ptr, D.ptr, s, f0, f1);
+        if (f0) ++tensor_fp_launches;
       }
       ++tensor_launches;
-      if (!rc) {
-        StepTimer tm(c, s, kCatKeyswitch);
-        rc = keyswitch_batch(c, lev, D.ptr + (int64_t)2 * nl * N, dw, D.ptr, dw, true, cnt, s);
-      }
-      if (!rc) {
-        StepTimer tm(c, s, kCatRescale);
-        rc = rescale_batch(c, lev, D.ptr, dw, OutLayout{out->data.ptr, 0, true, out->n_ct, (int64_t)bt.r0 * Nc}, cnt,
-                           s);
+      for (int64_t o0 = 0; o0 < cnt && !rc; o0 += ks_slice) {
+        const int64_t n = std::min(ks_slice, cnt - o0);
+        u64* Ds = D.ptr + o0 * dw;
+        {
+          StepTimer tm(c, s, kCatKeyswitch);
+          rc = keyswitch_batch(c, lev, Ds + (int64_t)2 * nl * N, dw, Ds, dw, true, n, s);
+        }
+        if (!rc) {
+          StepTimer tm(c, s, kCatRescale);
+          rc = rescale_batch(c, lev, Ds, dw, OutLayout{out->data.ptr, 0, true, out->n_ct, (int64_t)bt.r0 * Nc + o0}, n, s);
+        }
       }
       keyswitches += cnt;
     }
@@ -774,6 +789,8 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
   c->stats.keyswitches = keyswitches;
   c->stats.outputs = out->n_ct;
   c->stats.tensor_launches = tensor_launches;
+  c->stats.tensor_fp_launches = tensor_fp_launches;
+  c->stats.tensor_fp_primes = tensor_fp_prime_count(c);
   c->stats_pending = true;
   *C = out;
   return SFHE_OK;
@@ -788,7 +805,7 @@ int sfhe_last_stats(const sfhe_ctx* cc, sfhe_stats* out) {
     float ms = 0;
     SFHE_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->stats.ms = ms;
-    double cat[3] = {0, 0, 0};
+    double cat[4] = {0, 0, 0, 0};
     for (size_t x = 0; x < c->prof_cat.size(); ++x) {
       float e = 0;
       SFHE_HIP(hipEventElapsedTime(&e, c->prof_pool[2 * x], c->prof_pool[2 * x + 1]));
@@ -797,6 +814,7 @@ int sfhe_last_stats(const sfhe_ctx* cc, sfhe_stats* out) {
     c->stats.tensor_ms = cat[kCatTensor];
     c->stats.keyswitch_ms = cat[kCatKeyswitch];
     c->stats.rescale_ms = cat[kCatRescale];
+    c->stats.tensor_fp_ms = cat[kCatTensorFp];
     c->stats_pending = false;
   }
   *out = c->stats;

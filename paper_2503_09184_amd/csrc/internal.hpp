@@ -194,8 +194,11 @@ struct TileList {
   int Nc;               // output columns (= B columns)
   int64_t nA, nB;       // ciphertexts stored by A and B (chunked layout)
 };
-// D[pos * Nc + j][3][L][N] = sum over the visited k of tensor(A[row pos, k], B[k, j])
-int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, const u64* B, u64* D, hipStream_t s);
+// D[pos * Nc + j][3][L][N] = sum over the visited k of tensor(A[row pos, k], B[k, j]);
+// the fp64 kernel's launch is bracketed by fp_start / fp_stop when non-null
+int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, const u64* B, u64* D, hipStream_t s,
+                        hipEvent_t fp_start = nullptr, hipEvent_t fp_stop = nullptr);
+int tensor_fp_prime_count(const sfhe_ctx* c);
 
 // key switch of d2 rows (batch stride d2stride), result added into out
 // (batch stride ostride, [2][nl][N]) if add_in, else written.

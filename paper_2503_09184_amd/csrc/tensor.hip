@@ -188,21 +188,25 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   __shared__ int s_ek[kSegEntries], s_em[kSegEntries];
   __shared__ int s_es[kSegEntries][kTileRows];
   const int N = dp.N, L = dp.L;
-  const int n_tiles = tl.n_row_tiles * tl.n_col_tiles;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int tile, li, tbase;
+  // block b: XCD-aware order.  b mod 8 picks the 64-coefficient chunk of a
+  // 512-coefficient slab, so one XCD works on one chunk; above that the row
+  // tile varies fastest, then the column tile, then the slab: the row tiles
+  // of one column tile run back to back on an XCD and reuse its B from L2.
+  int g, h, li, tbase;
   {
     const int64_t b = blockIdx.x;
     const int x = (int)(b & 7);
     int64_t rest = b >> 3;
-    tile = (int)(rest % n_tiles);
-    rest /= n_tiles;
+    g = (int)(rest % tl.n_row_tiles);
+    rest /= tl.n_row_tiles;
+    h = (int)(rest % tl.n_col_tiles);
+    rest /= tl.n_col_tiles;
     const int chunks512 = N / 512;
     const int c512 = (int)(rest % chunks512);
     li = (int)(rest / chunks512);
     tbase = (c512 * 8 + x) * 64;
   }
-  const int h = tile % tl.n_col_tiles, g = tile / tl.n_col_tiles;
   const FpLimb& F = fl.l[li];
   const int l = F.limb;
   const Arith ar(F, dp.pr[l]);
@@ -365,7 +369,14 @@ static int launch_block(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl
   return SFHE_OK;
 }
 
-int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, const u64* B, u64* D, hipStream_t s) {
+int tensor_fp_prime_count(const sfhe_ctx* c) {
+  int n = 0;
+  for (int l = 0; l < c->L; ++l) n += c->primes[l] < (1ull << 42);
+  return n;
+}
+
+int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, const u64* B, u64* D, hipStream_t s,
+                        hipEvent_t fp_start, hipEvent_t fp_stop) {
   if (tl.rows <= 0) return SFHE_OK;
   // primes below 2^42 use the fp64 residue arithmetic, the others 128-bit integers
   FpLimbs ffp{}, fint{};
@@ -378,7 +389,9 @@ int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, con
     FpLimbs& dst = q < (1ull << 42) ? ffp : fint;
     dst.l[dst.n++] = F;
   }
+  if (fp_start) SFHE_HIP(hipEventRecord(fp_start, s));
   int rc = launch_block<ArithFp, kTileRows / 2>(c, tl, ffp, A, B, D, s);
+  if (fp_stop) SFHE_HIP(hipEventRecord(fp_stop, s));
   if (!rc) rc = launch_block<ArithInt, kTileRows / 4>(c, tl, fint, A, B, D, s);
   return rc;
 }

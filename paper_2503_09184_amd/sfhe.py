@@ -61,7 +61,9 @@ class MatInfo(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double), ("products", ctypes.c_int64), ("keyswitches", ctypes.c_int64),
                 ("outputs", ctypes.c_int64), ("tensor_ms", ctypes.c_double), ("keyswitch_ms", ctypes.c_double),
-                ("rescale_ms", ctypes.c_double), ("tensor_launches", ctypes.c_int64)]
+                ("rescale_ms", ctypes.c_double), ("tensor_launches", ctypes.c_int64),
+                ("tensor_fp_ms", ctypes.c_double), ("tensor_fp_launches", ctypes.c_int64),
+                ("tensor_fp_primes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
