@@ -115,7 +115,9 @@ typedef struct {
   double keyswitch_ms;      /* ModUp, key products, ModDown, their NTTs         */
   double rescale_ms;        /* rescale and per-product accumulation             */
   int64_t tensor_launches;  /* launch groups of the tensor step                 */
-  double tensor_fp_ms;      /* the part of tensor_ms spent on primes below 2^42 */
+  /* always measured (one hipEvent pair per launch, profiling on or off):
+   * device time of the tensor kernel for the primes below 2^42 */
+  double tensor_fp_ms;
   int64_t tensor_fp_launches; /* launches of that kernel                        */
   int32_t tensor_fp_primes; /* primes it covers                                 */
   int32_t reserved;

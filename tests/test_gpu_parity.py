@@ -310,3 +310,74 @@ def test_sweep_n8192_sampled_outputs_and_cross_encoding(torch_cuda, sparsity):
     cts, _, _ = orc.matmul(A, B, "csr", "lazy", sa, sb, outputs=sample, threads=8)
     for n, o in enumerate(outs["csr"]):
         assert np.array_equal(o, cts[n]), sample[n]
+
+
+# ---------------------------------------------------------------- full size
+def _threads():
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _realistic(sparsity):
+    P = W.PARAMS["realistic_n16384"]
+    ctx, orc = pair(P, W.key_seed(3))
+    A, B = W.operands(128, 128, 128, sparsity, W.workload_seed(3))
+    return ctx, orc, A, B, W.enc_seed(3, 0), W.enc_seed(3, 1)
+
+
+@pytest.mark.parametrize("sparsity", [0.5, 0.9])
+def test_realistic_128_lazy_sampled_outputs(torch_cuda, sparsity):
+    """The benchmarked product itself: 128 x 128 x 128 at N = 2^14 with five
+    data primes, CSR left operand, lazy schedule, the same calls and launch
+    configuration as the timed step.  Sampled outputs (including the corner
+    ones) match the oracle bit for bit, every one of the 16384 outputs
+    decrypts within 1e-6 of the fp64 product, and the ELLPACK and naive-sparse
+    encodings give the same ciphertexts on the samples."""
+    ctx, orc, A, B, sa, sb = _realistic(sparsity)
+    note("realistic 128^3 sparsity %.2f encrypt" % sparsity)
+    EB = ctx.encrypt(B, "dense", sb, 1)
+    # 256 sampled outputs: a 16 x 16 grid of rows and columns (corners
+    # included), so the oracle encrypts only the rows and columns it needs
+    rng = np.random.default_rng(1000 + int(sparsity * 100))
+    rows = sorted({0, 127} | set(int(x) for x in rng.choice(np.arange(1, 127), 14, replace=False)))
+    cols = sorted({0, 127} | set(int(x) for x in rng.choice(np.arange(1, 127), 14, replace=False)))
+    sample = [(i, j) for i in rows for j in cols]
+    assert len(sample) == 256
+    outs = {}
+    for enc in ("csr", "ell", "naive"):
+        note("realistic 128^3 sparsity %.2f %s lazy" % (sparsity, enc))
+        EA = ctx.encrypt(A, enc, sa, 0)
+        C = ctx.matmul(EA, EB, "lazy")
+        outs[enc] = [ctx.export_ct(C, i, j) for (i, j) in sample]
+        if enc == "csr":
+            dec = ctx.decrypt(C)
+            err = np.max(np.abs(dec - A @ B))
+            note("realistic max |err| %.3e" % err)
+            assert err < 1e-6
+        C.close()
+        EA.close()
+    for enc in ("ell", "naive"):
+        for x, y in zip(outs["csr"], outs[enc]):
+            assert np.array_equal(x, y), enc
+    note("realistic oracle on %d outputs" % len(sample))
+    cts, _, _ = orc.matmul(A, B, "csr", "lazy", sa, sb, outputs=sample, threads=_threads())
+    for n, o in enumerate(outs["csr"]):
+        assert np.array_equal(o, cts[n]), sample[n]
+
+
+def test_realistic_128_per_product_sampled_outputs(torch_cuda):
+    """The per-product schedule (relinearise and rescale every product, then
+    add) at the benchmarked size: sampled outputs match the oracle bit for bit
+    and every output decrypts within 1e-6."""
+    ctx, orc, A, B, sa, sb = _realistic(0.5)
+    note("realistic 128^3 per_product")
+    EB = ctx.encrypt(B, "dense", sb, 1)
+    EA = ctx.encrypt(A, "csr", sa, 0)
+    C = ctx.matmul(EA, EB, "per_product")
+    sample = [(0, 0), (64, 17), (127, 127)]
+    got = [ctx.export_ct(C, i, j) for (i, j) in sample]
+    dec = ctx.decrypt(C)
+    assert np.max(np.abs(dec - A @ B)) < 1e-6
+    cts, _, _ = orc.matmul(A, B, "csr", "per_product", sa, sb, outputs=sample, threads=_threads())
+    for n, o in enumerate(got):
+        assert np.array_equal(o, cts[n]), sample[n]
