@@ -184,8 +184,14 @@ const char* sfhe_last_error(void);
  * relinearise, rescale), exposed for testing and composition.  Polynomials
  * are rows of N uint64 residues in [0, q); "NTT domain" means the negacyclic
  * transform with index k holding a(psi^(2*brv(k)+1)), psi the smallest
- * primitive 2N-th root of unity mod q.  Buffers must not overlap unless
- * stated. */
+ * primitive 2N-th root of unity mod q.  Storage order of an NTT-domain row:
+ * index k at position k for N < 2^14; for N = 2^14 the transform kernels
+ * keep each thread's registers contiguous, so position r * 512 + t holds
+ * index ((r >> 4) << 13) | ((t & 63) << 4) | (t6 << 10) | (t8 << 11) |
+ * (t7 << 12) | (r & 15), where 0 <= r < 32, 0 <= t < 512 and t6..t8 are
+ * bits of t.  Every NTT-domain buffer of the library (matrices, keys,
+ * primitive inputs and outputs) uses that order; coefficient-domain rows are
+ * always in natural order.  Buffers must not overlap unless stated. */
 
 /* In-place negacyclic NTT (inverse = 0) or inverse NTT (inverse = 1) of
  * `batch` groups of n_limbs rows laid out [batch][n_limbs][N]; row l of a

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsfhe.so")
-SOURCES = ["ntt.hip", "sample.hip", "tensor.hip", "keyswitch.hip", "capi.hip"]
+SOURCES = ["ntt.hip", "sample.hip", "tensor.hip", "keyswitch.hip", "ks14.hip", "capi.hip"]
 
 
 def hipcc():
@@ -30,9 +30,16 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=o
          "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 
 
+# The register transforms unroll 32-register loops whose bodies are large;
+# LLVM's default cap on forced unrolling would leave some rolled, which puts
+# the register array in scratch memory.
+EXTRA = {"ks14.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"],
+         "ntt.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc()] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))

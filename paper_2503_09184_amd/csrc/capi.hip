@@ -174,6 +174,8 @@ static int build_tables(sfhe_ctx* c) {
           if (i2 != i) dq = mulmod(dq, c->primes[i2] % qi, qi);
         m.inv[i - m.lo] = invmod(dq, qi);
         m.inv_s[i - m.lo] = shoup(m.inv[i - m.lo], qi);
+        m.inv_n[i - m.lo] = mulmod(m.inv[i - m.lo], invmod((u64)N % qi, qi), qi);
+        m.inv_n_s[i - m.lo] = shoup(m.inv_n[i - m.lo], qi);
         for (int e = 0; e < m.ne; ++e) {
           const u64 qe = c->primes[m.basis[e]];
           u64 v = 1;  // (D/q_i) mod q_e
@@ -192,6 +194,8 @@ static int build_tables(sfhe_ctx* c) {
         if (k2 != k) v = mulmod(v, c->primes[L + k2] % pk, pk);
       d.pinv[k] = invmod(v, pk);
       d.pinv_s[k] = shoup(d.pinv[k], pk);
+      d.pinv_n[k] = mulmod(d.pinv[k], invmod((u64)N % pk, pk), pk);
+      d.pinv_n_s[k] = shoup(d.pinv_n[k], pk);
       for (int i = 0; i < nl; ++i) {
         const u64 qi = c->primes[i];
         u64 w = 1;
@@ -687,13 +691,19 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
       for (int64_t o0 = 0; o0 < cnt && !rc; o0 += ks_slice) {
         const int64_t n = std::min(ks_slice, cnt - o0);
         u64* Ds = D.ptr + o0 * dw;
+        const OutLayout ol{out->data.ptr, 0, true, out->n_ct, (int64_t)bt.r0 * Nc + o0};
+        if (keyswitch_rescale_n14_supported(c)) {   // fused transforms (key switch and rescale together)
+          StepTimer tm(c, s, kCatKeyswitch);
+          rc = keyswitch_rescale_n14(c, lev, Ds, dw, ol, n, s);
+          continue;
+        }
         {
           StepTimer tm(c, s, kCatKeyswitch);
           rc = keyswitch_batch(c, lev, Ds + (int64_t)2 * nl * N, dw, Ds, dw, true, n, s);
         }
         if (!rc) {
           StepTimer tm(c, s, kCatRescale);
-          rc = rescale_batch(c, lev, Ds, dw, OutLayout{out->data.ptr, 0, true, out->n_ct, (int64_t)bt.r0 * Nc + o0}, n, s);
+          rc = rescale_batch(c, lev, Ds, dw, ol, n, s);
         }
       }
       keyswitches += cnt;
@@ -727,15 +737,23 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
       }
       ++tensor_launches;
       const int64_t dw = (int64_t)3 * nl * N;
-      if (!r) {
+      const OutLayout ol{T.ptr, ctw, false, 0, 0};
+      if (!r && keyswitch_rescale_n14_supported(c)) {   // fused transforms (key switch and rescale together)
         StepTimer tm(c, s, kCatKeyswitch);
-        r = keyswitch_batch(c, lev, D.ptr + (int64_t)2 * nl * N, dw, D.ptr, dw, true, cnt, s);
+        r = keyswitch_rescale_n14(c, lev, D.ptr, dw, ol, cnt, s);
+      } else if (!r) {
+        {
+          StepTimer tm(c, s, kCatKeyswitch);
+          r = keyswitch_batch(c, lev, D.ptr + (int64_t)2 * nl * N, dw, D.ptr, dw, true, cnt, s);
+        }
+        if (!r) {
+          StepTimer tm(c, s, kCatRescale);
+          r = rescale_batch(c, lev, D.ptr, dw, ol, cnt, s);
+        }
       }
       if (!r) {
         StepTimer tm(c, s, kCatRescale);
-        r = rescale_batch(c, lev, D.ptr, dw, OutLayout{T.ptr, ctw, false, 0, 0}, cnt, s);
-        if (!r)
-          r = launch_segment_sum(c, lev, T.ptr, out->data.ptr, out->n_ct, d_seg.ptr, d_o.ptr, (int64_t)oidx.size(), s);
+        r = launch_segment_sum(c, lev, T.ptr, out->data.ptr, out->n_ct, d_seg.ptr, d_o.ptr, (int64_t)oidx.size(), s);
       }
       products += cnt;
       keyswitches += cnt;

@@ -22,12 +22,14 @@ struct ModUpConst {
   int ne;                              // extended basis size = lev + 1 + alpha
   int basis[kMaxBasis];                // basis index of extended position e
   u64 inv[kMaxDigit], inv_s[kMaxDigit];
+  u64 inv_n[kMaxDigit], inv_n_s[kMaxDigit];   // inv * N^-1 mod q_i (applied with an inverse NTT)
   u64 conv[kMaxDigit][kMaxBasis], conv_s[kMaxDigit][kMaxBasis];
 };
 // ModDown at level lev: y_k = [acc_{p_k} (P/p_k)^-1]_{p_k};
 // out_i = (acc_i - sum_k y_k [P/p_k]_{q_i}) [P^-1]_{q_i}.
 struct ModDownConst {
   u64 pinv[kMaxDigit], pinv_s[kMaxDigit];            // (P/p_k)^-1 mod p_k
+  u64 pinv_n[kMaxDigit], pinv_n_s[kMaxDigit];        // (P/p_k)^-1 N^-1 mod p_k
   u64 conv[kMaxDigit][kMaxBasis], conv_s[kMaxDigit][kMaxBasis];   // [P/p_k]_{q_i}
   u64 Pinv[kMaxBasis], Pinv_s[kMaxBasis];            // P^-1 mod q_i
 };
@@ -94,6 +96,7 @@ struct sfhe_ctx {
   bool has_keys = false;
   sfhe::DevBuf<sfhe::u64> d_s;           // secret, NTT domain [nb][N]
   sfhe::DevBuf<sfhe::u64> d_rlk;         // relinearisation key, NTT domain [dnum][2][nb][N]
+  sfhe::DevBuf<sfhe::u64> d_rlk_s;       // its Shoup companions floor(k 2^64 / q), same layout
   // last matmul
   sfhe_stats stats{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -213,6 +216,11 @@ struct OutLayout {
   int64_t n_ct, elem_base;
 };
 int rescale_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, OutLayout out, int64_t batch, hipStream_t s);
+// N = 2^14 only: Rescale((d0, d1) + KeySwitch(d2)) for n lazy sums D[b]
+// (stride dw words; rows d0, d1, d2 of lev + 1 primes, NTT domain) in four
+// fused transform kernels; the result goes to out (NTT domain, lev primes)
+int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s);
+bool keyswitch_rescale_n14_supported(const sfhe_ctx* c);
 // chunked out[oidx[o]] += sum of limb-major t[p] for p in seg[o] .. seg[o+1]-1 (rows [2][nl][N])
 int launch_segment_sum(const sfhe_ctx* c, int nl, const u64* t, u64* out, int64_t n_ct, const int* d_seg,
                        const int64_t* d_oidx, int64_t nout, hipStream_t s);

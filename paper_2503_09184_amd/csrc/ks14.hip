@@ -1,0 +1,524 @@
+// ks14.hip -- relinearisation and rescale of the lazy sums at N = 2^14,
+// fused around the register transforms of ntt14.hpp (the key-switch and
+// rescale steps of Algorithm 1, applied once per output).
+//
+// For a slice of n outputs at level lev (data primes q_0..q_lev, special
+// primes p_0..p_{alpha-1}, digits D_j of alpha consecutive data primes) with
+// D[b] = (d0, d1, d2) in the NTT domain, these kernels compute
+// C[b] = Rescale((d0, d1) + KeySwitch(d2)):
+//
+//  K1 (b, i)    y_i = [iNTT(d2_i) (D_j/q_i)^-1]_{q_i}: ModUp's pre-scale,
+//               with N^-1 folded into the constant.
+//  BConv (b, x) ext_{j,e} = sum_{i in D_j} y_i [D_j/q_i]_e for every digit j
+//               and every prime e outside it (element-wise).
+//  K2 (b, e)    x_j = NTT(ext_{j,e}) for the digits j not holding e, and the
+//               key products acc_p = sum_j x_j rlk_j,p[e] (+ d2_e rlk_own,p[e]
+//               when e is a data prime of digit own).  Data prime: acc_p is
+//               kept (NTT domain).  Special prime p_k: acc_p goes back to
+//               coefficients times (P/p_k)^-1, ModDown's pre-scale yP_k.
+//  K3a (b, p)   the last prime of the key-switched sum, in coefficients:
+//               r = iNTT(acc_lev P^-1 + d_lev) - z_lev P^-1 with
+//               z_i = sum_k yP_k [P/p_k]_{q_i}.
+//  Lift (b, p, x)  w_i = z_i P^-1 + [centered r]_{q_i} for i < lev
+//               (element-wise).
+//  K3b (b, p, i), i < lev:  C_i = (acc_i P^-1 + d_i - NTT(w_i)) q_lev^-1.
+//
+// Every identity is exact modular arithmetic, so the result is the same, bit
+// for bit, as key switching with uncentered fast base conversions followed
+// by an exactly rounded rescale.  Per output this takes 4 L + 4 + (the base
+// conversions') transforms -- 32 at L = 5, alpha = 3, dnum = 2 -- instead of
+// the 42 of the separate steps.  The transform kernels only load, transform
+// and store with light arithmetic on either side; the two base conversions,
+// whose sums over primes would not fit beside a row in registers, are
+// element-wise kernels of their own.
+//
+// Each transform block has 512 threads and 66.5 KiB of LDS, two blocks per
+// CU.  NTT-domain rows are in the register-major order pos_c of ntt14.hpp,
+// the private coefficient rows (y, ext, yP, r, w) in pos_a, so every access
+// of a register by a wave is one contiguous 512-byte run.
+#include "ntt14.hpp"
+
+namespace sfhe {
+
+namespace {
+
+using n14::kN;
+using n14::pos_a;
+using n14::pos_c;
+using n14::after;
+
+// keeps the scheduler from hoisting the loads of all 32 element-wise steps
+// at once (which would spill): every group of G steps is scheduled apart
+template <int G>
+__device__ __forceinline__ void group_fence(int u) {
+  if ((u % G) == G - 1) __builtin_amdgcn_sched_barrier(0);
+}
+
+struct Ks14Args {
+  const u64* D;          // [n] x dw words: d0, d1, d2 rows of nl primes (NTT domain)
+  int64_t dw;
+  u64* y;                // [n][nl][N]          ModUp inputs, coefficients
+  u64* ext;              // [n][next][N]        base-converted digits, coefficients
+  int next;              // rows of ext per output: sum over digits of (ne - digit size)
+  u64* accQ;             // [n][2][nl][N]       key products on the data primes, NTT domain
+  u64* part;             // [n][alpha][2][N]    key products on the special primes so far, NTT domain
+  u64* yP;               // [n][2][alpha][N]    ModDown inputs, coefficients
+  u64* r;                // [n][2][N]           last prime of the key-switched sum, coefficients
+  u64* w;                // [n][2][lev][N]      rescale inputs of the remaining primes, coefficients
+  const u64* rlk;        // [dnum][2][nb][N]
+  const u64* rlk_s;      // Shoup companions of rlk
+  const ModUpConst* mu;  // [dnum] at this level
+  const ModDownConst* md;
+  const RescaleConst* rs;
+  int lev, nl, n;
+};
+
+// row of ext holding digit j converted to extended-basis position e (e outside the digit)
+__device__ __forceinline__ int ext_slot(const ModUpConst* mu, int ne, int j, int e) {
+  int base = 0;
+  for (int jj = 0; jj < j; ++jj) base += ne - (mu[jj].hi - mu[jj].lo);
+  return base + (e < mu[j].lo ? e : e - (mu[j].hi - mu[j].lo));
+}
+
+template <typename Ar>
+__device__ __forceinline__ void load_a(const Ar& ar, typename Ar::Val (&v)[32], const u64* row, int t) {
+#pragma unroll
+  for (int u = 0; u < 32; ++u) v[u] = ar.in(row[pos_a(t, u)]);
+}
+template <typename Ar>
+__device__ __forceinline__ void load_c(const Ar& ar, typename Ar::Val (&v)[32], const u64* row, int t) {
+#pragma unroll
+  for (int r = 0; r < 32; ++r) v[r] = ar.in(row[pos_c(t, r)]);
+}
+
+// ---------------------------------------------------------------- K1
+template <typename Ar>
+__device__ __forceinline__ void k1_body(const Ks14Args& a, const DevParams& dp, int b, int i, void* lds) {
+  typedef typename Ar::Val Val;
+  const int t = threadIdx.x;
+  const PrimeDev& P = dp.pr[i];
+  const Ar ar(P, true);
+  Val v[32];
+  load_c(ar, v, a.D + (int64_t)b * a.dw + (int64_t)(2 * a.nl + i) * kN, t);
+  n14::inverse(ar, v, reinterpret_cast<Val*>(lds), t);
+  const ModUpConst& m = a.mu[i / dp.alpha];
+  const u64 w = m.inv_n[i - m.lo], ws = m.inv_n_s[i - m.lo];
+  u64* dst = a.y + ((int64_t)b * a.nl + i) * kN;
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    dst[pos_a(t, u)] = ar.out_mul(v[u], w, ws);
+    group_fence<8>(u);
+  }
+}
+
+__global__ void __launch_bounds__(n14::kThreads, 4) ks14_k1_kernel(Ks14Args a, DevParams dp) {
+  extern __shared__ u64 lds[];
+  const int b = blockIdx.x / a.nl, i = blockIdx.x % a.nl;
+  if (dp.pr[i].q < (1ull << 42))
+    k1_body<NttFp>(a, dp, b, i, lds);
+  else
+    k1_body<NttInt>(a, dp, b, i, lds);
+}
+
+// ---------------------------------------------------------------- BConv
+// one position of one output per thread; grid (N / 256, n)
+__global__ void __launch_bounds__(256) ks14_bconv_kernel(Ks14Args a, DevParams dp) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int b = blockIdx.y;
+  const int ne = a.nl + dp.alpha;
+  const u64* yb = a.y + (int64_t)b * a.nl * kN + x;
+  u64* eb = a.ext + (int64_t)b * a.next * kN + x;
+  int slot = 0;
+  for (int j = 0; j < dp.dnum; ++j) {
+    const ModUpConst& mc = a.mu[j];
+    if (mc.lo >= mc.hi) break;
+    for (int e = 0; e < ne; ++e) {
+      if (e >= mc.lo && e < mc.hi) continue;
+      const u64 q = dp.pr[mc.basis[e]].q;
+      u64 s = 0;
+      for (int i = mc.lo; i < mc.hi; ++i)
+        s = add_mod(s, mul_shoup(yb[(int64_t)i * kN], mc.conv[i - mc.lo][e], mc.conv_s[i - mc.lo][e], q), q);
+      eb[(int64_t)slot * kN] = s;
+      ++slot;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- K2
+// the key rows one digit multiplies: rlk_j,0[e] and its Shoup companions (the
+// p = 1 rows are `next` words further), and the same for e's own digit
+struct KeyRows {
+  const u64 *k, *ks, *ok, *oks;
+  int64_t next;
+};
+
+// key products of one transformed digit:
+// s_p = X rlk_p (+ o_p unless FIRST) (+ d2_e rlk_own,p if OWN); s_1 goes to o1,
+// s_0 to o0, or back into v for the inverse transform if KEEP0
+template <bool FIRST, bool OWN, bool KEEP0, typename Ar>
+__device__ __forceinline__ void k2_products(const Ar& ar, typename Ar::Val (&v)[32], const KeyRows& kr, const u64* d2e,
+                                            u64* o0, u64* o1, u64 q, int t) {
+  const int tt = after(t, v[15], v[31]);
+#pragma unroll
+  for (int r = 0; r < 32; ++r) {
+    const int x = pos_c(tt, r);
+    const u64 X = ar.fwd_res(v[r]);
+    u64 s0 = mul_shoup(X, kr.k[x], kr.ks[x], q);
+    u64 s1 = mul_shoup(X, kr.k[kr.next + x], kr.ks[kr.next + x], q);
+    if (!FIRST) {
+      s0 = add_mod(s0, o0[x], q);
+      s1 = add_mod(s1, o1[x], q);
+    }
+    if (OWN) {
+      const u64 d = d2e[x];
+      s0 = add_mod(s0, mul_shoup(d, kr.ok[x], kr.oks[x], q), q);
+      s1 = add_mod(s1, mul_shoup(d, kr.ok[kr.next + x], kr.oks[kr.next + x], q), q);
+    }
+    if (KEEP0) v[r] = ar.in(s0);
+    else o0[x] = s0;
+    o1[x] = s1;
+    group_fence<4>(r);
+  }
+}
+
+// step IT of the digit loop of k2_body, unrolled at compile time
+template <int IT, int NT, bool SPECIAL, typename Ar>
+__device__ __forceinline__ void k2_steps(const Ar& ar, typename Ar::Val (&v)[32], typename Ar::Val* sh, const Ks14Args& a,
+                                         const int (&js)[NT], int b, int e, int ne, int re, int nb, int64_t okrow,
+                                         const u64* d2e, u64* o0, u64* o1, u64 q, int t) {
+  if constexpr (IT < NT) {
+    const int j = js[IT];
+    load_a(ar, v, a.ext + ((int64_t)b * a.next + ext_slot(a.mu, ne, j, e)) * kN, t);
+    n14::forward(ar, v, sh, t);
+    const int64_t krow = ((int64_t)j * 2 * nb + re) * kN;   // rlk_j,0[re]; rlk_j,1[re] is nb rows further
+    const KeyRows kr{a.rlk + krow, a.rlk_s + krow, a.rlk + okrow, a.rlk_s + okrow, (int64_t)nb * kN};
+    k2_products<IT == 0, !SPECIAL && IT == NT - 1, SPECIAL && IT == NT - 1>(ar, v, kr, d2e, o0, o1, q, t);
+    k2_steps<IT + 1, NT, SPECIAL>(ar, v, sh, a, js, b, e, ne, re, nb, okrow, d2e, o0, o1, q, t);
+  }
+}
+
+// The NT digits needing a transform (those not holding prime e) are taken
+// one at a time; each adds its key products into the destination rows (accQ
+// for a data prime, part for a special one), the same words the same thread
+// wrote before, so no synchronisation is needed.  The digit holding a data
+// prime e needs no transform and is folded into the last pass.  For a special
+// prime the last pass keeps acc_0 in registers for the inverse transform.  NT
+// is a template argument so that no transform sits inside a run-time loop.
+template <int NT, bool SPECIAL, typename Ar>
+__device__ __forceinline__ void k2_body(const Ks14Args& a, const DevParams& dp, int b, int e, void* lds) {
+  typedef typename Ar::Val Val;
+  Val* sh = reinterpret_cast<Val*>(lds);
+  const int t = threadIdx.x, nb = dp.nb, ne = a.nl + dp.alpha;
+  const int re = a.mu[0].basis[e];
+  const PrimeDev& P = dp.pr[re];
+  const u64 q = P.q;
+  const int k = e - a.nl;
+  u64* o0 = SPECIAL ? a.part + (((int64_t)b * dp.alpha + k) * 2 + 0) * kN
+                    : a.accQ + (((int64_t)b * 2 + 0) * a.nl + e) * kN;
+  u64* o1 = SPECIAL ? a.part + (((int64_t)b * dp.alpha + k) * 2 + 1) * kN
+                    : a.accQ + (((int64_t)b * 2 + 1) * a.nl + e) * kN;
+  int js[NT];
+  int own = 0, n = 0;
+  for (int j = 0; j < dp.dnum; ++j) {
+    const ModUpConst& mc = a.mu[j];
+    if (mc.lo >= mc.hi) break;
+    if (re >= mc.lo && re < mc.hi) own = j;
+    else if (n < NT) js[n++] = j;
+  }
+  const int64_t okrow = ((int64_t)own * 2 * nb + re) * kN;
+  const u64* d2e = a.D + (int64_t)b * a.dw + (int64_t)(2 * a.nl + (SPECIAL ? 0 : re)) * kN;
+  const Ar ar(P, false);
+  Val v[32];
+  k2_steps<0, NT, SPECIAL>(ar, v, sh, a, js, b, e, ne, re, nb, okrow, d2e, o0, o1, q, t);
+  if (!SPECIAL) return;
+  // special prime p_k: both sums back to coefficients, times (P/p_k)^-1 N^-1
+  const Ar ai(P, true);
+  const u64 w = a.md->pinv_n[k], ws = a.md->pinv_n_s[k];
+  n14::inverse(ai, v, sh, t);
+  u64* y0 = a.yP + (((int64_t)b * 2 + 0) * dp.alpha + k) * kN;
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    y0[pos_a(t, u)] = ai.out_mul(v[u], w, ws);
+    group_fence<8>(u);
+  }
+  load_c(ai, v, o1, t);
+  n14::inverse(ai, v, sh, t);
+  u64* y1 = a.yP + (((int64_t)b * 2 + 1) * dp.alpha + k) * kN;
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    y1[pos_a(t, u)] = ai.out_mul(v[u], w, ws);
+    group_fence<8>(u);
+  }
+}
+
+// blocks (b, e): e over the special primes (SPECIAL) or the data primes
+template <int NT, bool SPECIAL>
+__global__ void __launch_bounds__(n14::kThreads, 4) ks14_k2_kernel(Ks14Args a, DevParams dp) {
+  extern __shared__ u64 lds[];
+  const int m = SPECIAL ? dp.alpha : a.nl;
+  const int b = blockIdx.x / m, f = blockIdx.x % m;
+  const int e = SPECIAL ? a.nl + f : f;
+  const int re = a.mu[0].basis[e];
+  if (dp.pr[re].q < (1ull << 42))
+    k2_body<NT, SPECIAL, NttFp>(a, dp, b, e, lds);
+  else
+    k2_body<NT, SPECIAL, NttInt>(a, dp, b, e, lds);
+}
+
+// a single digit holds every data prime: their key products need no transform
+__global__ void __launch_bounds__(256) ks14_k2own_kernel(Ks14Args a, DevParams dp) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int b = blockIdx.y / a.nl, e = blockIdx.y % a.nl;
+  const u64 q = dp.pr[e].q;
+  const int64_t nbN = (int64_t)dp.nb * kN;
+  const int64_t krow = (int64_t)e * kN + x;   // digit 0: rows rlk_0,p[e]
+  const u64 d = a.D[(int64_t)b * a.dw + (int64_t)(2 * a.nl + e) * kN + x];
+  a.accQ[(((int64_t)b * 2 + 0) * a.nl + e) * kN + x] = mul_shoup(d, a.rlk[krow], a.rlk_s[krow], q);
+  a.accQ[(((int64_t)b * 2 + 1) * a.nl + e) * kN + x] = mul_shoup(d, a.rlk[krow + nbN], a.rlk_s[krow + nbN], q);
+}
+
+// ---------------------------------------------------------------- K3a
+// z = sum_k yP_k [P/p_k]_{q_i} at one position (yb = yP rows of (b, p) at it)
+template <int ALPHA>
+__device__ __forceinline__ u64 moddown_z(const u64* yb, const ModDownConst* md, int i, u64 q) {
+  u64 z = 0;
+#pragma unroll
+  for (int k = 0; k < ALPHA; ++k) z = add_mod(z, mul_shoup(yb[(int64_t)k * kN], md->conv[k][i], md->conv_s[k][i], q), q);
+  return z;
+}
+
+// instantiated per alpha: a run-time trip count inside the unrolled
+// per-register code would keep the row's addresses live
+template <int ALPHA, typename Ar>
+__device__ __forceinline__ void k3a_body(const Ks14Args& a, const DevParams& dp, int b, int p, void* lds) {
+  typedef typename Ar::Val Val;
+  const int t = threadIdx.x, lev = a.lev;
+  const PrimeDev& P = dp.pr[lev];
+  const u64 q = P.q;
+  const Ar ar(P, true);
+  const u64 Pi = a.md->Pinv[lev], Pis = a.md->Pinv_s[lev];
+  const u64* acc = a.accQ + (((int64_t)b * 2 + p) * a.nl + lev) * kN;
+  const u64* d = a.D + (int64_t)b * a.dw + (int64_t)(p * a.nl + lev) * kN;
+  Val v[32];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) {
+    const int x = pos_c(t, r);
+    v[r] = ar.in(add_mod(mul_shoup(acc[x], Pi, Pis, q), d[x], q));
+    group_fence<8>(r);
+  }
+  n14::inverse(ar, v, reinterpret_cast<Val*>(lds), t);
+  const int tt = after(t, v[15], v[31]);
+  u64* o = a.r + ((int64_t)b * 2 + p) * kN;
+  const u64* yb = a.yP + ((int64_t)b * 2 + p) * ALPHA * kN;
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    const int x = pos_a(tt, u);
+    const u64 z = mul_shoup(moddown_z<ALPHA>(yb + x, a.md, lev, q), Pi, Pis, q);
+    o[x] = sub_mod(ar.out_inv(v[u], P), z, q);
+    group_fence<4>(u);
+  }
+}
+
+template <int ALPHA>
+__global__ void __launch_bounds__(n14::kThreads, 4) ks14_k3a_kernel(Ks14Args a, DevParams dp) {
+  extern __shared__ u64 lds[];
+  const int b = blockIdx.x >> 1, p = blockIdx.x & 1;
+  if (dp.pr[a.lev].q < (1ull << 42))
+    k3a_body<ALPHA, NttFp>(a, dp, b, p, lds);
+  else
+    k3a_body<ALPHA, NttInt>(a, dp, b, p, lds);
+}
+
+// ---------------------------------------------------------------- Lift
+// one position of one (output, poly) per thread; grid (N / 256, 2 n)
+template <int ALPHA>
+__global__ void __launch_bounds__(256) ks14_lift_kernel(Ks14Args a, DevParams dp) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int bp = blockIdx.y;                // b * 2 + p
+  const int lev = a.lev;
+  const u64 ql = dp.pr[lev].q;
+  const u64 c = a.r[(int64_t)bp * kN + x];
+  const i64 cl = c > (ql - 1) / 2 ? -(i64)(ql - c) : (i64)c;   // centered lift of the last prime
+  const u64* yb = a.yP + (int64_t)bp * ALPHA * kN + x;
+  u64 yk[ALPHA];
+#pragma unroll
+  for (int k = 0; k < ALPHA; ++k) yk[k] = yb[(int64_t)k * kN];
+  u64* wb = a.w + (int64_t)bp * lev * kN + x;
+  for (int i = 0; i < lev; ++i) {
+    const PrimeDev& P = dp.pr[i];
+    u64 z = 0;
+#pragma unroll
+    for (int k = 0; k < ALPHA; ++k) z = add_mod(z, mul_shoup(yk[k], a.md->conv[k][i], a.md->conv_s[k][i], P.q), P.q);
+    wb[(int64_t)i * kN] = add_mod(mul_shoup(z, a.md->Pinv[i], a.md->Pinv_s[i], P.q), signed_mod(cl, P), P.q);
+  }
+}
+
+// ---------------------------------------------------------------- K3b
+template <typename Ar>
+__device__ __forceinline__ void k3b_body(const Ks14Args& a, const DevParams& dp, const OutLayout& ol, int b, int p, int i,
+                                         void* lds) {
+  typedef typename Ar::Val Val;
+  const int t = threadIdx.x, lev = a.lev;
+  const PrimeDev& P = dp.pr[i];
+  const u64 q = P.q;
+  const Ar ar(P, false);
+  const u64 Pi = a.md->Pinv[i], Pis = a.md->Pinv_s[i];
+  Val v[32];
+  load_a(ar, v, a.w + (((int64_t)b * 2 + p) * lev + i) * kN, t);
+  n14::forward(ar, v, reinterpret_cast<Val*>(lds), t);
+  const u64* acc = a.accQ + (((int64_t)b * 2 + p) * a.nl + i) * kN;
+  const u64* d = a.D + (int64_t)b * a.dw + (int64_t)(p * a.nl + i) * kN;
+  const u64 qi = a.rs->qinv[i], qis = a.rs->qinv_s[i];
+  const int tt = after(t, v[15], v[31]);
+  // the two destination layouts in loops of their own (a select of the
+  // address inside one loop spills registers)
+  if (ol.chunked) {
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      const int x = pos_c(tt, r);
+      const u64 s = sub_mod(add_mod(mul_shoup(acc[x], Pi, Pis, q), d[x], q), ar.fwd_res(v[r]), q);
+      ol.base[chunk_index(ol.elem_base + b, p, i, x, ol.n_ct, kN >> 6)] = mul_shoup(s, qi, qis, q);
+      group_fence<4>(r);
+    }
+  } else {
+    u64* dst = ol.base + (int64_t)b * ol.stride + ((int64_t)p * lev + i) * kN;
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      const int x = pos_c(tt, r);
+      const u64 s = sub_mod(add_mod(mul_shoup(acc[x], Pi, Pis, q), d[x], q), ar.fwd_res(v[r]), q);
+      dst[x] = mul_shoup(s, qi, qis, q);
+      group_fence<4>(r);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(n14::kThreads, 4) ks14_k3b_kernel(Ks14Args a, OutLayout ol, DevParams dp) {
+  extern __shared__ u64 lds[];
+  const int lev = a.lev;
+  const int b = blockIdx.x / (2 * lev);
+  const int rem = blockIdx.x % (2 * lev);
+  const int p = rem / lev, i = rem % lev;
+  if (dp.pr[i].q < (1ull << 42))
+    k3b_body<NttFp>(a, dp, ol, b, p, i, lds);
+  else
+    k3b_body<NttInt>(a, dp, ol, b, p, i, lds);
+}
+
+template <int NT>
+int launch_k2(const sfhe_ctx* c, const Ks14Args& a, int64_t n, size_t lds, hipStream_t s) {
+  constexpr int NTD = NT > 1 ? NT - 1 : 1;   // transforms per data prime
+  static bool attr = false;
+  if (!attr) {
+    SFHE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&ks14_k2_kernel<NT, true>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    SFHE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&ks14_k2_kernel<NTD, false>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  const dim3 blk(n14::kThreads);
+  hipLaunchKernelGGL((ks14_k2_kernel<NT, true>), dim3((unsigned)(n * c->alpha)), blk, lds, s, a, c->dp);
+  SFHE_HIP(hipGetLastError());
+  if (NT > 1)
+    hipLaunchKernelGGL((ks14_k2_kernel<NTD, false>), dim3((unsigned)(n * a.nl)), blk, lds, s, a, c->dp);
+  else
+    hipLaunchKernelGGL(ks14_k2own_kernel, dim3(kN / 256, (unsigned)(n * a.nl)), dim3(256), 0, s, a, c->dp);
+  SFHE_HIP(hipGetLastError());
+  return SFHE_OK;
+}
+
+template <int ALPHA>
+int launch_ks14(sfhe_ctx* c, const Ks14Args& a, int ndig, OutLayout out, int64_t n, hipStream_t s) {
+  const size_t lds = (size_t)n14::kLdsWords * sizeof(u64);
+  static bool attr = false;
+  if (!attr) {
+    const void* fns[3] = {reinterpret_cast<const void*>(&ks14_k1_kernel),
+                          reinterpret_cast<const void*>(&ks14_k3a_kernel<ALPHA>),
+                          reinterpret_cast<const void*>(&ks14_k3b_kernel)};
+    for (const void* f : fns) SFHE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  const int lev = a.lev, nl = a.nl;
+  const dim3 blk(n14::kThreads);
+  hipLaunchKernelGGL(ks14_k1_kernel, dim3((unsigned)(n * nl)), blk, lds, s, a, c->dp);
+  SFHE_HIP(hipGetLastError());
+  hipLaunchKernelGGL(ks14_bconv_kernel, dim3(kN / 256, (unsigned)n), dim3(256), 0, s, a, c->dp);
+  SFHE_HIP(hipGetLastError());
+  int rc;
+  switch (ndig) {
+    case 1: rc = launch_k2<1>(c, a, n, lds, s); break;
+    case 2: rc = launch_k2<2>(c, a, n, lds, s); break;
+    case 3: rc = launch_k2<3>(c, a, n, lds, s); break;
+    default: rc = launch_k2<4>(c, a, n, lds, s); break;
+  }
+  if (rc) return rc;
+  hipLaunchKernelGGL(ks14_k3a_kernel<ALPHA>, dim3((unsigned)(n * 2)), blk, lds, s, a, c->dp);
+  SFHE_HIP(hipGetLastError());
+  hipLaunchKernelGGL(ks14_lift_kernel<ALPHA>, dim3(kN / 256, (unsigned)(n * 2)), dim3(256), 0, s, a, c->dp);
+  SFHE_HIP(hipGetLastError());
+  hipLaunchKernelGGL(ks14_k3b_kernel, dim3((unsigned)(n * 2 * lev)), blk, lds, s, a, out, c->dp);
+  SFHE_HIP(hipGetLastError());
+  return SFHE_OK;
+}
+
+}  // namespace
+
+bool keyswitch_rescale_n14_supported(const sfhe_ctx* c) {
+  return c->logN == n14::kLogN && c->alpha >= 1 && c->alpha <= 4 && c->dnum <= 4;
+}
+
+int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s) {
+  if (n <= 0) return SFHE_OK;
+  if (!keyswitch_rescale_n14_supported(c)) {
+    set_error("fused key switch: N = 2^14, 1 <= alpha <= 4 and dnum <= 4 only");
+    return SFHE_E_INVALID_ARG;
+  }
+  if (lev < 1) { set_error("rescale: level 0 has no prime to drop"); return SFHE_E_LEVEL; }
+  if (!c->d_rlk_s.ptr) { set_error("keygen first"); return SFHE_E_STATE; }
+  const int nl = lev + 1, ne = nl + c->alpha;
+  if (n * ne > 0x7FFFFFFF || n * std::max(2, nl) > 65535) {   // grid limits of the element-wise kernels
+    set_error("key switch: slice too large");
+    return SFHE_E_INVALID_ARG;
+  }
+  int next = 0, ndig = 0;
+  for (int j = 0; j < c->dnum; ++j) {
+    const int lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, nl);
+    if (lo >= hi) break;
+    next += ne - (hi - lo);
+    ++ndig;
+  }
+  DevBuf<u64> y, ext, accQ, part, yP, r, w;
+  if (!y.alloc(&c->alloc, (size_t)n * nl * kN) || !ext.alloc(&c->alloc, (size_t)n * next * kN) ||
+      !accQ.alloc(&c->alloc, (size_t)n * 2 * nl * kN) || !part.alloc(&c->alloc, (size_t)n * 2 * c->alpha * kN) ||
+      !yP.alloc(&c->alloc, (size_t)n * 2 * c->alpha * kN) || !r.alloc(&c->alloc, (size_t)n * 2 * kN) ||
+      !w.alloc(&c->alloc, (size_t)n * 2 * lev * kN)) {
+    set_error("key switch: device allocation failed");
+    return SFHE_E_NOMEM;
+  }
+  Ks14Args a;
+  a.D = D;
+  a.dw = dw;
+  a.y = y.ptr;
+  a.ext = ext.ptr;
+  a.next = next;
+  a.accQ = accQ.ptr;
+  a.part = part.ptr;
+  a.yP = yP.ptr;
+  a.r = r.ptr;
+  a.w = w.ptr;
+  a.rlk = c->d_rlk.ptr;
+  a.rlk_s = c->d_rlk_s.ptr;
+  a.mu = c->d_modup.ptr + (size_t)lev * c->dnum;
+  a.md = c->d_moddown.ptr + lev;
+  a.rs = c->d_rescale.ptr + lev;
+  a.lev = lev;
+  a.nl = nl;
+  a.n = (int)n;
+  switch (c->alpha) {
+    case 1: return launch_ks14<1>(c, a, ndig, out, n, s);
+    case 2: return launch_ks14<2>(c, a, ndig, out, n, s);
+    case 3: return launch_ks14<3>(c, a, ndig, out, n, s);
+    default: return launch_ks14<4>(c, a, ndig, out, n, s);
+  }
+}
+
+}  // namespace sfhe

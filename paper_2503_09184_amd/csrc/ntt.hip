@@ -1,6 +1,8 @@
 // ntt.hip -- batched negacyclic NTT / inverse NTT kernels (one workgroup
-// per row, the transform of ntt_core.hpp), and layout helpers.
-#include "ntt_core.hpp"
+// per row: the 32-residues-per-thread transform of ntt14.hpp for N = 2^14,
+// the radix-16 transform of ntt_core.hpp for smaller rings), and layout
+// helpers.
+#include "ntt14.hpp"
 
 namespace sfhe {
 
@@ -53,6 +55,46 @@ __global__ void __launch_bounds__(1024) ntt_kernel(NttRows R, DevParams dp) {
     ntt_row<INV, NttInt>(p, P, N, logN, lds);
 }
 
+
+// one row of 2^14 residues in place: coefficients in natural order, the NTT
+// domain in the register-major order of ntt14.hpp
+template <bool INV, typename Ar>
+__device__ __forceinline__ void ntt14_row(u64* p, const PrimeDev& P, void* lds) {
+  typedef typename Ar::Val Val;
+  Val* sh = reinterpret_cast<Val*>(lds);
+  const int t = threadIdx.x;
+  const Ar ar(P, INV);
+  Val v[32];
+  if (!INV) {
+    const u64* src = p + n14::xa(n14::opaque(t), 0);
+#pragma unroll
+    for (int u = 0; u < 32; ++u) v[u] = ar.in(src[n14::off_a(u)]);
+    n14::forward(ar, v, sh, t);
+#pragma unroll
+    for (int r = 0; r < 32; ++r) p[n14::pos_c(t, r)] = ar.out_fwd(v[r]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 32; ++r) v[r] = ar.in(p[n14::pos_c(t, r)]);
+    n14::inverse(ar, v, sh, t);
+    u64* dst = p + n14::xa(n14::opaque(t), 0);
+#pragma unroll
+    for (int u = 0; u < 32; ++u) dst[n14::off_a(u)] = ar.out_inv(v[u], P);
+  }
+}
+
+template <bool INV>
+__global__ void __launch_bounds__(n14::kThreads, 4) ntt14_kernel(NttRows R, DevParams dp) {
+  extern __shared__ u64 lds[];
+  const int64_t g = blockIdx.x / R.nrow;
+  const int r = blockIdx.x % R.nrow;
+  u64* p = R.base + g * R.bstride + (int64_t)R.pos[r] * n14::kN;
+  const PrimeDev& P = dp.pr[R.prime[r]];
+  if (P.q < (1ull << 42))
+    ntt14_row<INV, NttFp>(p, P, lds);
+  else
+    ntt14_row<INV, NttInt>(p, P, lds);
+}
+
 int launch_ntt(const sfhe_ctx* c, u64* base, int64_t batch, int64_t bstride, int nrow, const int* pos,
                const int* prime, bool inverse, hipStream_t s) {
   if (batch <= 0 || nrow <= 0) return SFHE_OK;
@@ -63,10 +105,27 @@ int launch_ntt(const sfhe_ctx* c, u64* base, int64_t batch, int64_t bstride, int
   R.nrow = nrow;
   for (int i = 0; i < kMaxRows; ++i) { R.pos[i] = i < nrow ? pos[i] : 0; R.prime[i] = i < nrow ? prime[i] : 0; }
   const int N = c->N;
-  const int threads = N / 16 < 1024 ? N / 16 : 1024;
-  const size_t lds = (size_t)(N + (N >> kPadShift)) * sizeof(u64);
   const int64_t blocks = batch * nrow;
   if (blocks > 0x7FFFFFFF) { set_error("ntt: batch too large"); return SFHE_E_INVALID_ARG; }
+  if (c->logN == n14::kLogN) {
+    static bool attr14 = false;
+    if (!attr14) {
+      SFHE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&ntt14_kernel<false>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, n14::kLdsWords * 8));
+      SFHE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&ntt14_kernel<true>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, n14::kLdsWords * 8));
+      attr14 = true;
+    }
+    const size_t lds = (size_t)n14::kLdsWords * sizeof(u64);
+    if (inverse)
+      hipLaunchKernelGGL(ntt14_kernel<true>, dim3((unsigned)blocks), dim3(n14::kThreads), lds, s, R, c->dp);
+    else
+      hipLaunchKernelGGL(ntt14_kernel<false>, dim3((unsigned)blocks), dim3(n14::kThreads), lds, s, R, c->dp);
+    SFHE_HIP(hipGetLastError());
+    return SFHE_OK;
+  }
+  const int threads = N / 16 < 1024 ? N / 16 : 1024;
+  const size_t lds = (size_t)(N + (N >> kPadShift)) * sizeof(u64);
   static bool attr_done[2] = {false, false};
   if (!attr_done[inverse ? 1 : 0]) {
     const void* fn = inverse ? reinterpret_cast<const void*>(&ntt_kernel<true>)

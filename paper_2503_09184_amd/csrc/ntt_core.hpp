@@ -80,6 +80,12 @@ struct NttInt {
     const u64 v = mul_shoup_lazy(x, P.ninv, P.ninv_s, q);
     return v >= q ? v - q : v;
   }
+  // inverse output times a constant w in [0, q) (Shoup companion ws) that
+  // already holds N^-1
+  __device__ u64 out_mul(Val x, u64 w, u64 ws) const {
+    const u64 v = mul_shoup_lazy(x, w, ws, q);
+    return v >= q ? v - q : v;
+  }
 };
 
 struct NttFp {
@@ -106,6 +112,7 @@ struct NttFp {
   __device__ u64 out_inv(Val x, const PrimeDev& P) const {
     return fp_to_residue(fmm(x, (double)P.ninv, q, qinv), q, qinv);
   }
+  __device__ u64 out_mul(Val x, u64 w, u64) const { return fp_to_residue(fmm(x, (double)w, q, qinv), q, qinv); }
 };
 
 // one forward pass of P stages s0 .. s0+P-1 over all units of this thread;

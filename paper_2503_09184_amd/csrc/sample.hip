@@ -8,6 +8,7 @@
 // switching.  Randomness is drawn from counter-based SplitMix64 streams keyed
 // by (seed, tag, fields), sampled in the coefficient domain.
 #include "internal.hpp"
+#include "hostmath.hpp"
 
 namespace sfhe {
 
@@ -175,6 +176,14 @@ int keygen_device(sfhe_ctx* c, u64 seed, hipStream_t s) {
                      d_gad.ptr, c->dp);
   SFHE_HIP(hipGetLastError());
   SFHE_HIP(hipStreamSynchronize(s));
+  // Shoup companions floor(k 2^64 / q) of every key word, for the key
+  // products of the fused key switch (computed once, on the host)
+  const size_t nk = (size_t)dnum * 2 * nb * N;
+  std::vector<u64> key(nk);
+  SFHE_HIP(hipMemcpy(key.data(), c->d_rlk.ptr, nk * sizeof(u64), hipMemcpyDeviceToHost));
+  for (size_t w = 0; w < nk; ++w) key[w] = hostmath::shoup(key[w], c->primes[(w / N) % nb]);
+  if (!c->d_rlk_s.alloc(&c->alloc, nk)) { set_error("keygen: device allocation failed"); return SFHE_E_NOMEM; }
+  SFHE_HIP(hipMemcpy(c->d_rlk_s.ptr, key.data(), nk * sizeof(u64), hipMemcpyHostToDevice));
   return SFHE_OK;
 }
 
