@@ -188,7 +188,8 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   __shared__ int s_ek[kSegEntries], s_em[kSegEntries];
   __shared__ int s_es[kSegEntries][kTileRows];
   const int N = dp.N, L = dp.L;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: row and column choices are scalar
   // block b: XCD-aware order.  b mod 8 picks the 64-coefficient chunk of a
   // 512-coefficient slab, so one XCD works on one chunk; above that the row
   // tile varies fastest, then the column tile, then the slab: the row tiles
@@ -231,11 +232,13 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   };
   // the tile's entry list goes through LDS in segments, so that the loads two
   // entries ahead need no scalar memory round trip
+  // entry metadata is the same for every lane: read it into scalar registers
+  // so that the row tests below are scalar branches, not lane masks
   auto fetch = [&](int x, int xend, Stage& st) {
     st.mask = 0;
     if (x >= xend) return;
-    const int k = s_ek[x];
-    st.mask = s_em[x];
+    const int k = __builtin_amdgcn_readfirstlane(s_ek[x]);
+    st.mask = __builtin_amdgcn_readfirstlane(s_em[x]);
     st.b0 = st.b1 = 0;
     if (j < Nc && ((st.mask >> rbase) & ((1 << RPW) - 1))) {
       const u64* bp = Bb + ((int64_t)k * Nc + j) * 64;
@@ -243,12 +246,12 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
       st.b1 = bp[pB];
     }
     if ((st.mask >> arow0) & 1) {
-      const u64* ap = Ab + (int64_t)s_es[x][arow0] * 64;
+      const u64* ap = Ab + (int64_t)__builtin_amdgcn_readfirstlane(s_es[x][arow0]) * 64;
       st.a00 = ap[0];
       st.a01 = ap[pA];
     }
     if ((st.mask >> arow1) & 1) {
-      const u64* ap = Ab + (int64_t)s_es[x][arow1] * 64;
+      const u64* ap = Ab + (int64_t)__builtin_amdgcn_readfirstlane(s_es[x][arow1]) * 64;
       st.a10 = ap[0];
       st.a11 = ap[pA];
     }
@@ -263,17 +266,23 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
       sa[bf][arow1][1][lane] = Arith::load(st.a11);
     }
   };
+  // the A values of all RPW rows are read from LDS before any multiply, so
+  // their latency is paid once per entry; a row not visiting k reads a stale
+  // word that is never used
   auto compute = [&](const Stage& st, int bf) {
     const int wmask = (st.mask >> rbase) & ((1 << RPW) - 1);
     if (!wmask) return;
     const Val b0 = Arith::load(st.b0), b1 = Arith::load(st.b1);
     const Val bs = Arith::sum(b0, b1);
+    Val a0[RPW], a1[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
-      if (wmask & (1 << r)) {
-        const Val a0 = sa[bf][rbase + r][0][lane], a1 = sa[bf][rbase + r][1][lane];
-        ar.mac(acc[r], a0, a1, Arith::sum(a0, a1), b0, b1, bs);
-      }
+      a0[r] = sa[bf][rbase + r][0][lane];
+      a1[r] = sa[bf][rbase + r][1][lane];
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      if (wmask & (1 << r)) ar.mac(acc[r], a0[r], a1[r], Arith::sum(a0[r], a1[r]), b0, b1, bs);
     }
   };
   int cnt = 0;
