@@ -9,8 +9,8 @@
 //
 //  K1 (b, i)    y_i = [iNTT(d2_i) (D_j/q_i)^-1]_{q_i}: ModUp's pre-scale,
 //               with N^-1 folded into the constant.
-//  BConv (b, x) ext_{j,e} = sum_{i in D_j} y_i [D_j/q_i]_e for every digit j
-//               and every prime e outside it (element-wise).
+//  BConv (b, j, e, x)  ext_{j,e} = sum_{i in D_j} y_i [D_j/q_i]_e for every
+//               digit j and every prime e outside it (element-wise).
 //  K2 (b, e)    x_j = NTT(ext_{j,e}) for the digits j not holding e, and the
 //               key products acc_p = sum_j x_j rlk_j,p[e] (+ d2_e rlk_own,p[e]
 //               when e is a data prime of digit own).  Data prime: acc_p is
@@ -19,7 +19,7 @@
 //  K3a (b, p)   the last prime of the key-switched sum, in coefficients:
 //               r = iNTT(acc_lev P^-1 + d_lev) - z_lev P^-1 with
 //               z_i = sum_k yP_k [P/p_k]_{q_i}.
-//  Lift (b, p, x)  w_i = z_i P^-1 + [centered r]_{q_i} for i < lev
+//  Lift (b, p, i, x)  w_i = z_i P^-1 + [centered r]_{q_i} for i < lev
 //               (element-wise).
 //  K3b (b, p, i), i < lev:  C_i = (acc_i P^-1 + d_i - NTT(w_i)) q_lev^-1.
 //
@@ -121,27 +121,37 @@ __global__ void __launch_bounds__(n14::kThreads, 4) ks14_k1_kernel(Ks14Args a, D
 }
 
 // ---------------------------------------------------------------- BConv
-// one position of one output per thread; grid (N / 256, n)
-__global__ void __launch_bounds__(256) ks14_bconv_kernel(Ks14Args a, DevParams dp) {
-  const int x = blockIdx.x * 256 + threadIdx.x;
-  const int b = blockIdx.y;
+// Element-wise kernels take kEwPer positions per thread (strided by the
+// block size), so that the per-block scalar set-up is amortised and each
+// thread has kEwPer independent loads in flight.
+constexpr int kEwThreads = 256, kEwPer = 8, kEwSpan = kEwThreads * kEwPer;
+
+// grid (N / kEwSpan, n * next): block row (b, slot), slot enumerating
+// (digit j, position e outside j) as ext_slot does
+__global__ void __launch_bounds__(kEwThreads) ks14_bconv_kernel(Ks14Args a, DevParams dp) {
+  const int x0 = blockIdx.x * kEwSpan + threadIdx.x;
+  const int b = blockIdx.y / a.next, slot = blockIdx.y % a.next;
   const int ne = a.nl + dp.alpha;
-  const u64* yb = a.y + (int64_t)b * a.nl * kN + x;
-  u64* eb = a.ext + (int64_t)b * a.next * kN + x;
-  int slot = 0;
-  for (int j = 0; j < dp.dnum; ++j) {
-    const ModUpConst& mc = a.mu[j];
-    if (mc.lo >= mc.hi) break;
-    for (int e = 0; e < ne; ++e) {
-      if (e >= mc.lo && e < mc.hi) continue;
-      const u64 q = dp.pr[mc.basis[e]].q;
-      u64 s = 0;
-      for (int i = mc.lo; i < mc.hi; ++i)
-        s = add_mod(s, mul_shoup(yb[(int64_t)i * kN], mc.conv[i - mc.lo][e], mc.conv_s[i - mc.lo][e], q), q);
-      eb[(int64_t)slot * kN] = s;
-      ++slot;
-    }
+  int j = 0, rem = slot;
+  while (rem >= ne - (a.mu[j].hi - a.mu[j].lo)) {
+    rem -= ne - (a.mu[j].hi - a.mu[j].lo);
+    ++j;
   }
+  const ModUpConst& mc = a.mu[j];
+  const int e = rem < mc.lo ? rem : rem + (mc.hi - mc.lo);
+  const u64 q = dp.pr[mc.basis[e]].q;
+  const u64* yb = a.y + (int64_t)b * a.nl * kN + x0;
+  u64 s[kEwPer];
+#pragma unroll
+  for (int m = 0; m < kEwPer; ++m) s[m] = 0;
+  for (int i = mc.lo; i < mc.hi; ++i) {
+    const u64 c = mc.conv[i - mc.lo][e], cs = mc.conv_s[i - mc.lo][e];
+#pragma unroll
+    for (int m = 0; m < kEwPer; ++m) s[m] = add_mod(s[m], mul_shoup(yb[(int64_t)i * kN + m * kEwThreads], c, cs, q), q);
+  }
+  u64* o = a.ext + ((int64_t)b * a.next + slot) * kN + x0;
+#pragma unroll
+  for (int m = 0; m < kEwPer; ++m) o[m * kEwThreads] = s[m];
 }
 
 // ---------------------------------------------------------------- K2
@@ -330,26 +340,37 @@ __global__ void __launch_bounds__(n14::kThreads, 4) ks14_k3a_kernel(Ks14Args a, 
 }
 
 // ---------------------------------------------------------------- Lift
-// one position of one (output, poly) per thread; grid (N / 256, 2 n)
+// grid (N / kEwSpan, 2 n lev): block row (b * 2 + p) * lev + i
 template <int ALPHA>
-__global__ void __launch_bounds__(256) ks14_lift_kernel(Ks14Args a, DevParams dp) {
-  const int x = blockIdx.x * 256 + threadIdx.x;
-  const int bp = blockIdx.y;                // b * 2 + p
+__global__ void __launch_bounds__(kEwThreads) ks14_lift_kernel(Ks14Args a, DevParams dp) {
+  const int x0 = blockIdx.x * kEwSpan + threadIdx.x;
   const int lev = a.lev;
+  const int bp = blockIdx.y / lev, i = blockIdx.y % lev;   // bp = b * 2 + p
   const u64 ql = dp.pr[lev].q;
-  const u64 c = a.r[(int64_t)bp * kN + x];
-  const i64 cl = c > (ql - 1) / 2 ? -(i64)(ql - c) : (i64)c;   // centered lift of the last prime
-  const u64* yb = a.yP + (int64_t)bp * ALPHA * kN + x;
-  u64 yk[ALPHA];
+  const PrimeDev& P = dp.pr[i];
+  const u64 q = P.q;
+  const u64 Pi = a.md->Pinv[i], Pis = a.md->Pinv_s[i];
+  u64 cv[ALPHA], cs[ALPHA];
 #pragma unroll
-  for (int k = 0; k < ALPHA; ++k) yk[k] = yb[(int64_t)k * kN];
-  u64* wb = a.w + (int64_t)bp * lev * kN + x;
-  for (int i = 0; i < lev; ++i) {
-    const PrimeDev& P = dp.pr[i];
+  for (int k = 0; k < ALPHA; ++k) {
+    cv[k] = a.md->conv[k][i];
+    cs[k] = a.md->conv_s[k][i];
+  }
+  const u64* yb = a.yP + (int64_t)bp * ALPHA * kN + x0;
+  const u64* rb = a.r + (int64_t)bp * kN + x0;
+  u64* o = a.w + (int64_t)blockIdx.y * kN + x0;
+#pragma unroll
+  for (int m = 0; m < kEwPer; ++m) {
     u64 z = 0;
 #pragma unroll
-    for (int k = 0; k < ALPHA; ++k) z = add_mod(z, mul_shoup(yk[k], a.md->conv[k][i], a.md->conv_s[k][i], P.q), P.q);
-    wb[(int64_t)i * kN] = add_mod(mul_shoup(z, a.md->Pinv[i], a.md->Pinv_s[i], P.q), signed_mod(cl, P), P.q);
+    for (int k = 0; k < ALPHA; ++k) z = add_mod(z, mul_shoup(yb[(int64_t)k * kN + m * kEwThreads], cv[k], cs[k], q), q);
+    // centered lift of the last prime, reduced mod q_i
+    const u64 c = rb[m * kEwThreads];
+    const bool neg = c > (ql - 1) / 2;
+    const u64 mag = neg ? ql - c : c;
+    u64 r = mag < q ? mag : reduce_wide(U128{mag, 0}, q, P.mu_hi, P.mu_lo);
+    r = (neg && r) ? q - r : r;
+    o[m * kEwThreads] = add_mod(mul_shoup(z, Pi, Pis, q), r, q);
   }
 }
 
@@ -441,7 +462,7 @@ int launch_ks14(sfhe_ctx* c, const Ks14Args& a, int ndig, OutLayout out, int64_t
   const dim3 blk(n14::kThreads);
   hipLaunchKernelGGL(ks14_k1_kernel, dim3((unsigned)(n * nl)), blk, lds, s, a, c->dp);
   SFHE_HIP(hipGetLastError());
-  hipLaunchKernelGGL(ks14_bconv_kernel, dim3(kN / 256, (unsigned)n), dim3(256), 0, s, a, c->dp);
+  hipLaunchKernelGGL(ks14_bconv_kernel, dim3(kN / kEwSpan, (unsigned)(n * a.next)), dim3(kEwThreads), 0, s, a, c->dp);
   SFHE_HIP(hipGetLastError());
   int rc;
   switch (ndig) {
@@ -453,7 +474,8 @@ int launch_ks14(sfhe_ctx* c, const Ks14Args& a, int ndig, OutLayout out, int64_t
   if (rc) return rc;
   hipLaunchKernelGGL(ks14_k3a_kernel<ALPHA>, dim3((unsigned)(n * 2)), blk, lds, s, a, c->dp);
   SFHE_HIP(hipGetLastError());
-  hipLaunchKernelGGL(ks14_lift_kernel<ALPHA>, dim3(kN / 256, (unsigned)(n * 2)), dim3(256), 0, s, a, c->dp);
+  hipLaunchKernelGGL(ks14_lift_kernel<ALPHA>, dim3(kN / kEwSpan, (unsigned)(n * 2 * lev)), dim3(kEwThreads), 0, s, a,
+                     c->dp);
   SFHE_HIP(hipGetLastError());
   hipLaunchKernelGGL(ks14_k3b_kernel, dim3((unsigned)(n * 2 * lev)), blk, lds, s, a, out, c->dp);
   SFHE_HIP(hipGetLastError());
@@ -475,16 +497,17 @@ int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLay
   if (lev < 1) { set_error("rescale: level 0 has no prime to drop"); return SFHE_E_LEVEL; }
   if (!c->d_rlk_s.ptr) { set_error("keygen first"); return SFHE_E_STATE; }
   const int nl = lev + 1, ne = nl + c->alpha;
-  if (n * ne > 0x7FFFFFFF || n * std::max(2, nl) > 65535) {   // grid limits of the element-wise kernels
-    set_error("key switch: slice too large");
-    return SFHE_E_INVALID_ARG;
-  }
   int next = 0, ndig = 0;
   for (int j = 0; j < c->dnum; ++j) {
     const int lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, nl);
     if (lo >= hi) break;
     next += ne - (hi - lo);
     ++ndig;
+  }
+  // grid limits of the element-wise kernels (rows in y)
+  if (n * ne > 0x7FFFFFFF || n * std::max(std::max(next, 2 * lev), nl) > 65535) {
+    set_error("key switch: slice too large");
+    return SFHE_E_INVALID_ARG;
   }
   DevBuf<u64> y, ext, accQ, part, yP, r, w;
   if (!y.alloc(&c->alloc, (size_t)n * nl * kN) || !ext.alloc(&c->alloc, (size_t)n * next * kN) ||
