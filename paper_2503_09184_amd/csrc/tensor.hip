@@ -130,42 +130,43 @@ struct ArithFp {   // q < 2^42: fp64 residues, Karatsuba middle term
   }
 };
 
-// a*b added to a 128-bit sum from four 32x32 -> 64 products
+// a*b added to a 128-bit sum, for a, b < 2^62: four 32x32 -> 64 multiply-adds
+// (the high halves are below 2^30, so every partial sum stays below 2^64)
 __device__ __forceinline__ void mac_wide(U128& acc, u64 a, u64 b) {
   const u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
-  const u64 p00 = (u64)a0 * b0, p01 = (u64)a0 * b1, p10 = (u64)a1 * b0, p11 = (u64)a1 * b1;
-  const u64 mid = (p00 >> 32) + (u64)(u32)p01 + (u64)(u32)p10;
-  const u64 lo = (mid << 32) | (u64)(u32)p00;
-  const u64 hi = p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+  const u64 p00 = (u64)a0 * b0;
+  const u64 t = (u64)a1 * b0 + ((u64)a0 * b1 + (p00 >> 32));
+  const u64 lo = (t << 32) | (p00 & 0xffffffffull);
+  const u64 hi = (u64)a1 * b1 + (t >> 32);
   add_wide(acc, U128{lo, hi});
 }
 
-struct ArithInt {   // any q < 2^62: 128-bit integer sums
+struct ArithInt {   // q < 2^61: 128-bit integer sums, Karatsuba middle term
   typedef u64 Val;
   struct Acc {
-    U128 d0, d1, d2;
+    U128 d0, d2, ss;   // sums of a0 b0, a1 b1, (a0 + a1)(b0 + b1)
   };
   u64 q, mu_hi, mu_lo;
   __device__ ArithInt(const FpLimb&, const PrimeDev& P) : q(P.q), mu_hi(P.mu_hi), mu_lo(P.mu_lo) {}
   __device__ static Val load(u64 x) { return x; }
-  __device__ static void zero(Acc& a) { a.d0 = a.d1 = a.d2 = U128{0, 0}; }
-  __device__ static Val sum(Val, Val) { return 0; }
-  __device__ void mac(Acc& a, Val a0, Val a1, Val, Val b0, Val b1, Val) const {
+  __device__ static void zero(Acc& a) { a.d0 = a.d2 = a.ss = U128{0, 0}; }
+  __device__ static Val sum(Val x, Val y) { return x + y; }   // < 2^62
+  __device__ void mac(Acc& a, Val a0, Val a1, Val as, Val b0, Val b1, Val bs) const {
     mac_wide(a.d0, a0, b0);
-    mac_wide(a.d1, a0, b1);
-    mac_wide(a.d1, a1, b0);
     mac_wide(a.d2, a1, b1);
+    mac_wide(a.ss, as, bs);
   }
-  static constexpr int kFold = 32;     // 64 terms below 2^122 stay below 2^128
+  static constexpr int kFold = 16;     // 16 terms below 2^124 (plus a residue) stay below 2^128
   __device__ void fold(Acc& a) const {
     a.d0 = U128{reduce_wide(a.d0, q, mu_hi, mu_lo), 0};
-    a.d1 = U128{reduce_wide(a.d1, q, mu_hi, mu_lo), 0};
     a.d2 = U128{reduce_wide(a.d2, q, mu_hi, mu_lo), 0};
+    a.ss = U128{reduce_wide(a.ss, q, mu_hi, mu_lo), 0};
   }
+  // d1 = (a0 + a1)(b0 + b1) - a0 b0 - a1 b1, formed once per output
   __device__ void final(const Acc& a, u64& d0, u64& d1, u64& d2) const {
     d0 = reduce_wide(a.d0, q, mu_hi, mu_lo);
-    d1 = reduce_wide(a.d1, q, mu_hi, mu_lo);
     d2 = reduce_wide(a.d2, q, mu_hi, mu_lo);
+    d1 = sub_mod(sub_mod(reduce_wide(a.ss, q, mu_hi, mu_lo), d0, q), d2, q);
   }
 };
 
