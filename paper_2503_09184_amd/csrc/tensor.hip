@@ -186,8 +186,8 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   constexpr int kHalves = kTileRows / RPW;
   constexpr int kCols = kWavesPerBlock / kHalves;
   __shared__ Val sa[2][kTileRows][2][64];
-  __shared__ int s_ek[kSegEntries], s_em[kSegEntries];
-  __shared__ int s_es[kSegEntries][kTileRows];
+  __shared__ int2 s_km[kSegEntries];               // (k, row mask) per entry
+  __shared__ int s_es[kSegEntries][kTileRows];     // A slot per entry and row
   const int N = dp.N, L = dp.L;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: row and column choices are scalar
@@ -238,8 +238,10 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   auto fetch = [&](int x, int xend, Stage& st) {
     st.mask = 0;
     if (x >= xend) return;
-    const int k = __builtin_amdgcn_readfirstlane(s_ek[x]);
-    st.mask = __builtin_amdgcn_readfirstlane(s_em[x]);
+    const int2 km = s_km[x];
+    const int2 sl = *reinterpret_cast<const int2*>(&s_es[x][arow0]);   // slots of rows arow0, arow0 + 1
+    const int k = __builtin_amdgcn_readfirstlane(km.x);
+    st.mask = __builtin_amdgcn_readfirstlane(km.y);
     st.b0 = st.b1 = 0;
     if (j < Nc && ((st.mask >> rbase) & ((1 << RPW) - 1))) {
       const u64* bp = Bb + ((int64_t)k * Nc + j) * 64;
@@ -247,12 +249,12 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
       st.b1 = bp[pB];
     }
     if ((st.mask >> arow0) & 1) {
-      const u64* ap = Ab + (int64_t)__builtin_amdgcn_readfirstlane(s_es[x][arow0]) * 64;
+      const u64* ap = Ab + (int64_t)__builtin_amdgcn_readfirstlane(sl.x) * 64;
       st.a00 = ap[0];
       st.a01 = ap[pA];
     }
     if ((st.mask >> arow1) & 1) {
-      const u64* ap = Ab + (int64_t)__builtin_amdgcn_readfirstlane(s_es[x][arow1]) * 64;
+      const u64* ap = Ab + (int64_t)__builtin_amdgcn_readfirstlane(sl.y) * 64;
       st.a10 = ap[0];
       st.a11 = ap[pA];
     }
@@ -291,8 +293,7 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
     const int n = min(kSegEntries, e1 - sg);
     __syncthreads();   // the previous segment's entries are no longer read
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
-      s_ek[x] = tl.ek[sg + x];
-      s_em[x] = tl.emask[sg + x];
+      s_km[x] = make_int2(tl.ek[sg + x], tl.emask[sg + x]);
     }
     for (int x = threadIdx.x; x < n * kTileRows; x += blockDim.x) s_es[x / kTileRows][x % kTileRows] = tl.eslot[(int64_t)sg * kTileRows + x];
     __syncthreads();
