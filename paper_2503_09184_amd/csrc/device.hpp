@@ -96,6 +96,15 @@ __device__ __forceinline__ u64 signed_mod(i64 v, const PrimeDev& P) {
   return r == 0 ? 0 : P.q - r;
 }
 
+// Exact conversions between integers below 2^52 and fp64 through the
+// mantissa of 2^52: one integer op and one fp64 op each way.
+__device__ __forceinline__ double u52_to_f64(u64 x) {
+  return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 4503599627370496.0;
+}
+__device__ __forceinline__ u64 f64_to_u52(double r) {   // r an integer in [0, 2^52)
+  return (u64)__double_as_longlong(r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+}
+
 // ---------------------------------------------------------------- randomness
 // SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) used as a counter-based
 // generator: stream key k = mix(seed + (tag+1) G), then k = mix(k + (f+1) G)

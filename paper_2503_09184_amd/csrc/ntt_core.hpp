@@ -47,7 +47,7 @@ __device__ __forceinline__ u64 fp_to_residue(double x, double q, double qinv) {
   double r = fma(-k, q, x);
   r = r < 0.0 ? r + q : r;
   r = r >= q ? r - q : r;
-  return (u64)r;
+  return f64_to_u52(r);
 }
 
 struct NttInt {
@@ -93,7 +93,7 @@ struct NttFp {
   double q, qinv;
   const double* w;
   __device__ NttFp(const PrimeDev& P, bool inv) : q((double)P.q), qinv(1.0 / (double)P.q), w(inv ? P.itwd : P.twd) {}
-  __device__ Val in(u64 x) const { return (double)x; }
+  __device__ Val in(u64 x) const { return u52_to_f64(x); }   // x < q < 2^42
   __device__ void ct(Val& X, Val& Y, int idx) const {
     const double T = fmm(w[idx], Y, q, qinv);
     const double x = X;

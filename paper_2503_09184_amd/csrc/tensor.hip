@@ -80,7 +80,7 @@ __device__ __forceinline__ u64 fp_final(double x, double q, double qinv) {
   double r = fma(-k, q, x);
   r = r < 0.0 ? r + q : r;
   r = r >= q ? r - q : r;
-  return (u64)r;
+  return f64_to_u52(r);
 }
 // |x| < 2^53 exact integer -> congruent value of magnitude <= q / 2 + 1
 __device__ __forceinline__ double fp_fold(double x, double q, double qinv) { return fma(-rint(x * qinv), q, x); }
@@ -106,7 +106,7 @@ struct ArithFp {   // q < 2^42: fp64 residues, Karatsuba middle term
   };
   double q, qinv;
   __device__ ArithFp(const FpLimb& F, const PrimeDev&) : q(F.q), qinv(F.qinv) {}
-  __device__ static Val load(u64 x) { return (double)x; }
+  __device__ static Val load(u64 x) { return u52_to_f64(x); }   // x < q < 2^42
   __device__ static void zero(Acc& a) { a.d0 = a.d2 = a.ss = 0.0; }
   __device__ static Val sum(Val x, Val y) { return x + y; }
   __device__ void mac(Acc& a, Val a0, Val a1, Val as, Val b0, Val b1, Val bs) const {
