@@ -172,12 +172,12 @@ struct ArithInt {   // q < 2^61: 128-bit integer sums, Karatsuba middle term
 
 // Block kernel: 8 waves share one 64-coefficient chunk of one prime and a
 // tile of kTileRows output rows.  Wave w owns output column h * kCols + w %
-// kCols for RPW rows: with RPW = kTileRows every wave sees the same rows, so
-// the work per visited k is identical across waves and the barrier costs no
-// imbalance; RPW = kTileRows / 2 splits the rows into two halves for the
-// 128-bit arithmetic's register budget.  Per visited k, the A values of the
-// tile rows that visit it are staged once through LDS (double-buffered) and
-// used by every column; each wave loads its own B[k, column] directly.
+// kCols for RPW rows (kTileRows / RPW groups of rows, so that the
+// accumulators fit the register budget).  Per visited k, the A values of the
+// tile rows that visit it and the B values of the block's kCols columns are
+// staged once through LDS (double-buffered): each wave loads two A rows and
+// one B row (a column's poly), and every wave reads what it needs from LDS,
+// so each operand word is loaded from memory once per block and entry.
 // Global loads run two entries ahead of the multiplies.
 template <typename Arith, int RPW>
 __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const u64* A, const u64* B, u64* D,
@@ -186,6 +186,7 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   constexpr int kHalves = kTileRows / RPW;
   constexpr int kCols = kWavesPerBlock / kHalves;
   __shared__ Val sa[2][kTileRows][2][64];
+  __shared__ Val sb[2][kCols][2][64];              // B of the block's columns for the entry
   __shared__ int2 s_km[kSegEntries];               // (k, row mask) per entry
   __shared__ int s_es[kSegEntries][kTileRows];     // A slot per entry and row
   const int N = dp.N, L = dp.L;
@@ -222,13 +223,17 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   const int j = h * kCols + (wave % kCols);
   const int rbase = half * RPW;
   const int arow0 = 2 * wave, arow1 = 2 * wave + 1;   // the rows this wave stages
+  // and the B row (column wave / 2 of the block, poly wave % 2) it stages
+  const bool bload = wave < 2 * kCols;
+  const int jb = h * kCols + (wave >> 1);
+  const int64_t pb_off = (wave & 1) ? pB : 0;
   typename Arith::Acc acc[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; ++r) Arith::zero(acc[r]);
 
   const int e0 = tl.tstart[g], e1 = tl.tstart[g + 1];
   struct Stage {
-    u64 b0, b1, a00, a01, a10, a11;
+    u64 b, a00, a01, a10, a11;
     int mask;
   };
   // the tile's entry list goes through LDS in segments, so that the loads two
@@ -242,12 +247,8 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
     const int2 sl = *reinterpret_cast<const int2*>(&s_es[x][arow0]);   // slots of rows arow0, arow0 + 1
     const int k = __builtin_amdgcn_readfirstlane(km.x);
     st.mask = __builtin_amdgcn_readfirstlane(km.y);
-    st.b0 = st.b1 = 0;
-    if (j < Nc && ((st.mask >> rbase) & ((1 << RPW) - 1))) {
-      const u64* bp = Bb + ((int64_t)k * Nc + j) * 64;
-      st.b0 = bp[0];
-      st.b1 = bp[pB];
-    }
+    st.b = 0;
+    if (bload && jb < Nc) st.b = Bb[((int64_t)k * Nc + jb) * 64 + pb_off];
     if ((st.mask >> arow0) & 1) {
       const u64* ap = Ab + (int64_t)__builtin_amdgcn_readfirstlane(sl.x) * 64;
       st.a00 = ap[0];
@@ -260,6 +261,7 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
     }
   };
   auto put = [&](const Stage& st, int bf) {
+    if (bload) sb[bf][wave >> 1][wave & 1][lane] = Arith::load(st.b);
     if ((st.mask >> arow0) & 1) {
       sa[bf][arow0][0][lane] = Arith::load(st.a00);
       sa[bf][arow0][1][lane] = Arith::load(st.a01);
@@ -269,23 +271,27 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
       sa[bf][arow1][1][lane] = Arith::load(st.a11);
     }
   };
-  // the A values of all RPW rows are read from LDS before any multiply, so
-  // their latency is paid once per entry; a row not visiting k reads a stale
-  // word that is never used
+  // the A values of groups of four rows are read from LDS before their
+  // multiplies, so their latency is paid once per group; a row not visiting
+  // k reads a stale word that is never used
   auto compute = [&](const Stage& st, int bf) {
     const int wmask = (st.mask >> rbase) & ((1 << RPW) - 1);
     if (!wmask) return;
-    const Val b0 = Arith::load(st.b0), b1 = Arith::load(st.b1);
+    const Val b0 = sb[bf][wave % kCols][0][lane], b1 = sb[bf][wave % kCols][1][lane];
     const Val bs = Arith::sum(b0, b1);
-    Val a0[RPW], a1[RPW];
+    constexpr int G = RPW > 4 ? 4 : RPW;   // rows read from LDS together
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      a0[r] = sa[bf][rbase + r][0][lane];
-      a1[r] = sa[bf][rbase + r][1][lane];
-    }
+    for (int g0 = 0; g0 < RPW; g0 += G) {
+      Val a0[G], a1[G];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      if (wmask & (1 << r)) ar.mac(acc[r], a0[r], a1[r], Arith::sum(a0[r], a1[r]), b0, b1, bs);
+      for (int r = 0; r < G; ++r) {
+        a0[r] = sa[bf][rbase + g0 + r][0][lane];
+        a1[r] = sa[bf][rbase + g0 + r][1][lane];
+      }
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        if (wmask & (1 << (g0 + r))) ar.mac(acc[g0 + r], a0[r], a1[r], Arith::sum(a0[r], a1[r]), b0, b1, bs);
+      }
     }
   };
   int cnt = 0;
