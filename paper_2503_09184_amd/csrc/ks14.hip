@@ -261,12 +261,22 @@ __device__ __forceinline__ void k2_body(const Ks14Args& a, const DevParams& dp, 
   }
 }
 
-// blocks (b, e): e over the special primes (SPECIAL) or the data primes
+// Workgroups are dispatched to the 8 XCDs round robin (block i to XCD i mod
+// 8), and each XCD has its own L2.  This maps block i to a work index so that
+// each XCD takes one contiguous range of [0, G): consecutive work indices
+// share their key rows, so an XCD's key working set stays within its L2.
+__device__ __forceinline__ int xcd_range_index(int i, int G) {
+  const int per = G >> 3, rem = G & 7, x = i & 7, s = i >> 3;
+  return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + s;
+}
+
+// blocks (e, b), prime-major: e over the special primes (SPECIAL) or the
+// data primes; every output b of one prime multiplies the same key rows
 template <int NT, bool SPECIAL>
 __global__ void __launch_bounds__(n14::kThreads, 4) ks14_k2_kernel(Ks14Args a, DevParams dp) {
   extern __shared__ u64 lds[];
-  const int m = SPECIAL ? dp.alpha : a.nl;
-  const int b = blockIdx.x / m, f = blockIdx.x % m;
+  const int w = xcd_range_index(blockIdx.x, gridDim.x);
+  const int f = w / a.n, b = w % a.n;
   const int e = SPECIAL ? a.nl + f : f;
   const int re = a.mu[0].basis[e];
   if (dp.pr[re].q < (1ull << 42))

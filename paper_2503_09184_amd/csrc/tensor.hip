@@ -171,20 +171,23 @@ struct ArithInt {   // q < 2^61: 128-bit integer sums, Karatsuba middle term
 };
 
 // Block kernel: 8 waves share one 64-coefficient chunk of one prime and a
-// tile of kTileRows output rows.  Wave w owns output column h * kCols + w %
-// kCols for RPW rows (kTileRows / RPW groups of rows, so that the
-// accumulators fit the register budget).  Per visited k, the A values of the
+// tile of kTileRows output rows and kCols columns.  Each wave owns RPW rows
+// and CPW columns of the tile (RPW x CPW accumulators fit the register
+// budget; a wave reads RPW + CPW operands from LDS per entry for RPW * CPW
+// products).  Per visited k, the A values of the
 // tile rows that visit it and the B values of the block's kCols columns are
 // staged once through LDS (double-buffered): each wave loads two A rows and
 // one B row (a column's poly), and every wave reads what it needs from LDS,
 // so each operand word is loaded from memory once per block and entry.
 // Global loads run two entries ahead of the multiplies.
-template <typename Arith, int RPW>
+template <typename Arith, int RPW, int CPW>
 __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const u64* A, const u64* B, u64* D,
                                                              FpLimbs fl, DevParams dp) {
   typedef typename Arith::Val Val;
-  constexpr int kHalves = kTileRows / RPW;
-  constexpr int kCols = kWavesPerBlock / kHalves;
+  constexpr int kRowGroups = kTileRows / RPW;
+  constexpr int kColGroups = kWavesPerBlock / kRowGroups;
+  constexpr int kCols = kColGroups * CPW;
+  static_assert(kRowGroups * kColGroups == kWavesPerBlock, "waves tile the block");
   __shared__ Val sa[2][kTileRows][2][64];
   __shared__ Val sb[2][kCols][2][64];              // B of the block's columns for the entry
   __shared__ int2 s_km[kSegEntries];               // (k, row mask) per entry
@@ -219,17 +222,18 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   const u64* Ab = A + cidx * 2 * tl.nA * 64 + lane;
   const u64* Bb = B + cidx * 2 * tl.nB * 64 + lane;
   const int64_t pA = tl.nA * 64, pB = tl.nB * 64;
-  const int half = wave / kCols;
-  const int j = h * kCols + (wave % kCols);
-  const int rbase = half * RPW;
+  const int rbase = (wave / kColGroups) * RPW;   // the wave's rows and columns within the tile
+  const int cbase = (wave % kColGroups) * CPW;
   const int arow0 = 2 * wave, arow1 = 2 * wave + 1;   // the rows this wave stages
   // and the B row (column wave / 2 of the block, poly wave % 2) it stages
   const bool bload = wave < 2 * kCols;
   const int jb = h * kCols + (wave >> 1);
   const int64_t pb_off = (wave & 1) ? pB : 0;
-  typename Arith::Acc acc[RPW];
+  typename Arith::Acc acc[RPW][CPW];
 #pragma unroll
-  for (int r = 0; r < RPW; ++r) Arith::zero(acc[r]);
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) Arith::zero(acc[r][c]);
 
   const int e0 = tl.tstart[g], e1 = tl.tstart[g + 1];
   struct Stage {
@@ -277,8 +281,14 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   auto compute = [&](const Stage& st, int bf) {
     const int wmask = (st.mask >> rbase) & ((1 << RPW) - 1);
     if (!wmask) return;
-    const Val b0 = sb[bf][wave % kCols][0][lane], b1 = sb[bf][wave % kCols][1][lane];
-    const Val bs = Arith::sum(b0, b1);
+    Val b0[CPW], b1[CPW], bs[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      b0[c] = sb[bf][cbase + c][0][lane];
+      b1[c] = sb[bf][cbase + c][1][lane];
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) bs[c] = Arith::sum(b0[c], b1[c]);
     constexpr int G = RPW > 4 ? 4 : RPW;   // rows read from LDS together
 #pragma unroll
     for (int g0 = 0; g0 < RPW; g0 += G) {
@@ -290,7 +300,11 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
       }
 #pragma unroll
       for (int r = 0; r < G; ++r) {
-        if (wmask & (1 << (g0 + r))) ar.mac(acc[g0 + r], a0[r], a1[r], Arith::sum(a0[r], a1[r]), b0, b1, bs);
+        if (wmask & (1 << (g0 + r))) {
+          const Val as = Arith::sum(a0[r], a1[r]);
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) ar.mac(acc[g0 + r][c], a0[r], a1[r], as, b0[c], b1[c], bs[c]);
+        }
       }
     }
   };
@@ -323,21 +337,27 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
       if (cnt >= Arith::kFold) {
         cnt = 0;
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) ar.fold(acc[r]);
+        for (int r = 0; r < RPW; ++r)
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) ar.fold(acc[r][c]);
       }
     }
   }
-  if (j >= Nc) return;
 #pragma unroll
-  for (int r = 0; r < RPW; ++r) {
-    const int pos = g * kTileRows + rbase + r;
-    if (pos >= tl.rows) continue;
-    u64* dp_ = D + ((int64_t)pos * Nc + j) * (int64_t)3 * L * N + (int64_t)l * N + tbase + lane;
-    u64 d0, d1, d2;
-    ar.final(acc[r], d0, d1, d2);
-    dp_[0] = d0;
-    dp_[(int64_t)L * N] = d1;
-    dp_[(int64_t)2 * L * N] = d2;
+  for (int c = 0; c < CPW; ++c) {
+    const int j = h * kCols + cbase + c;
+    if (j >= Nc) continue;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int pos = g * kTileRows + rbase + r;
+      if (pos >= tl.rows) continue;
+      u64* dp_ = D + ((int64_t)pos * Nc + j) * (int64_t)3 * L * N + (int64_t)l * N + tbase + lane;
+      u64 d0, d1, d2;
+      ar.final(acc[r][c], d0, d1, d2);
+      dp_[0] = d0;
+      dp_[(int64_t)L * N] = d1;
+      dp_[(int64_t)2 * L * N] = d2;
+    }
   }
 }
 
@@ -371,16 +391,16 @@ int launch_tensor_gather(const sfhe_ctx* c, int lev, const u64* A, int64_t nA, c
   return SFHE_OK;
 }
 
-template <typename Arith, int RPW>
+template <typename Arith, int RPW, int CPW>
 static int launch_block(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl, const u64* A, const u64* B, u64* D,
                         hipStream_t s) {
   if (fl.n == 0) return SFHE_OK;
-  constexpr int kCols = kWavesPerBlock / (kTileRows / RPW);
+  constexpr int kCols = kWavesPerBlock / (kTileRows / RPW) * CPW;
   TileList t2 = tl;
   t2.n_col_tiles = (tl.Nc + kCols - 1) / kCols;
   const int64_t blocks = (int64_t)fl.n * (c->N / 64) * tl.n_row_tiles * t2.n_col_tiles;
   if (blocks > 0x7FFFFFFF) { set_error("tensor: grid too large"); return SFHE_E_INVALID_ARG; }
-  hipLaunchKernelGGL((tensor_block_kernel<Arith, RPW>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, t2, A,
+  hipLaunchKernelGGL((tensor_block_kernel<Arith, RPW, CPW>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, t2, A,
                      B, D, fl, c->dp);
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;
@@ -407,9 +427,9 @@ int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, con
     dst.l[dst.n++] = F;
   }
   if (fp_start) SFHE_HIP(hipEventRecord(fp_start, s));
-  int rc = launch_block<ArithFp, kTileRows / 2>(c, tl, ffp, A, B, D, s);
+  int rc = launch_block<ArithFp, 4, 2>(c, tl, ffp, A, B, D, s);
   if (fp_stop) SFHE_HIP(hipEventRecord(fp_stop, s));
-  if (!rc) rc = launch_block<ArithInt, kTileRows / 4>(c, tl, fint, A, B, D, s);
+  if (!rc) rc = launch_block<ArithInt, 4, 1>(c, tl, fint, A, B, D, s);
   return rc;
 }
 
