@@ -89,6 +89,12 @@ def lib():
                                  ctypes.c_uint64, ctypes.c_uint64, _i32p, _i32p, ctypes.c_int,
                                  ctypes.c_int, _u64p, _f64p, _f64p]
         L.orc_matmul.restype = ctypes.c_int
+        L.orc_weight.argtypes = [ctypes.c_double, ctypes.c_double, _i64p]
+        L.orc_weight.restype = ctypes.c_int
+        L.orc_matmul_plain.argtypes = [ctypes.c_void_p, _f64p, ctypes.c_int, ctypes.c_int, _f64p, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                       _i32p, _i32p, ctypes.c_int, ctypes.c_int, _u64p, _f64p, _f64p]
+        L.orc_matmul_plain.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -279,6 +285,45 @@ class Oracle:
         if rc != 0:
             raise ValueError("oracle matmul failed (%d)" % rc)
         return out, (vals if decrypt else None), float(secs[0])
+
+    # ---- plaintext weights times encrypted values (Sec. 3.3.2) ----------
+    def matmul_plain(self, W, B, enc, seedB, log2_scale_w=40, outputs=None, threads=1, opB=1, decrypt=True):
+        """Selected outputs of W B for plaintext weights W (constant-polynomial
+        encoding at scale 2^log2_scale_w) and B encrypted per element.  Returns
+        (cts, vals, seconds) as matmul() does; the decryption scale is
+        2^log2_scale_w * Delta / q_{L-1}."""
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        M, K = W.shape
+        K2, Nc = B.shape
+        assert K == K2
+        if outputs is None:
+            outputs = [(i, j) for i in range(M) for j in range(Nc)]
+        rows = np.asarray([o[0] for o in outputs], dtype=np.int32)
+        cols = np.asarray([o[1] for o in outputs], dtype=np.int32)
+        nout = len(outputs)
+        out = np.zeros((nout, 2, self.L - 1, self.n), dtype=np.uint64)
+        vals = np.zeros(nout, dtype=np.float64)
+        secs = np.zeros(1, dtype=np.float64)
+        rc = lib().orc_matmul_plain(self._h, _p(W, _f64p), M, K, _p(B, _f64p), Nc, ENC[enc], float(log2_scale_w),
+                                    ctypes.c_uint64(seedB), ctypes.c_uint64(opB), _p(rows, _i32p), _p(cols, _i32p),
+                                    nout, int(threads), _p(out, _u64p), _p(vals, _f64p) if decrypt else None,
+                                    _p(secs, _f64p))
+        if rc != 0:
+            raise ValueError("oracle plaintext-weight matmul failed (%d)" % rc)
+        return out, (vals if decrypt else None), float(secs[0])
+
+    def plain_out_scale(self, log2_scale_w=40):
+        """Scale of a plaintext-weight product after its rescale."""
+        return 2.0 ** (log2_scale_w + self.log2_scale) / float(self.q[-1])
+
+
+def weight(w, log2_scale_w):
+    """The constant-polynomial coefficient of weight w (None if it does not fit)."""
+    m = np.zeros(1, dtype=np.int64)
+    if lib().orc_weight(float(w), float(log2_scale_w), _p(m, _i64p)) != 0:
+        return None
+    return int(m[0])
 
 
 def stream_word(seed, tag, fields, n):

@@ -34,6 +34,8 @@
  *   R6  outputs with no product are trivial zero ciphertexts.
  *   R7  NTT-domain index k holds a(psi^(2*brv(k)+1)), psi the smallest
  *       primitive 2N-th root of unity mod q.
+ *   R8  plaintext weights (the server-side weights of Sec. 3.3.2) are
+ *       constant polynomials nearbyint(w * 2^sw); see orc_weight().
  */
 #include <math.h>
 #include <pthread.h>
@@ -856,6 +858,121 @@ int orc_matmul(const orc_ctx* c, const double* A, int M, int K, const double* B,
   for (size_t x = 0; x < (size_t)M * K; x++) free(encA[x]);
   for (size_t x = 0; x < (size_t)K * Nc; x++) free(encB[x]);
   free(encA); free(encB);
+  struct_free(&S);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* plaintext weights times encrypted values (Sec. 3.3.2: a server that   */
+/* holds the model weights in plaintext multiplies them into the         */
+/* client's encrypted input)                                              */
+/* ------------------------------------------------------------------ */
+/* R8  a weight w is the constant polynomial m = nearbyint(w * 2^sw): a
+ *     constant takes the same value at every root of X^N + 1, so it scales
+ *     every slot by m, and multiplying a ciphertext by it multiplies both
+ *     polys coefficient-wise by m (in either domain).  Returns -1 if the
+ *     scaled weight does not fit 62 bits. */
+int orc_weight(double w, double sw, i64* m) {
+  double x = ldexp(w, (int)sw);
+  if (sw != floor(sw) || !(fabs(x) < 4.0e18)) return -1;
+  *m = (i64)nearbyint(x);
+  return 0;
+}
+
+typedef struct {
+  const orc_ctx* c;
+  const orc_struct* S;
+  const double* W;
+  double sw;
+  int K, Nc, nthreads, tid;
+  u64** encB;
+  const int* orow; const int* ocol; int nout;
+  u64* out;
+} pm_job;
+
+/* C_ij = Rescale(sum over the visited k, ascending, of m_ik B_kj) */
+static void pm_output(const pm_job* J, int i, int j, u64* o) {
+  const orc_ctx* c = J->c;
+  int N = c->N, L = c->L, top = L - 1;
+  size_t ct_top = (size_t)2 * L * N, ct_out = (size_t)2 * top * N;
+  int* ks = malloc(sizeof(int) * (J->K + 1));
+  int nk = row_ks(J->S, i, ks);
+  memset(o, 0, sizeof(u64) * ct_out);                       /* R6: trivial zero */
+  if (nk == 0) { free(ks); return; }
+  u64* acc = calloc(ct_top, sizeof(u64));
+  for (int n = 0; n < nk; n++) {
+    int k = ks[n];
+    i64 m;
+    orc_weight(J->W[(size_t)i * J->K + k], J->sw, &m);
+    const u64* b = J->encB[(size_t)k * J->Nc + j];
+    for (int p = 0; p < 2; p++)
+      for (int r = 0; r < L; r++) {
+        u64 q = c->q[r], mq = redi(m, q);
+        const u64* bb = b + ((size_t)p * L + r) * N;
+        u64* aa = acc + ((size_t)p * L + r) * N;
+        for (int t = 0; t < N; t++) aa[t] = addm(aa[t], mulm(mq, bb[t], q), q);
+      }
+  }
+  for (int p = 0; p < 2; p++) for (int r = 0; r < L; r++) ntt_inv(c, r, acc + ((size_t)p * L + r) * N);
+  orc_rescale(c, top, acc, o);
+  free(ks); free(acc);
+}
+
+static void* pm_worker(void* arg) {
+  const pm_job* J = arg;
+  size_t ct_out = (size_t)2 * (J->c->L - 1) * J->c->N;
+  for (int n = 0; n < J->nout; n++) {
+    long idx = (long)J->orow[n] * J->Nc + J->ocol[n];
+    if (idx % J->nthreads != J->tid) continue;
+    pm_output(J, J->orow[n], J->ocol[n], J->out + (size_t)n * ct_out);
+  }
+  return NULL;
+}
+
+/* Listed outputs of C = W B with W (M x K) plaintext weights stored with
+ * encoding `enc` and scaled by 2^sw (R8), B (K x Nc) dense and encrypted with
+ * (seedB, opB).  out receives [nout][2][L-1][N] coefficient-domain residues,
+ * vals (nullable) the values decrypted at scale 2^sw * Delta / q_{L-1},
+ * seconds (nullable) the wall time of the multiply stage. */
+int orc_matmul_plain(const orc_ctx* c, const double* W, int M, int K, const double* B, int Nc, int enc, double sw,
+                     u64 seedB, u64 opB, const int* orow, const int* ocol, int nout, int nthreads,
+                     u64* out, double* vals, double* seconds) {
+  if (!c->has_keys || c->L < 2 || nthreads < 1) return -1;
+  for (int n = 0; n < nout; n++) if (orow[n] < 0 || orow[n] >= M || ocol[n] < 0 || ocol[n] >= Nc) return -2;
+  for (size_t x = 0; x < (size_t)M * K; x++) { i64 m; if (W[x] != 0.0 && orc_weight(W[x], sw, &m)) return -3; }
+  orc_struct S; struct_build(&S, W, M, K, enc);
+  size_t ct_top = (size_t)2 * c->L * c->N;
+  u64** encB = calloc((size_t)K * Nc, sizeof(u64*));
+  int* ks = malloc(sizeof(int) * (K + 1));
+  for (int n = 0; n < nout; n++) {
+    int nk = row_ks(&S, orow[n], ks);
+    for (int x = 0; x < nk; x++) {
+      size_t ib = (size_t)ks[x] * Nc + ocol[n];
+      if (!encB[ib]) encB[ib] = malloc(sizeof(u64) * ct_top);
+    }
+  }
+  free(ks);
+  encrypt_marked(c, B, K, Nc, seedB, opB, encB, nthreads);
+
+  pthread_t th[256]; pm_job jobs[256];
+  int T = nthreads > 256 ? 256 : nthreads;
+  double t0 = now_s();
+  for (int t = 0; t < T; t++) {
+    jobs[t] = (pm_job){c, &S, W, sw, K, Nc, T, t, encB, orow, ocol, nout, out};
+    pthread_create(&th[t], NULL, pm_worker, &jobs[t]);
+  }
+  for (int t = 0; t < T; t++) pthread_join(th[t], NULL);
+  double t1 = now_s();
+  if (seconds) *seconds = t1 - t0;
+
+  if (vals) {
+    int top = c->L - 1;
+    double scale = ldexp(1.0, (int)sw + (int)c->log2_scale) / (double)c->q[top];
+    size_t ct_out = (size_t)2 * top * c->N;
+    for (int n = 0; n < nout; n++) vals[n] = orc_decrypt(c, top - 1, out + (size_t)n * ct_out, scale);
+  }
+  for (size_t x = 0; x < (size_t)K * Nc; x++) free(encB[x]);
+  free(encB);
   struct_free(&S);
   return 0;
 }

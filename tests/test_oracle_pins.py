@@ -477,3 +477,88 @@ def test_plaintext_schedules_give_the_product(enc):
         for k in ks:
             C[i] += A[i, k] * B[k]
     assert np.allclose(C, A @ B, atol=1e-14)
+
+
+# ------------------------------------------- plaintext weights (Sec. 3.3.2)
+from oracle.oracle import weight as _weight
+
+
+def test_weight_encoding_rounds_to_nearest_even():
+    """A weight is the integer nearest to w * 2^sw, ties to even (checked with
+    Python's round, which rounds half to even)."""
+    for w, sw in [(0.1, 40), (-0.7, 40), (2.5 * 2.0 ** -40, 40), (-3.5 * 2.0 ** -40, 40), (1.0, 0), (-2.0, 0),
+                  (0.5, 0), (1.5, 0), (0.999999, 20)]:
+        assert _weight(w, sw) == round(w * 2.0 ** sw), (w, sw)
+    assert _weight(1.0, 70) is None                          # does not fit 62 bits
+
+
+@pytest.mark.parametrize("params", [TINY_SINGLE, TINY_HYBRID])
+def test_plain_product_is_rescaled_integer_combination(params):
+    """With integer weights (scale 2^0) each output is the exact rounding
+    round(C / q_l) of C = sum_k m_ik B_kj, formed here in Python integers from
+    the coefficient-domain encryptions of the B elements."""
+    o = make(params, seed=4)
+    Wt = np.array([[1.0, 0.0, 0.0, 0.0],
+                   [0.0, -2.0, 0.0, 3.0],
+                   [0.0, 0.0, 0.0, 0.0],
+                   [5.0, -1.0, 7.0, -4.0]])
+    B = W.uniform_matrix(4, 2, 31)
+    seedB, opB = 11, 1
+    cts, _, _ = o.matmul_plain(Wt, B, "csr", seedB, log2_scale_w=0, threads=2, opB=opB, decrypt=False)
+    lev = o.L - 1
+    qs = o.q
+    Q = brute.prod(qs)
+    Qd = brute.prod(qs[:-1])
+    ql = qs[-1]
+    encB = {(k, j): o.encrypt(B[k, j], seedB, opB, k, j) for k in range(4) for j in range(2)}
+    for i in range(4):
+        for j in range(2):
+            got_ct = cts[i * 2 + j]
+            if not Wt[i].any():
+                assert not got_ct.any()                        # trivial zero
+                continue
+            for p in range(2):
+                for t in range(o.n):
+                    res = []
+                    for r in range(lev + 1):
+                        s = sum(int(Wt[i, k]) * int(encB[(k, j)][p, r, t]) for k in range(4))
+                        res.append(s % qs[r])
+                    C = brute.centered(brute.crt(res, qs), Q)
+                    want = (2 * C + ql) // (2 * ql)
+                    got = brute.crt([int(got_ct[p, r, t]) for r in range(lev)], qs[:-1])
+                    assert got == want % Qd, (i, j, p, t)
+
+
+def _bound_plain(o, w_row, sw):
+    """6-sigma decrypted-error bound of one plaintext-weight output: the
+    weighted fresh noise of the B terms plus one rescale rounding."""
+    n = o.n
+    delta = 2.0 ** o.log2_scale
+    dp = o.plain_out_scale(sw)
+    sf = 3.2 * math.sqrt(n / 2) / delta
+    srs = math.sqrt((1 + 2 * n / 3) / 12 * n / 2) / dp
+    var = srs ** 2 + float(np.sum(np.asarray(w_row) ** 2)) * sf ** 2 * 2
+    return 6 * math.sqrt(var) + 1e-12
+
+
+@pytest.mark.parametrize("params,sw", [(W.PARAMS["toy_n1024"], 40), (SMALL, 40), (SMALL_HYBRID, 30)])
+def test_plain_product_decrypts_to_fp64_product(params, sw):
+    o = make(params, seed=6)
+    Wt, B = W.operands(6, 5, 4, 0.5, 44)
+    _, vals, _ = o.matmul_plain(Wt, B, "ell", 9, log2_scale_w=sw, threads=3)
+    ref = Wt @ B
+    for n, (i, j) in enumerate([(i, j) for i in range(6) for j in range(4)]):
+        assert abs(vals[n] - ref[i, j]) <= _bound_plain(o, Wt[i], sw), (i, j)
+
+
+def test_plain_product_schemes_bit_identical_and_dense_at_zero_sparsity():
+    o = make(SMALL_HYBRID, seed=12)
+    Wt, B = W.operands(5, 7, 3, 0.5, 15)
+    Wt[1, :] = 0.0
+    outs = {enc: o.matmul_plain(Wt, B, enc, 3, threads=2, decrypt=False)[0] for enc in ("naive", "csr", "ell")}
+    assert np.array_equal(outs["naive"], outs["csr"]) and np.array_equal(outs["csr"], outs["ell"])
+    assert not outs["csr"].reshape(5, 3, -1)[1].any()
+    W0, B0 = W.operands(4, 5, 3, 0.0, 16)
+    d = o.matmul_plain(W0, B0, "dense", 3, threads=2, decrypt=False)[0]
+    c = o.matmul_plain(W0, B0, "csr", 3, threads=2, decrypt=False)[0]
+    assert np.array_equal(d, c)
