@@ -168,6 +168,51 @@ int sfhe_decrypt_matrix(sfhe_ctx* ctx, const sfhe_mat* m, double* out, int64_t l
 int sfhe_export_ct(sfhe_ctx* ctx, const sfhe_mat* m, int32_t i, int32_t j, uint64_t* out, size_t cap,
                    void* stream);
 
+/* ---- Plaintext weights times encrypted values -------------------------
+ * Sec. 3.3.2: a server that holds a layer's weights in plaintext multiplies
+ * them into the client's encrypted input; the weights' zeros are skipped
+ * through the same encodings.  A weight w is the constant polynomial
+ * m = nearbyint(w * 2^log2_scale_w) (round half to even): a constant takes
+ * the same value at every root of X^N + 1, so it scales every slot by m, and
+ * its product with a ciphertext multiplies both polys coefficient-wise by
+ * m mod q_i.  No relinearisation is needed. */
+
+/* Encode a rows x cols row-major fp64 weight matrix (leading dimension ld >=
+ * cols) with the given encoding (zeros: elements equal to 0.0), scale
+ * 2^log2_scale_w, 0 <= log2_scale_w <= 62, and |w| * 2^log2_scale_w below
+ * 2^62 (else SFHE_E_INVALID_ARG).  The weights' residues stay in host
+ * memory owned by the handle; no key is needed.  The handle is a left
+ * operand of sfhe_matmul_plain only (sfhe_matmul, sfhe_decrypt_matrix and
+ * sfhe_export_ct reject it with SFHE_E_UNSUPPORTED); sfhe_matrix_info reports
+ * level L - 1, scale 2^log2_scale_w and zero device bytes. */
+int sfhe_encode_matrix(sfhe_ctx* ctx, const double* vals, int32_t rows, int32_t cols, int64_t ld,
+                       sfhe_encoding enc, int32_t log2_scale_w, sfhe_mat** out);
+
+/* C = W * B for plaintext weights W (from sfhe_encode_matrix) and an
+ * encrypted DENSE B at the top level: per output, the products of the
+ * visited k are summed in the NTT domain and the sum is rescaled once.  The
+ * result is a DENSE encrypted matrix one level lower with scale
+ * W.scale * B.scale / q_level; outputs with no visited k are trivial zeros.
+ * Errors as sfhe_matmul (SFHE_E_SHAPE if W.cols != B.rows). */
+int sfhe_matmul_plain(sfhe_ctx* ctx, const sfhe_mat* W, const sfhe_mat* B, void* stream, sfhe_mat** C);
+
+typedef enum {
+  SFHE_PLAIN_FUSED = 0,             /* every product of the batch in one launch per arithmetic */
+  SFHE_PLAIN_LAUNCH_PER_PRODUCT = 1 /* one launch per (output, k) product: the unbatched form */
+} sfhe_plain_launch;
+
+/* count independent products C[n] = W[n] * B[n] (each as sfhe_matmul_plain,
+ * shapes free per n) in one call.  SFHE_PLAIN_FUSED runs the products of all
+ * of them in one kernel launch (two when the primes need both the fp64 and
+ * the integer arithmetic), then one rescale per matrix;
+ * SFHE_PLAIN_LAUNCH_PER_PRODUCT launches one kernel per product instead.
+ * Both give the same bits.  The sums of all outputs are held on the device
+ * at once (2 (L) N words per output): SFHE_E_NOMEM if they do not fit.  C
+ * has count entries; on failure every entry is NULL.  sfhe_last_stats
+ * reports the device time of the whole call, products and launches. */
+int sfhe_matmul_plain_batch(sfhe_ctx* ctx, int32_t count, const sfhe_mat* const* W, const sfhe_mat* const* B,
+                            sfhe_plain_launch launch, void* stream, sfhe_mat** C);
+
 int sfhe_matrix_info(const sfhe_mat* m, sfhe_mat_info* out);
 int sfhe_last_stats(const sfhe_ctx* ctx, sfhe_stats* out);
 

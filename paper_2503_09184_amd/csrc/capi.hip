@@ -307,6 +307,64 @@ static int64_t slot_of(const sfhe_mat* m, int i, int j) {
   return -1;
 }
 
+// The plaintext structure of encoding m->enc (Sec. 3.3.2) for the rows x cols
+// matrix vals (leading dimension ld), and the storage slot of every stored
+// element: push(i, j, slot) is called once per stored element.
+template <typename Push>
+static void build_structure(sfhe_mat* m, const double* vals, int64_t ld, Push push) {
+  const int rows = m->rows, cols = m->cols;
+  const sfhe_encoding enc = m->enc;
+  auto nz = [&](int i, int j) { return vals[(int64_t)i * ld + j] != 0.0; };
+  int64_t nnz = 0;
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < cols; ++j) nnz += nz(i, j);
+  m->nnz = nnz;
+  switch (enc) {
+    case SFHE_ENC_DENSE:
+    case SFHE_ENC_NAIVE_SPARSE:
+      m->n_ct = (int64_t)rows * cols;
+      for (int i = 0; i < rows; ++i)
+        for (int j = 0; j < cols; ++j) push(i, j, (int64_t)i * cols + j);
+      if (enc == SFHE_ENC_NAIVE_SPARSE) {
+        m->zero_mask.assign((size_t)((int64_t)rows * cols + 31) / 32, 0u);
+        for (int i = 0; i < rows; ++i)
+          for (int j = 0; j < cols; ++j)
+            if (!nz(i, j)) {
+              const int64_t e = (int64_t)i * cols + j;
+              m->zero_mask[e >> 5] |= 1u << (e & 31);
+            }
+      }
+      break;
+    case SFHE_ENC_CSR:
+      m->row_ptr.assign(rows + 1, 0);
+      for (int i = 0; i < rows; ++i) {
+        m->row_ptr[i] = (int)m->col_idx.size();
+        for (int j = 0; j < cols; ++j)
+          if (nz(i, j)) { push(i, j, (int64_t)m->col_idx.size()); m->col_idx.push_back(j); }
+      }
+      m->row_ptr[rows] = (int)m->col_idx.size();
+      m->n_ct = (int64_t)m->col_idx.size();
+      break;
+    case SFHE_ENC_ELL: {
+      int w = 0;
+      for (int i = 0; i < rows; ++i) {
+        int n = 0;
+        for (int j = 0; j < cols; ++j) n += nz(i, j);
+        w = std::max(w, n);
+      }
+      m->ell_w = w;
+      m->ell_col.assign((size_t)rows * w, -1);
+      for (int i = 0; i < rows; ++i) {
+        int n = 0;
+        for (int j = 0; j < cols; ++j)
+          if (nz(i, j)) { m->ell_col[(size_t)i * w + n] = j; push(i, j, (int64_t)i * w + n); ++n; }
+      }
+      m->n_ct = (int64_t)rows * w;
+      break;
+    }
+  }
+}
+
 }  // namespace sfhe
 
 using namespace sfhe;
@@ -463,61 +521,12 @@ int sfhe_encrypt_matrix(sfhe_ctx* c, const double* vals, int32_t rows, int32_t c
   std::vector<int> ei, ej;
   std::vector<double> z;
   std::vector<int64_t> slot;
-  auto nz = [&](int i, int j) { return vals[(int64_t)i * ld + j] != 0.0; };
-  int64_t nnz = 0;
-  for (int i = 0; i < rows; ++i)
-    for (int j = 0; j < cols; ++j) nnz += nz(i, j);
-  m->nnz = nnz;
-  auto push = [&](int i, int j, int64_t sl) {
+  build_structure(m, vals, ld, [&](int i, int j, int64_t sl) {
     ei.push_back(i);
     ej.push_back(j);
     z.push_back(vals[(int64_t)i * ld + j]);
     slot.push_back(sl);
-  };
-  switch (enc) {
-    case SFHE_ENC_DENSE:
-    case SFHE_ENC_NAIVE_SPARSE:
-      m->n_ct = (int64_t)rows * cols;
-      for (int i = 0; i < rows; ++i)
-        for (int j = 0; j < cols; ++j) push(i, j, (int64_t)i * cols + j);
-      if (enc == SFHE_ENC_NAIVE_SPARSE) {
-        m->zero_mask.assign((size_t)((int64_t)rows * cols + 31) / 32, 0u);
-        for (int i = 0; i < rows; ++i)
-          for (int j = 0; j < cols; ++j)
-            if (!nz(i, j)) {
-              const int64_t e = (int64_t)i * cols + j;
-              m->zero_mask[e >> 5] |= 1u << (e & 31);
-            }
-      }
-      break;
-    case SFHE_ENC_CSR:
-      m->row_ptr.assign(rows + 1, 0);
-      for (int i = 0; i < rows; ++i) {
-        m->row_ptr[i] = (int)m->col_idx.size();
-        for (int j = 0; j < cols; ++j)
-          if (nz(i, j)) { push(i, j, (int64_t)m->col_idx.size()); m->col_idx.push_back(j); }
-      }
-      m->row_ptr[rows] = (int)m->col_idx.size();
-      m->n_ct = (int64_t)m->col_idx.size();
-      break;
-    case SFHE_ENC_ELL: {
-      int w = 0;
-      for (int i = 0; i < rows; ++i) {
-        int n = 0;
-        for (int j = 0; j < cols; ++j) n += nz(i, j);
-        w = std::max(w, n);
-      }
-      m->ell_w = w;
-      m->ell_col.assign((size_t)rows * w, -1);
-      for (int i = 0; i < rows; ++i) {
-        int n = 0;
-        for (int j = 0; j < cols; ++j)
-          if (nz(i, j)) { m->ell_col[(size_t)i * w + n] = j; push(i, j, (int64_t)i * w + n); ++n; }
-      }
-      m->n_ct = (int64_t)rows * w;
-      break;
-    }
-  }
+  });
   const int N = c->N, L = c->L;
   int rc = SFHE_OK;
   const size_t words = (size_t)m->n_ct * 2 * L * N;
@@ -563,7 +572,7 @@ int sfhe_matrix_info(const sfhe_mat* m, sfhe_mat_info* out) {
   out->n_ciphertexts = m->n_ct;
   out->nnz = m->nnz;
   out->ell_width = m->ell_w;
-  out->device_bytes = (uint64_t)m->n_ct * 2 * (m->level + 1) * m->ctx->N * sizeof(u64);
+  out->device_bytes = m->plain ? 0 : (uint64_t)m->n_ct * 2 * (m->level + 1) * m->ctx->N * sizeof(u64);
   return SFHE_OK;
 }
 
@@ -575,6 +584,7 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
   *C = nullptr;
   if (!c || !A || !B) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
   if (A->ctx != c || B->ctx != c) { set_error("matrices belong to another context"); return SFHE_E_INVALID_ARG; }
+  if (A->plain || B->plain) { set_error("plaintext weights: use sfhe_matmul_plain"); return SFHE_E_UNSUPPORTED; }
   if (sched != SFHE_SCHED_PER_PRODUCT && sched != SFHE_SCHED_LAZY) { set_error("bad schedule"); return SFHE_E_INVALID_ARG; }
   if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
   if (B->enc != SFHE_ENC_DENSE) { set_error("the right operand must be DENSE"); return SFHE_E_UNSUPPORTED; }
@@ -813,6 +823,229 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
   GUARD_END
 }
 
+int sfhe_encode_matrix(sfhe_ctx* c, const double* vals, int32_t rows, int32_t cols, int64_t ld, sfhe_encoding enc,
+                       int32_t log2_scale_w, sfhe_mat** out) {
+  GUARD_BEGIN
+  if (!out) { set_error("out is NULL"); return SFHE_E_INVALID_ARG; }
+  *out = nullptr;
+  if (!c || !vals) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (rows < 1 || cols < 1 || ld < cols) { set_error("bad shape or leading dimension"); return SFHE_E_SHAPE; }
+  if ((int)enc < 0 || (int)enc > 3) { set_error("bad encoding"); return SFHE_E_INVALID_ARG; }
+  if (log2_scale_w < 0 || log2_scale_w > 62) { set_error("log2_scale_w outside [0, 62]"); return SFHE_E_INVALID_ARG; }
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < cols; ++j) {
+      const double x = ldexp(vals[(int64_t)i * ld + j], log2_scale_w);
+      if (!(fabs(x) < 4.0e18)) { set_error("weight not finite or too large to encode"); return SFHE_E_INVALID_ARG; }
+    }
+  sfhe_mat* m = new sfhe_mat();
+  m->ctx = c;
+  m->rows = rows;
+  m->cols = cols;
+  m->level = c->L - 1;
+  m->scale = ldexp(1.0, log2_scale_w);
+  m->enc = enc;
+  m->plain = true;
+  const int L = c->L;
+  std::vector<std::pair<int64_t, double>> stored;   // (slot, weight)
+  build_structure(m, vals, ld, [&](int i, int j, int64_t sl) { stored.push_back({sl, vals[(int64_t)i * ld + j]}); });
+  // the constant polynomial nearbyint(w 2^sw), reduced per data prime; ELL
+  // padding slots stay 0 (never visited)
+  m->w_res.assign((size_t)std::max<int64_t>(m->n_ct, 1) * L, 0);
+  for (auto& st : stored) {
+    const int64_t mi = (int64_t)nearbyint(ldexp(st.second, log2_scale_w));
+    for (int l = 0; l < L; ++l) {
+      const u64 q = c->primes[l];
+      const u64 r = mi >= 0 ? (u64)mi % q : (q - 1) - (u64)(-(mi + 1)) % q;
+      m->w_res[(size_t)st.first * L + l] = r;
+    }
+  }
+  *out = m;
+  return SFHE_OK;
+  GUARD_END
+}
+
+// the plaintext-weight product of count (W, B) pairs: checks, tile tables,
+// one fused launch set (or one launch per product), then one rescale per pair
+static int plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, const sfhe_mat* const* Bm,
+                       sfhe_plain_launch launch, hipStream_t s, sfhe_mat** C) {
+  for (int n = 0; n < count; ++n) C[n] = nullptr;
+  if (launch != SFHE_PLAIN_FUSED && launch != SFHE_PLAIN_LAUNCH_PER_PRODUCT) { set_error("bad launch mode"); return SFHE_E_INVALID_ARG; }
+  for (int n = 0; n < count; ++n) {
+    const sfhe_mat *W = Wm[n], *B = Bm[n];
+    if (!W || !B) { set_error("NULL matrix"); return SFHE_E_INVALID_ARG; }
+    if (W->ctx != c || B->ctx != c) { set_error("matrices belong to another context"); return SFHE_E_INVALID_ARG; }
+    if (!W->plain) { set_error("the left operand must be plaintext weights (sfhe_encode_matrix)"); return SFHE_E_INVALID_ARG; }
+    if (B->plain) { set_error("the right operand must be encrypted"); return SFHE_E_INVALID_ARG; }
+    if (B->enc != SFHE_ENC_DENSE) { set_error("the right operand must be DENSE"); return SFHE_E_UNSUPPORTED; }
+    if (W->cols != B->rows) { set_error("W.cols != B.rows"); return SFHE_E_SHAPE; }
+    if (B->level != c->L - 1) { set_error("the encrypted operand must be at the top level"); return SFHE_E_LEVEL; }
+    if (B->level < 1) { set_error("no prime left to rescale"); return SFHE_E_LEVEL; }
+  }
+  const int N = c->N, lev = c->L - 1, nl = lev + 1;
+  const int64_t dw = (int64_t)2 * nl * N;   // words per output sum
+  // host tables: tiles of 16 rows per job, their entries (k, row mask) and
+  // the weights of each entry, row and prime
+  std::vector<PlainJob> jobs(count);
+  std::vector<int4> desc;
+  std::vector<int> tstart, ek, emask;
+  std::vector<u64> ew, ews;
+  std::vector<std::pair<int, int64_t>> pairs;
+  int64_t outs = 0, products = 0;
+  int tiles = 0;
+  for (int n = 0; n < count; ++n) {
+    const sfhe_mat *W = Wm[n], *B = Bm[n];
+    const int M = W->rows, K = W->cols, Nc = B->cols;
+    jobs[n] = PlainJob{B->data.ptr, B->n_ct, Nc, M, tiles, outs};
+    const int ntile = (M + 15) / 16, ncg = (Nc + 3) / 4;
+    std::vector<int> kmask(K);
+    std::vector<int64_t> kslot((size_t)K * 16);
+    for (int g = 0; g < ntile; ++g) {
+      std::fill(kmask.begin(), kmask.end(), 0);
+      for (int r = 0; r < 16 && g * 16 + r < M; ++r) {
+        row_pairs(W, g * 16 + r, pairs);
+        products += (int64_t)pairs.size() * Nc;
+        for (auto& pr : pairs) {
+          kmask[pr.first] |= 1 << r;
+          kslot[(size_t)pr.first * 16 + r] = pr.second;
+        }
+      }
+      tstart.push_back((int)ek.size());
+      for (int k = 0; k < K; ++k) {
+        if (!kmask[k]) continue;
+        ek.push_back(k);
+        emask.push_back(kmask[k]);
+        for (int l = 0; l < nl; ++l) {
+          const u64 q = c->primes[l];
+          for (int r = 0; r < 16; ++r) {
+            const u64 w = (kmask[k] >> r) & 1 ? W->w_res[(size_t)kslot[(size_t)k * 16 + r] * c->L + l] : 0;
+            if (q < (1ull << 42)) {
+              const double wd = (double)w;
+              u64 bits;
+              memcpy(&bits, &wd, sizeof(bits));
+              ew.push_back(bits);
+              ews.push_back(0);
+            } else {
+              ew.push_back(w);
+              ews.push_back(hostmath::shoup(w, q));
+            }
+          }
+        }
+      }
+      for (int h = 0; h < ncg; ++h) desc.push_back(make_int4(n, g, h, 0));
+      ++tiles;
+    }
+    outs += (int64_t)M * Nc;
+  }
+  tstart.push_back((int)ek.size());
+  if (ek.size() > (size_t)0x7FFFFFFF / 16) { set_error("plaintext-weight product: too many entries"); return SFHE_E_INVALID_ARG; }
+  c->prof_used = 0;
+  c->prof_cat.clear();
+  SFHE_HIP(hipEventRecord(c->ev0, s));
+  int rc = SFHE_OK;
+  for (int n = 0; n < count && !rc; ++n) {
+    sfhe_mat* o = new sfhe_mat();
+    C[n] = o;
+    o->ctx = c;
+    o->rows = Wm[n]->rows;
+    o->cols = Bm[n]->cols;
+    o->level = lev - 1;
+    o->scale = Wm[n]->scale * Bm[n]->scale / (double)c->primes[lev];
+    o->enc = SFHE_ENC_DENSE;
+    o->n_ct = (int64_t)o->rows * o->cols;
+    o->nnz = o->n_ct;
+    if (!o->data.alloc(&c->alloc, (size_t)o->n_ct * 2 * lev * N)) { rc = SFHE_E_NOMEM; set_error("device allocation failed for a result"); }
+  }
+  DevBuf<u64> D, d_ew, d_ews;
+  DevBuf<int> d_ts, d_ek, d_em;
+  DevBuf<int4> d_desc;
+  DevBuf<PlainJob> d_jobs;
+  if (!rc && (!D.alloc(&c->alloc, (size_t)std::max<int64_t>(outs, 1) * dw) || !upload(c, d_ts, tstart, s) ||
+              !upload(c, d_ek, ek, s) || !upload(c, d_em, emask, s) || !upload(c, d_ew, ew, s) ||
+              !upload(c, d_ews, ews, s) || !upload(c, d_desc, desc, s) || !upload(c, d_jobs, jobs, s))) {
+    rc = SFHE_E_NOMEM;
+    set_error("device allocation failed (the sums of every output are held at once)");
+  }
+  int64_t launches = 0;
+  if (!rc && launch == SFHE_PLAIN_FUSED) {
+    PlainBatch pb{d_jobs.ptr, d_desc.ptr, (int)desc.size(), d_ts.ptr, d_ek.ptr, d_em.ptr, d_ew.ptr, d_ews.ptr, nl, D.ptr};
+    rc = launch_plain_batch(c, pb, s);
+    launches = 1 + (tensor_fp_prime_count(c) > 0 && tensor_fp_prime_count(c) < nl);
+  } else if (!rc) {
+    // one launch per product: weights of every product uploaded once
+    std::vector<u64> pw, pws;
+    std::vector<int64_t> pb_slot, pd;
+    std::vector<int> pjob;
+    for (int n = 0; n < count; ++n) {
+      const sfhe_mat *W = Wm[n], *B = Bm[n];
+      for (int i = 0; i < W->rows; ++i) {
+        row_pairs(W, i, pairs);
+        for (int j = 0; j < B->cols; ++j)
+          for (auto& pr : pairs) {
+            for (int l = 0; l < nl; ++l) {
+              const u64 w = W->w_res[(size_t)pr.second * c->L + l];
+              pw.push_back(w);
+              pws.push_back(hostmath::shoup(w, c->primes[l]));
+            }
+            pb_slot.push_back((int64_t)pr.first * B->cols + j);
+            pd.push_back(jobs[n].d0 + (int64_t)i * B->cols + j);
+            pjob.push_back(n);
+          }
+      }
+    }
+    DevBuf<u64> d_pw, d_pws;
+    if (!upload(c, d_pw, pw, s) || !upload(c, d_pws, pws, s)) { rc = SFHE_E_NOMEM; set_error("device allocation failed"); }
+    if (!rc) rc = launch_zero(D.ptr, std::max<int64_t>(outs, 1) * dw, s);
+    for (size_t x = 0; x < pb_slot.size() && !rc; ++x) {
+      const sfhe_mat* B = Bm[pjob[x]];
+      rc = launch_plain_product(c, B->data.ptr, B->n_ct, pb_slot[x], d_pw.ptr + x * nl, d_pws.ptr + x * nl,
+                                D.ptr + pd[x] * dw, nl, s);
+      ++launches;
+    }
+  }
+  for (int n = 0; n < count && !rc; ++n) {
+    const int64_t cnt = (int64_t)C[n]->n_ct;
+    const OutLayout ol{C[n]->data.ptr, 0, true, C[n]->n_ct, 0};
+    rc = rescale_batch(c, lev, D.ptr + jobs[n].d0 * dw, dw, ol, cnt, s);
+  }
+  if (!rc) {
+    hipError_t e = hipEventRecord(c->ev1, s);
+    if (e != hipSuccess) { rc = SFHE_E_DEVICE; set_error(hipGetErrorString(e)); }
+  }
+  if (rc) {
+    (void)hipStreamSynchronize(s);
+    for (int n = 0; n < count; ++n) { delete C[n]; C[n] = nullptr; }
+    return rc;
+  }
+  c->stats = sfhe_stats{};
+  c->stats.products = products;
+  c->stats.outputs = outs;
+  c->stats.tensor_launches = launches;
+  c->stats_pending = true;
+  return SFHE_OK;
+}
+
+int sfhe_matmul_plain(sfhe_ctx* c, const sfhe_mat* W, const sfhe_mat* B, void* stream, sfhe_mat** C) {
+  GUARD_BEGIN
+  if (!C) { set_error("C is NULL"); return SFHE_E_INVALID_ARG; }
+  *C = nullptr;
+  if (!c || !W || !B) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  return plain_batch(c, 1, &W, &B, SFHE_PLAIN_FUSED, (hipStream_t)stream, C);
+  GUARD_END
+}
+
+int sfhe_matmul_plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* W, const sfhe_mat* const* B,
+                            sfhe_plain_launch launch, void* stream, sfhe_mat** C) {
+  GUARD_BEGIN
+  if (!C) { set_error("C is NULL"); return SFHE_E_INVALID_ARG; }
+  if (!c || !W || !B || count < 1) {
+    if (count > 0) for (int n = 0; n < count; ++n) C[n] = nullptr;
+    set_error("NULL argument or count < 1");
+    return SFHE_E_INVALID_ARG;
+  }
+  return plain_batch(c, count, W, B, launch, (hipStream_t)stream, C);
+  GUARD_END
+}
+
 int sfhe_last_stats(const sfhe_ctx* cc, sfhe_stats* out) {
   if (!cc || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
   sfhe_ctx* c = const_cast<sfhe_ctx*>(cc);
@@ -841,6 +1074,7 @@ int sfhe_decrypt_matrix(sfhe_ctx* c, const sfhe_mat* m, double* out, int64_t ld,
   GUARD_BEGIN
   if (!c || !m || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
   if (m->ctx != c) { set_error("matrix belongs to another context"); return SFHE_E_INVALID_ARG; }
+  if (m->plain) { set_error("plaintext weights hold no ciphertexts"); return SFHE_E_UNSUPPORTED; }
   if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
   if (ld < m->cols) { set_error("ld < cols"); return SFHE_E_SHAPE; }
   hipStream_t s = (hipStream_t)stream;
@@ -885,6 +1119,7 @@ int sfhe_decrypt_matrix(sfhe_ctx* c, const sfhe_mat* m, double* out, int64_t ld,
 int sfhe_export_ct(sfhe_ctx* c, const sfhe_mat* m, int32_t i, int32_t j, uint64_t* out, size_t cap, void* stream) {
   GUARD_BEGIN
   if (!c || !m || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (m->plain) { set_error("plaintext weights hold no ciphertexts"); return SFHE_E_UNSUPPORTED; }
   if (i < 0 || i >= m->rows || j < 0 || j >= m->cols) { set_error("index out of range"); return SFHE_E_SHAPE; }
   const int N = c->N, nl = m->level + 1;
   const size_t words = (size_t)2 * nl * N;

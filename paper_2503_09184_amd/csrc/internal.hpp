@@ -123,6 +123,10 @@ struct sfhe_mat {
   std::vector<uint32_t> zero_mask;       // naive sparse: bit (i*cols + k) set iff A_ik == 0
   sfhe::DevBuf<int> d_row_ptr, d_col_idx, d_ell_col;
   sfhe::DevBuf<uint32_t> d_mask;
+  // plaintext weights (sfhe_encode_matrix): no ciphertexts; the residue of
+  // each stored weight per data prime, host side, [n_ct][L]
+  bool plain = false;
+  std::vector<uint64_t> w_res;
 };
 
 namespace sfhe {
@@ -202,6 +206,35 @@ struct TileList {
 int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, const u64* B, u64* D, hipStream_t s,
                         hipEvent_t fp_start = nullptr, hipEvent_t fp_stop = nullptr);
 int tensor_fp_prime_count(const sfhe_ctx* c);
+
+// ---- plaintext weights times encrypted values (ctpt.hip) ----
+// one matmul W B of a batch: W's tiles of 16 rows are tile0 .. tile0 +
+// ceil(rows / 16) - 1 of the batch's tile arrays, its outputs d0 ..
+// d0 + rows * Nc - 1 of D (row-major)
+struct PlainJob {
+  const u64* B;      // encrypted K x Nc dense matrix, chunked layout, nB stored ciphertexts
+  int64_t nB;
+  int Nc, rows;
+  int tile0;
+  int64_t d0;
+};
+struct PlainBatch {
+  const PlainJob* jobs;
+  const int4* desc;      // per block group (job, tile within the job, column group of 4, 0)
+  int n_desc;
+  const int* tstart;     // [tiles + 1] entry range of each tile
+  const int* ek;         // k of each entry (ascending within a tile)
+  const int* emask;      // bit r: tile row r visits k
+  const u64* ew;         // [entry][nl][16] weight of each tile row: the residue, as fp64 bits below 2^42
+  const u64* ews;        // [entry][nl][16] Shoup companions (primes of 2^42 and above)
+  int nl;                // primes of B and of the weight tables
+  u64* D;                // [output][2][nl][N] sums, NTT domain
+};
+// every product of the batch, in one launch per arithmetic (fp64, integer)
+int launch_plain_batch(const sfhe_ctx* c, const PlainBatch& pb, hipStream_t s);
+// D[2][nl][N] += w B[slot] for one product (the one-launch-per-product form)
+int launch_plain_product(const sfhe_ctx* c, const u64* B, int64_t nB, int64_t slot, const u64* w, const u64* ws,
+                         u64* D, int nl, hipStream_t s);
 
 // key switch of d2 rows (batch stride d2stride), result added into out
 // (batch stride ostride, [2][nl][N]) if add_in, else written.

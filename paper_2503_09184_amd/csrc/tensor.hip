@@ -2,7 +2,7 @@
 // step of Algorithm 1): d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 per prime
 // and coefficient, one product at a time (per-product form) or summed over
 // every visited k of an output before any reduction (lazy form).
-#include "internal.hpp"
+#include "fparith.hpp"
 
 namespace sfhe {
 
@@ -64,36 +64,6 @@ __global__ void tensor_gather_kernel(int nl, const u64* A, int64_t nA, const u64
 // block b takes 64-coefficient chunk (b mod 8) of a 512-coefficient slab; a
 // slab's A and B stay resident in the Infinity Cache while every output tile
 // of the slab is computed, and each XCD's L2 sees one 64-coefficient chunk.
-
-// fp64 residue product: a*b - k*q exactly, with k = rint(a*b/q); |result| <= 1.5 q.
-// Exact for integers a, b < 2^44 and q < 2^42 (2Prod via fma; h - k q and
-// the sum with the rounding error are integers below 2^53).
-__device__ __forceinline__ double fp_mulmod_lazy(double a, double b, double q, double qinv) {
-  const double h = a * b;
-  const double l = fma(a, b, -h);
-  const double k = rint(h * qinv);
-  return fma(-k, q, h) + l;
-}
-// reduce an exact integer-valued double |x| < 2^53 to [0, q)
-__device__ __forceinline__ u64 fp_final(double x, double q, double qinv) {
-  const double k = floor(x * qinv);
-  double r = fma(-k, q, x);
-  r = r < 0.0 ? r + q : r;
-  r = r >= q ? r - q : r;
-  return f64_to_u52(r);
-}
-// |x| < 2^53 exact integer -> congruent value of magnitude <= q / 2 + 1
-__device__ __forceinline__ double fp_fold(double x, double q, double qinv) { return fma(-rint(x * qinv), q, x); }
-
-struct FpLimb {
-  int limb;
-  double q, qinv;
-};
-
-struct FpLimbs {
-  int n;
-  FpLimb l[kMaxBasis];
-};
 
 constexpr int kWavesPerBlock = 8;
 constexpr int kSegEntries = 128;   // tile entries held in LDS at a time

@@ -28,7 +28,10 @@ EXPORTED = [
     "sfhe_encrypt_matrix", "sfhe_matmul", "sfhe_decrypt_matrix", "sfhe_export_ct",
     "sfhe_matrix_info", "sfhe_last_stats", "sfhe_set_profiling", "sfhe_mat_destroy", "sfhe_last_error",
     "sfhe_ntt", "sfhe_tensor", "sfhe_keyswitch", "sfhe_rescale",
+    "sfhe_encode_matrix", "sfhe_matmul_plain", "sfhe_matmul_plain_batch",
 ]
+
+PLAIN_LAUNCH = {"fused": 0, "per_product": 1}
 
 
 class SfheError(RuntimeError):
@@ -98,6 +101,11 @@ def lib():
         L.sfhe_tensor.argtypes = [vp, i32, vp, vp, vp, i32, vp]
         L.sfhe_keyswitch.argtypes = [vp, i32, vp, vp, i32, vp]
         L.sfhe_rescale.argtypes = [vp, i32, vp, vp, i32, vp]
+        L.sfhe_encode_matrix.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, i32, i64, ctypes.c_int, i32,
+                                         ctypes.POINTER(vp)]
+        L.sfhe_matmul_plain.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.sfhe_matmul_plain_batch.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp,
+                                              ctypes.POINTER(vp)]
         _lib = L
     return _lib
 
@@ -210,6 +218,30 @@ class Context:
         _check(lib().sfhe_matmul(self._h, A.handle, B.handle, SCHED[sched], _stream_handle(stream),
                                  ctypes.byref(h)))
         return Matrix(self, h)
+
+    # ---- plaintext weights times encrypted values -----------------------
+    def encode_weights(self, vals, enc, log2_scale_w=40):
+        """Plaintext weight matrix (constant-polynomial weights at scale 2^log2_scale_w)."""
+        v = np.ascontiguousarray(vals, dtype=np.float64)
+        rows, cols = v.shape
+        h = ctypes.c_void_p()
+        _check(lib().sfhe_encode_matrix(self._h, v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), rows, cols,
+                                        cols, ENC[enc], int(log2_scale_w), ctypes.byref(h)))
+        return Matrix(self, h)
+
+    def matmul_plain(self, W, B, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().sfhe_matmul_plain(self._h, W.handle, B.handle, _stream_handle(stream), ctypes.byref(h)))
+        return Matrix(self, h)
+
+    def matmul_plain_batch(self, Ws, Bs, launch="fused", stream=None):
+        n = len(Ws)
+        assert len(Bs) == n
+        wh = (ctypes.c_void_p * n)(*[W.handle.value for W in Ws])
+        bh = (ctypes.c_void_p * n)(*[B.handle.value for B in Bs])
+        out = (ctypes.c_void_p * n)()
+        _check(lib().sfhe_matmul_plain_batch(self._h, n, wh, bh, PLAIN_LAUNCH[launch], _stream_handle(stream), out))
+        return [Matrix(self, ctypes.c_void_p(out[x])) for x in range(n)]
 
     def set_profiling(self, on):
         _check(lib().sfhe_set_profiling(self._h, 1 if on else 0))
