@@ -119,6 +119,88 @@ def cpu_baseline(P, A, Bm, seed, threads, target_s=15.0):
             "seconds": secs, "products": products}
 
 
+# plaintext weights times encrypted values: one output's sum (five primes,
+# two polys) and its rescaled result (four primes), and one stored ciphertext
+PLAIN_SUM_MIB, PLAIN_OUT_MIB, PLAIN_CT_MIB = 1.25, 1.0, 1.25
+
+
+def ctpt_leg(torch, sfhe, W, count=32):
+    """The uneven batch of plaintext-weight products: count independent W B
+    with M, K, Nc drawn from {32, 64, 128, 256} and W's zero fraction uniform
+    on [0.5, 0.9], N = 2^14, B encrypted per element.  The whole batch does not
+    fit in HBM at once (about 1.4 TB of operands, sums and results), so it runs
+    in waves admitted by memory: a job whose operands, sums and results exceed
+    the wave budget is split into column blocks of B, and each wave is one
+    fused batch call.  Encryption and encoding are outside the timed calls.
+    The one-launch-per-product form is timed on the job with the fewest
+    products, beside the fused form on that job."""
+    P = W.PARAMS["plain_n16384"]
+    cfg = 4
+    ctx = sfhe.Context(**P)
+    ctx.keygen(W.key_seed(cfg))
+    jobs = W.uneven_batch(W.workload_seed(cfg), count)
+    free, _ = torch.cuda.mem_get_info()
+    budget_mib = min(0.45 * free / 2 ** 20, 120 * 1024.0)
+    units = []   # (job, M, K, col0, ncols, sparsity)
+    for jn, (M, K, Nc, s) in enumerate(jobs):
+        per_col = K * PLAIN_CT_MIB + M * (PLAIN_SUM_MIB + PLAIN_OUT_MIB)
+        blk = max(1, min(Nc, int(budget_mib // per_col)))
+        for c0 in range(0, Nc, blk):
+            units.append((jn, M, K, c0, min(blk, Nc - c0), s))
+    waves, cur, used = [], [], 0.0
+    for u in units:
+        need = u[4] * (u[2] * PLAIN_CT_MIB + u[1] * (PLAIN_SUM_MIB + PLAIN_OUT_MIB))
+        if cur and used + need > budget_mib:
+            waves.append(cur)
+            cur, used = [], 0.0
+        cur.append(u)
+        used += need
+    if cur:
+        waves.append(cur)
+    ops = {jn: W.operands(M, K, Nc, s, W.workload_seed(cfg) + 1 + jn) for jn, (M, K, Nc, s) in enumerate(jobs)}
+    total_ms, products, launches, wall = 0.0, 0, 0, 0.0
+    for wn, wave in enumerate(waves):
+        Ws = [ctx.encode_weights(ops[jn][0], "csr", 40) for (jn, M, K, c0, nc, s) in wave]
+        Bs = [ctx.encrypt(ops[jn][1][:, c0:c0 + nc], "dense", W.enc_seed(cfg, 1) + jn, 1)
+              for (jn, M, K, c0, nc, s) in wave]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Cs = ctx.matmul_plain_batch(Ws, Bs, "fused")
+        st = ctx.last_stats()
+        wall += time.perf_counter() - t0
+        total_ms += st.ms
+        products += st.products
+        launches += st.tensor_launches
+        log("ctpt wave %d/%d: %d products in %d units, %.1f ms" % (wn + 1, len(waves), st.products, len(wave), st.ms))
+        for x in Cs + Bs + Ws:
+            x.close()
+        del Cs, Bs, Ws
+    # one launch per product against the fused form, on the smallest job
+    jn = min(range(len(jobs)), key=lambda x: int(np.count_nonzero(ops[x][0])) * jobs[x][2])
+    Wm = ctx.encode_weights(ops[jn][0], "csr", 40)
+    Bm = ctx.encrypt(ops[jn][1], "dense", W.enc_seed(cfg, 1) + jn, 1)
+    sample = {"job": list(jobs[jn][:3]), "sparsity": jobs[jn][3]}
+    for mode in ("fused", "per_product"):
+        ctx.matmul_plain_batch([Wm], [Bm], mode)[0].close()   # warm-up
+        C = ctx.matmul_plain_batch([Wm], [Bm], mode)[0]
+        stx = ctx.last_stats()
+        C.close()
+        sample[mode + "_ms"] = stx.ms
+        sample["products"] = int(stx.products)
+        sample[mode + "_launches"] = int(stx.tensor_launches)
+    sample["fused_over_per_product"] = sample["per_product_ms"] / sample["fused_ms"]
+    log("ctpt per-product launches on %s: %.2f ms vs fused %.2f ms" %
+        (sample["job"], sample["per_product_ms"], sample["fused_ms"]))
+    Wm.close()
+    Bm.close()
+    ctx.close()
+    torch.cuda.empty_cache()
+    return {"matmuls": len(jobs), "shapes_MKN_sparsity": [list(j) for j in jobs], "waves": len(waves),
+            "units": len(units), "products": int(products), "ms": total_ms,
+            "ctpt_mults_per_s": products / (total_ms / 1e3), "fused_launches": int(launches),
+            "host_wall_s": wall, "per_product_launch_sample": sample}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,7 +209,7 @@ def main():
     ap.add_argument("--sparsity", type=float, default=0.5)
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--only", default="", help="comma list of extra legs to run (default all): "
-                    "s90,dense,ell,naive,per_product,cpu")
+                    "s90,dense,ell,naive,per_product,ctpt,cpu")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -230,6 +312,15 @@ def main():
             leg("lazy_dense_90_operands", A90, "dense", "lazy", 1)
     if run("per_product"):
         leg("per_product_csr_50", A, "csr", "per_product", 1)
+    EA.close()
+    EB.close()
+    torch.cuda.empty_cache()
+    if run("ctpt"):
+        log("plaintext weights x encrypted values: uneven batch of 32 products")
+        legs["ctpt_uneven_batch"] = ctpt_leg(torch, sfhe, W)
+        log("ctpt: %d products in %.1f ms, %.4g ct-pt mults/s" %
+            (legs["ctpt_uneven_batch"]["products"], legs["ctpt_uneven_batch"]["ms"],
+             legs["ctpt_uneven_batch"]["ctpt_mults_per_s"]))
 
     cpu = None
     if not args.no_cpu and run("cpu"):

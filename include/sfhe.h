@@ -209,7 +209,9 @@ typedef enum {
  * Both give the same bits.  The sums of all outputs are held on the device
  * at once (2 (L) N words per output): SFHE_E_NOMEM if they do not fit.  C
  * has count entries; on failure every entry is NULL.  sfhe_last_stats
- * reports the device time of the whole call, products and launches. */
+ * reports the device time of the products and rescales (after the result,
+ * scratch and table allocations and uploads), the products and the product
+ * launches. */
 int sfhe_matmul_plain_batch(sfhe_ctx* ctx, int32_t count, const sfhe_mat* const* W, const sfhe_mat* const* B,
                             sfhe_plain_launch launch, void* stream, sfhe_mat** C);
 

