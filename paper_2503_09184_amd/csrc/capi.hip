@@ -1008,7 +1008,9 @@ static int plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, co
     const int64_t cnt = (int64_t)C[n]->n_ct;
     for (int64_t o0 = 0; o0 < cnt && !rc; o0 += 2048) {
       const OutLayout ol{C[n]->data.ptr, 0, true, C[n]->n_ct, o0};
-      rc = rescale_batch(c, lev, D.ptr + (jobs[n].d0 + o0) * dw, dw, ol, std::min<int64_t>(2048, cnt - o0), s);
+      const int64_t m = std::min<int64_t>(2048, cnt - o0);
+      const u64* Ds = D.ptr + (jobs[n].d0 + o0) * dw;
+      rc = c->logN == 14 ? rescale_n14(c, lev, Ds, dw, ol, m, s) : rescale_batch(c, lev, Ds, dw, ol, m, s);
     }
   }
   if (!rc) {

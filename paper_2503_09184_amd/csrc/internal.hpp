@@ -253,6 +253,9 @@ int rescale_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, OutLayou
 // (stride dw words; rows d0, d1, d2 of lev + 1 primes, NTT domain) in four
 // fused transform kernels; the result goes to out (NTT domain, lev primes)
 int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s);
+// N = 2^14 only: Rescale((d0, d1)) for n sums D[b] (stride dw words, rows d0,
+// d1 of lev + 1 primes, NTT domain) in two transform kernels
+int rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s);
 bool keyswitch_rescale_n14_supported(const sfhe_ctx* c);
 // chunked out[oidx[o]] += sum of limb-major t[p] for p in seg[o] .. seg[o+1]-1 (rows [2][nl][N])
 int launch_segment_sum(const sfhe_ctx* c, int nl, const u64* t, u64* out, int64_t n_ct, const int* d_seg,

@@ -492,10 +492,128 @@ int launch_ks14(sfhe_ctx* c, const Ks14Args& a, int ndig, OutLayout out, int64_t
   return SFHE_OK;
 }
 
+// ---------------------------------------------------------------- rescale alone
+// The rescale of degree-1 sums that need no key switch (plaintext weights
+// times encrypted values): RS-A (b, p) r = iNTT(d_lev), the last prime in
+// coefficients; RS-B (b, p, i), i < lev: C_i = (d_i - NTT([centered r]_{q_i}))
+// q_lev^-1, the lift taken while the row is loaded.
+struct Rs14Args {
+  const u64* D;          // [n] x dw words: d0, d1 rows of nl primes (NTT domain)
+  int64_t dw;
+  u64* r;                // [n][2][N] last prime in coefficients
+  const RescaleConst* rs;
+  int lev, nl;
+};
+
+template <typename Ar>
+__device__ __forceinline__ void rsa_body(const Rs14Args& a, const DevParams& dp, int b, int p, void* lds) {
+  typedef typename Ar::Val Val;
+  const int t = threadIdx.x;
+  const PrimeDev& P = dp.pr[a.lev];
+  const Ar ar(P, true);
+  Val v[32];
+  load_c(ar, v, a.D + (int64_t)b * a.dw + (int64_t)(p * a.nl + a.lev) * kN, t);
+  n14::inverse(ar, v, reinterpret_cast<Val*>(lds), t);
+  u64* o = a.r + ((int64_t)b * 2 + p) * kN;
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    o[pos_a(t, u)] = ar.out_inv(v[u], P);
+    group_fence<8>(u);
+  }
+}
+
+__global__ void __launch_bounds__(n14::kThreads, 4) rs14_a_kernel(Rs14Args a, DevParams dp) {
+  extern __shared__ u64 lds[];
+  const int b = blockIdx.x >> 1, p = blockIdx.x & 1;
+  if (dp.pr[a.lev].q < (1ull << 42))
+    rsa_body<NttFp>(a, dp, b, p, lds);
+  else
+    rsa_body<NttInt>(a, dp, b, p, lds);
+}
+
+template <typename Ar>
+__device__ __forceinline__ void rsb_body(const Rs14Args& a, const DevParams& dp, const OutLayout& ol, int b, int p, int i,
+                                         void* lds) {
+  typedef typename Ar::Val Val;
+  const int t = threadIdx.x, lev = a.lev;
+  const PrimeDev& P = dp.pr[i];
+  const u64 q = P.q, ql = dp.pr[lev].q;
+  const Ar ar(P, false);
+  const u64* rr = a.r + ((int64_t)b * 2 + p) * kN;
+  Val v[32];
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    // centered lift of the last prime, reduced mod q_i
+    const u64 c = rr[pos_a(t, u)];
+    const bool neg = c > (ql - 1) / 2;
+    const u64 mag = neg ? ql - c : c;
+    u64 x = mag < q ? mag : reduce_wide(U128{mag, 0}, q, P.mu_hi, P.mu_lo);
+    x = (neg && x) ? q - x : x;
+    v[u] = ar.in(x);
+  }
+  n14::forward(ar, v, reinterpret_cast<Val*>(lds), t);
+  const u64* d = a.D + (int64_t)b * a.dw + (int64_t)(p * a.nl + i) * kN;
+  const u64 qi = a.rs->qinv[i], qis = a.rs->qinv_s[i];
+  const int tt = after(t, v[15], v[31]);
+  if (ol.chunked) {
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      const int x = pos_c(tt, r);
+      ol.base[chunk_index(ol.elem_base + b, p, i, x, ol.n_ct, kN >> 6)] = mul_shoup(sub_mod(d[x], ar.fwd_res(v[r]), q), qi, qis, q);
+      group_fence<4>(r);
+    }
+  } else {
+    u64* dst = ol.base + (int64_t)b * ol.stride + ((int64_t)p * lev + i) * kN;
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      const int x = pos_c(tt, r);
+      dst[x] = mul_shoup(sub_mod(d[x], ar.fwd_res(v[r]), q), qi, qis, q);
+      group_fence<4>(r);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(n14::kThreads, 4) rs14_b_kernel(Rs14Args a, OutLayout ol, DevParams dp) {
+  extern __shared__ u64 lds[];
+  const int lev = a.lev;
+  const int b = blockIdx.x / (2 * lev);
+  const int rem = blockIdx.x % (2 * lev);
+  const int p = rem / lev, i = rem % lev;
+  if (dp.pr[i].q < (1ull << 42))
+    rsb_body<NttFp>(a, dp, ol, b, p, i, lds);
+  else
+    rsb_body<NttInt>(a, dp, ol, b, p, i, lds);
+}
+
 }  // namespace
 
 bool keyswitch_rescale_n14_supported(const sfhe_ctx* c) {
   return c->logN == n14::kLogN && c->alpha >= 1 && c->alpha <= 4 && c->dnum <= 4;
+}
+
+int rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s) {
+  if (n <= 0) return SFHE_OK;
+  if (c->logN != n14::kLogN) { set_error("rescale_n14: N = 2^14 only"); return SFHE_E_INVALID_ARG; }
+  if (lev < 1) { set_error("rescale: level 0 has no prime to drop"); return SFHE_E_LEVEL; }
+  if (n * 2 * lev > 0x7FFFFFFF) { set_error("rescale: batch too large"); return SFHE_E_INVALID_ARG; }
+  const size_t lds = (size_t)n14::kLdsWords * sizeof(u64);
+  static bool attr = false;
+  if (!attr) {
+    SFHE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rs14_a_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    SFHE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rs14_b_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  DevBuf<u64> r;
+  if (!r.alloc(&c->alloc, (size_t)n * 2 * kN)) { set_error("rescale: device allocation failed"); return SFHE_E_NOMEM; }
+  Rs14Args a{D, dw, r.ptr, c->d_rescale.ptr + lev, lev, lev + 1};
+  const dim3 blk(n14::kThreads);
+  hipLaunchKernelGGL(rs14_a_kernel, dim3((unsigned)(n * 2)), blk, lds, s, a, c->dp);
+  SFHE_HIP(hipGetLastError());
+  hipLaunchKernelGGL(rs14_b_kernel, dim3((unsigned)(n * 2 * lev)), blk, lds, s, a, out, c->dp);
+  SFHE_HIP(hipGetLastError());
+  return SFHE_OK;
 }
 
 int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s) {

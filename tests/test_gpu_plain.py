@@ -161,3 +161,18 @@ def test_plain_realistic_sampled_outputs(torch_cuda, sparsity):
     cts, _, _ = orc.matmul_plain(Wt, B, "csr", sb, 40, outputs=sample, threads=_threads())
     for n, (i, j) in enumerate(sample):
         assert np.array_equal(ctx.export_ct(C, i, j), cts[n]), (i, j)
+
+
+def test_plain_n14_large_last_prime(torch_cuda):
+    """N = 2^14 with a 60-bit last prime above the 40-bit ones: the rescale's
+    centered lift must reduce the last prime's residues modulo each smaller
+    prime (the fused N = 2^14 rescale)."""
+    P = dict(log_n=14, q_bits=[40, 41, 60], p_bits=[60], dnum=3)
+    ctx, orc = pair(P, 23)
+    Wt, B = W.operands(20, 9, 5, 0.5, 54)
+    note("plain N=2^14 large last prime")
+    C = ctx.matmul_plain(ctx.encode_weights(Wt, "ell", 40), ctx.encrypt(B, "dense", 13, 1))
+    sample = [(0, 0), (19, 4), (7, 2), (16, 1)]
+    cts, _, _ = orc.matmul_plain(Wt, B, "ell", 13, 40, outputs=sample, threads=_threads())
+    for n, (i, j) in enumerate(sample):
+        assert np.array_equal(ctx.export_ct(C, i, j), cts[n]), (i, j)
