@@ -89,6 +89,11 @@ def lib():
                                  ctypes.c_uint64, ctypes.c_uint64, _i32p, _i32p, ctypes.c_int,
                                  ctypes.c_int, _u64p, _f64p, _f64p]
         L.orc_matmul.restype = ctypes.c_int
+        L.orc_matmul2.argtypes = [ctypes.c_void_p, _f64p, ctypes.c_int, ctypes.c_int, _f64p, ctypes.c_int,
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                  ctypes.c_uint64, ctypes.c_uint64, _i32p, _i32p, ctypes.c_int,
+                                  ctypes.c_int, _u64p, _f64p, _f64p]
+        L.orc_matmul2.restype = ctypes.c_int
         L.orc_weight.argtypes = [ctypes.c_double, ctypes.c_double, _i64p]
         L.orc_weight.restype = ctypes.c_int
         L.orc_matmul_plain.argtypes = [ctypes.c_void_p, _f64p, ctypes.c_int, ctypes.c_int, _f64p, ctypes.c_int,
@@ -261,9 +266,10 @@ class Oracle:
         return ks[:n].copy()
 
     def matmul(self, A, B, enc, sched, seedA, seedB, outputs=None, threads=1,
-               opA=0, opB=1, decrypt=True):
+               opA=0, opB=1, decrypt=True, encB="dense"):
         """Selected outputs of the encrypted product.  Returns (cts, vals, seconds):
-        cts[n] = [2][L-1][N] coefficient-domain residues of output `outputs[n]`."""
+        cts[n] = [2][L-1][N] coefficient-domain residues of output `outputs[n]`.
+        encB is the right operand's encoding: a sparse one skips its zeros too."""
         A = np.ascontiguousarray(A, dtype=np.float64)
         B = np.ascontiguousarray(B, dtype=np.float64)
         M, K = A.shape
@@ -277,7 +283,7 @@ class Oracle:
         out = np.zeros((nout, 2, self.L - 1, self.n), dtype=np.uint64)
         vals = np.zeros(nout, dtype=np.float64)
         secs = np.zeros(1, dtype=np.float64)
-        rc = lib().orc_matmul(self._h, _p(A, _f64p), M, K, _p(B, _f64p), Nc, ENC[enc], SCHED[sched],
+        rc = lib().orc_matmul2(self._h, _p(A, _f64p), M, K, _p(B, _f64p), Nc, ENC[enc], ENC[encB], SCHED[sched],
                               ctypes.c_uint64(seedA), ctypes.c_uint64(opA), ctypes.c_uint64(seedB),
                               ctypes.c_uint64(opB), _p(rows, _i32p), _p(cols, _i32p), nout,
                               int(threads), _p(out, _u64p),

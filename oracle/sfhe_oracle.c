@@ -36,6 +36,9 @@
  *       primitive 2N-th root of unity mod q.
  *   R8  plaintext weights (the server-side weights of Sec. 3.3.2) are
  *       constant polynomials nearbyint(w * 2^sw); see orc_weight().
+ *   R9  both operands sparse (the naive scheme's two masks, Sec. 3.3.2, and
+ *       CSR/ELLPACK on the right operand): output (i, j) visits the k of row
+ *       i whose B_kj the right operand's encoding stores; see out_ks().
  */
 #include <math.h>
 #include <pthread.h>
@@ -669,6 +672,30 @@ static int row_ks(const orc_struct* S, int i, int* ks) {
   return n;
 }
 
+/* whether the encoding stores element (r, col) as a value to multiply: every
+ * element for dense, the nonzeros for the three sparse schemes */
+static int stores(const orc_struct* S, int r, int col) {
+  switch (S->enc) {
+    case ORC_ENC_DENSE: return 1;
+    case ORC_ENC_NAIVE: return !S->zero[(size_t)r * S->K + col];
+    case ORC_ENC_CSR:
+      for (int p = S->row_ptr[r]; p < S->row_ptr[r + 1]; p++) if (S->col_idx[p] == col) return 1;
+      return 0;
+    case ORC_ENC_ELL:
+      for (int s = 0; s < S->ell_w; s++) if (S->ell_col[(size_t)r * S->ell_w + s] == col) return 1;
+      return 0;
+  }
+  return 0;
+}
+
+/* the k that output (i, j) visits: row i's visited k (ascending) whose B_kj
+ * the right operand's encoding stores (R9) */
+static int out_ks(const orc_struct* S, const orc_struct* SB, int i, int j, int* ks) {
+  int n = row_ks(S, i, ks), m = 0;
+  for (int x = 0; x < n; x++) if (stores(SB, ks[x], j)) ks[m++] = ks[x];
+  return m;
+}
+
 int orc_row_ks(const double* A, int M, int K, int enc, int i, int* ks) {
   orc_struct S; struct_build(&S, A, M, K, enc);
   int n = row_ks(&S, i, ks);
@@ -679,6 +706,7 @@ int orc_row_ks(const double* A, int M, int K, int enc, int i, int* ks) {
 typedef struct {
   const orc_ctx* c;
   const orc_struct* S;
+  const orc_struct* SB;   /* the right operand's structure */
   int M, K, Nc, sched, nthreads, tid;
   u64** encA;      /* [M*K] encrypted elements, NTT domain (NULL if unused) */
   u64** encB;      /* [K*Nc] */
@@ -692,7 +720,7 @@ static void mm_output(const mm_job* J, int i, int j, u64* o) {
   int N = c->N, L = c->L, top = L - 1;
   size_t ct_top = (size_t)2 * L * N, ct_out = (size_t)2 * top * N;
   int* ks = malloc(sizeof(int) * (J->K + 1));
-  int nk = row_ks(J->S, i, ks);
+  int nk = out_ks(J->S, J->SB, i, j, ks);
   memset(o, 0, sizeof(u64) * ct_out);                       /* R6: trivial zero */
   if (nk == 0) { free(ks); return; }
   u64* d = malloc(sizeof(u64) * 3 * L * N);
@@ -815,19 +843,20 @@ static double now_s(void) { struct timespec ts; clock_gettime(CLOCK_MONOTONIC, &
  * [nout][2][L-1][N] coefficient-domain residues; vals (nullable) the decrypted
  * values; seconds (nullable) the wall time of the multiply stage only
  * (encryption and decryption excluded, Sec. 4.1). */
-int orc_matmul(const orc_ctx* c, const double* A, int M, int K, const double* B, int Nc,
-               int enc, int sched, u64 seedA, u64 opA, u64 seedB, u64 opB,
-               const int* orow, const int* ocol, int nout, int nthreads,
-               u64* out, double* vals, double* seconds) {
+int orc_matmul2(const orc_ctx* c, const double* A, int M, int K, const double* B, int Nc,
+                int enc, int enc_b, int sched, u64 seedA, u64 opA, u64 seedB, u64 opB,
+                const int* orow, const int* ocol, int nout, int nthreads,
+                u64* out, double* vals, double* seconds) {
   if (!c->has_keys || c->L < 2 || nthreads < 1) return -1;
   for (int n = 0; n < nout; n++) if (orow[n] < 0 || orow[n] >= M || ocol[n] < 0 || ocol[n] >= Nc) return -2;
   orc_struct S; struct_build(&S, A, M, K, enc);
+  orc_struct SB; struct_build(&SB, B, K, Nc, enc_b);
   size_t ct_top = (size_t)2 * c->L * c->N;
   u64** encA = calloc((size_t)M * K, sizeof(u64*));
   u64** encB = calloc((size_t)K * Nc, sizeof(u64*));
   int* ks = malloc(sizeof(int) * (K + 1));
   for (int n = 0; n < nout; n++) {
-    int nk = row_ks(&S, orow[n], ks);
+    int nk = out_ks(&S, &SB, orow[n], ocol[n], ks);
     for (int x = 0; x < nk; x++) {
       size_t ia = (size_t)orow[n] * K + ks[x], ib = (size_t)ks[x] * Nc + ocol[n];
       if (!encA[ia]) encA[ia] = malloc(sizeof(u64) * ct_top);
@@ -842,7 +871,7 @@ int orc_matmul(const orc_ctx* c, const double* A, int M, int K, const double* B,
   int T = nthreads > 256 ? 256 : nthreads;
   double t0 = now_s();
   for (int t = 0; t < T; t++) {
-    jobs[t] = (mm_job){c, &S, M, K, Nc, sched, T, t, encA, encB, orow, ocol, nout, out};
+    jobs[t] = (mm_job){c, &S, &SB, M, K, Nc, sched, T, t, encA, encB, orow, ocol, nout, out};
     pthread_create(&th[t], NULL, mm_worker, &jobs[t]);
   }
   for (int t = 0; t < T; t++) pthread_join(th[t], NULL);
@@ -859,7 +888,17 @@ int orc_matmul(const orc_ctx* c, const double* A, int M, int K, const double* B,
   for (size_t x = 0; x < (size_t)K * Nc; x++) free(encB[x]);
   free(encA); free(encB);
   struct_free(&S);
+  struct_free(&SB);
   return 0;
+}
+
+/* the right operand dense (the hot path's configuration) */
+int orc_matmul(const orc_ctx* c, const double* A, int M, int K, const double* B, int Nc,
+               int enc, int sched, u64 seedA, u64 opA, u64 seedB, u64 opB,
+               const int* orow, const int* ocol, int nout, int nthreads,
+               u64* out, double* vals, double* seconds) {
+  return orc_matmul2(c, A, M, K, B, Nc, enc, ORC_ENC_DENSE, sched, seedA, opA, seedB, opB, orow, ocol, nout, nthreads,
+                     out, vals, seconds);
 }
 
 /* ------------------------------------------------------------------ */

@@ -562,3 +562,45 @@ def test_plain_product_schemes_bit_identical_and_dense_at_zero_sparsity():
     d = o.matmul_plain(W0, B0, "dense", 3, threads=2, decrypt=False)[0]
     c = o.matmul_plain(W0, B0, "csr", 3, threads=2, decrypt=False)[0]
     assert np.array_equal(d, c)
+
+
+# ------------------------------------ both operands sparse (R9, Sec. 3.3.2)
+def test_both_sparse_equals_left_only_product_with_the_zeros_moved():
+    """Output (i, j) with a sparse right operand visits the k where A_ik and
+    B_kj are both nonzero: the same as the left-only product whose row i has
+    its entries at B_kj == 0 zeroed (a different code path), bit for bit."""
+    o = make(SMALL_HYBRID, seed=12)
+    A, B = W.operands(5, 9, 4, 0.3, 70)
+    B[W.uniform_matrix(9, 4, 71) < 0.0] = 0.0           # about half of B zero
+    for sched in ("lazy", "per_product"):
+        both = o.matmul(A, B, "csr", sched, 3, 4, encB="csr", decrypt=False)[0]
+        for (i, j) in [(0, 0), (2, 3), (4, 1)]:
+            A2 = A.copy()
+            A2[i, B[:, j] == 0.0] = 0.0
+            ref = o.matmul(A2, B, "csr", sched, 3, 4, outputs=[(i, j)], decrypt=False)[0][0]
+            assert np.array_equal(both[i * 4 + j], ref), (sched, i, j)
+
+
+def test_both_sparse_schemes_bit_identical_and_dense_at_zero_sparsity():
+    o = make(TINY_HYBRID, seed=13)
+    A, B = W.operands(6, 7, 5, 0.4, 72)
+    B[W.uniform_matrix(7, 5, 73) < -0.2] = 0.0
+    B[:, 2] = 0.0                                      # a column with no product
+    for sched in ("lazy", "per_product"):
+        outs = {e: o.matmul(A, B, "ell", sched, 5, 6, encB=e, decrypt=False)[0] for e in ("naive", "csr", "ell")}
+        assert np.array_equal(outs["naive"], outs["csr"]) and np.array_equal(outs["csr"], outs["ell"])
+        assert not outs["csr"].reshape(6, 5, -1)[:, 2].any()         # trivial zeros
+    B0 = W.uniform_matrix(7, 5, 74)
+    for sched in ("lazy", "per_product"):
+        d = o.matmul(A, B0, "csr", sched, 5, 6, encB="dense", decrypt=False)[0]
+        c = o.matmul(A, B0, "csr", sched, 5, 6, encB="naive", decrypt=False)[0]
+        assert np.array_equal(d, c)
+
+
+def test_both_sparse_decrypts_to_fp64_product():
+    o = make(SMALL, seed=5)
+    A, B = W.operands(6, 8, 5, 0.5, 75)
+    B[W.uniform_matrix(8, 5, 76) < 0.0] = 0.0
+    for sched in ("lazy", "per_product"):
+        _, vals, _ = o.matmul(A, B, "naive", sched, 1, 2, encB="naive", threads=3)
+        assert np.max(np.abs(vals - (A @ B).ravel())) < 1e-6
