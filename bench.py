@@ -209,7 +209,7 @@ def main():
     ap.add_argument("--sparsity", type=float, default=0.5)
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--only", default="", help="comma list of extra legs to run (default all): "
-                    "s90,dense,ell,naive,per_product,ctpt,cpu")
+                    "s90,dense,ell,naive,per_product,both,ctpt,cpu")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -312,6 +312,20 @@ def main():
             leg("lazy_dense_90_operands", A90, "dense", "lazy", 1)
     if run("per_product"):
         leg("per_product_csr_50", A, "csr", "per_product", 1)
+    if run("both"):
+        # both operands sparse (the paper's own setting): B with half its
+        # entries zero, as a ReLU leaves activations, CSR on both sides
+        Bz = Bm.copy()
+        Bz[np.random.default_rng(W.workload_seed(cfg_id) + 5).random(Bz.shape) < 0.5] = 0.0
+        EBz = ctx.encrypt(Bz, "csr", sb, 1)
+        EAx = ctx.encrypt(A, "csr", sa, 0)
+        tt, stx, _, _ = timed(ctx, torch, EAx, EBz, "lazy", args.steps, 1)
+        m = float(np.mean(tt))
+        legs["lazy_csr_both_50"] = {"ms": m, "products": int(stx.products), "ct_mults_per_s": stx.products / (m / 1e3),
+                                    "keyswitches": int(stx.keyswitches), "b_zero_fraction": float(np.mean(Bz == 0.0))}
+        log("lazy_csr_both_50: %.2f ms, %d products" % (m, stx.products))
+        EAx.close()
+        EBz.close()
     EA.close()
     EB.close()
     torch.cuda.empty_cache()
@@ -337,6 +351,9 @@ def main():
         speedups["sparse90_over_dense"] = legs["lazy_dense_90_operands"]["ms"] / legs["lazy_csr_90"]["ms"]
     if "per_product_csr_50" in legs:
         speedups["lazy_over_per_product_50"] = legs["per_product_csr_50"]["ms"] / ms
+    if "lazy_csr_both_50" in legs and "lazy_dense_same_operands" in legs:
+        # the dense schedule's time does not depend on the values
+        speedups["both_sparse50_over_dense"] = legs["lazy_dense_same_operands"]["ms"] / legs["lazy_csr_both_50"]["ms"]
 
     out = {
         "metric": "ms per encrypted 128x128x128 matmul @50%/90% sparsity; ct-mults/s vs dense",

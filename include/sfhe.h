@@ -41,7 +41,7 @@ extern "C" {
 #define SFHE_E_SHAPE (-3)         /* A.cols != B.rows, index out of range           */
 #define SFHE_E_LEVEL (-4)         /* no prime left to rescale, level mismatch       */
 #define SFHE_E_SCALE (-5)         /* operand scales differ                         */
-#define SFHE_E_UNSUPPORTED (-6)   /* a sparse-encoded right operand, logN > 14 ... */
+#define SFHE_E_UNSUPPORTED (-6)   /* an operation the handle or ring does not support */
 #define SFHE_E_NOMEM (-7)         /* device or host allocation failed               */
 #define SFHE_E_DEVICE (-8)        /* a HIP call failed (its text is in last_error)  */
 #define SFHE_E_STATE (-9)         /* keys not generated yet                        */
@@ -150,10 +150,13 @@ int sfhe_encrypt_matrix(sfhe_ctx* ctx, const double* vals, int32_t rows, int32_t
                         sfhe_mat** out);
 
 /* C = A * B (Algorithm 1 at c = 1 with A's zeros skipped per its encoding).
- * A and B must be at the same level (>= 1) with equal scales, B DENSE.  The
- * result is a DENSE matrix one level lower with scale^2 / q_level.  Outputs
- * with no nonzero product are trivial zero ciphertexts.  The device time is
- * reported by sfhe_last_stats. */
+ * A and B must be at the same level (>= 1) with equal scales.  B may be of
+ * any encoding: with a sparse-encoded B (naive sparse, CSR, ELLPACK) a
+ * product is skipped when A_ik or B_kj is zero (the naive scheme's two masks,
+ * Sec. 3.3.2); a DENSE B multiplies every k of A's row.  The result is a DENSE
+ * matrix one level lower with scale^2 / q_level.  Outputs with no product
+ * are trivial zero ciphertexts.  The device time is reported by
+ * sfhe_last_stats. */
 int sfhe_matmul(sfhe_ctx* ctx, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched,
                 void* stream, sfhe_mat** C);
 

@@ -365,6 +365,33 @@ static void build_structure(sfhe_mat* m, const double* vals, int64_t ld, Push pu
   }
 }
 
+// stored slot of every element of a sparse-encoded matrix as a value to
+// multiply, -1 for a zero: [rows][cols] (the right operand's side of the
+// both-sparse product)
+static void value_slots(const sfhe_mat* m, std::vector<int>& out) {
+  out.assign((size_t)m->rows * m->cols, -1);
+  switch (m->enc) {
+    case SFHE_ENC_DENSE:
+      for (int64_t e = 0; e < (int64_t)m->rows * m->cols; ++e) out[e] = (int)e;
+      break;
+    case SFHE_ENC_NAIVE_SPARSE:
+      for (int64_t e = 0; e < (int64_t)m->rows * m->cols; ++e)
+        if (!((m->zero_mask[e >> 5] >> (e & 31)) & 1u)) out[e] = (int)e;
+      break;
+    case SFHE_ENC_CSR:
+      for (int r = 0; r < m->rows; ++r)
+        for (int p = m->row_ptr[r]; p < m->row_ptr[r + 1]; ++p) out[(size_t)r * m->cols + m->col_idx[p]] = p;
+      break;
+    case SFHE_ENC_ELL:
+      for (int r = 0; r < m->rows; ++r)
+        for (int x = 0; x < m->ell_w; ++x) {
+          const int col = m->ell_col[(size_t)r * m->ell_w + x];
+          if (col >= 0) out[(size_t)r * m->cols + col] = r * m->ell_w + x;
+        }
+      break;
+  }
+}
+
 }  // namespace sfhe
 
 using namespace sfhe;
@@ -587,8 +614,8 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
   if (A->plain || B->plain) { set_error("plaintext weights: use sfhe_matmul_plain"); return SFHE_E_UNSUPPORTED; }
   if (sched != SFHE_SCHED_PER_PRODUCT && sched != SFHE_SCHED_LAZY) { set_error("bad schedule"); return SFHE_E_INVALID_ARG; }
   if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
-  if (B->enc != SFHE_ENC_DENSE) { set_error("the right operand must be DENSE"); return SFHE_E_UNSUPPORTED; }
   if (A->cols != B->rows) { set_error("A.cols != B.rows"); return SFHE_E_SHAPE; }
+  if ((int64_t)B->rows * B->cols > 0x7FFFFFFF) { set_error("B too large"); return SFHE_E_INVALID_ARG; }
   if (A->level != B->level) { set_error("operand levels differ"); return SFHE_E_LEVEL; }
   if (A->level != c->L - 1) { set_error("operands must be at the top level"); return SFHE_E_LEVEL; }
   if (A->level < 1) { set_error("no prime left to rescale"); return SFHE_E_LEVEL; }
@@ -614,6 +641,11 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
   }
   std::vector<int64_t> visits(M);
   for (int i = 0; i < M; ++i) visits[i] = row_visits(A, i);
+  // a sparse right operand: products whose B_kj is zero are skipped too
+  const bool bsp = B->enc != SFHE_ENC_DENSE;
+  std::vector<int> bslot;
+  if (bsp) value_slots(B, bslot);
+  auto b_slot = [&](int k, int j) -> int64_t { return bsp ? bslot[(size_t)k * Nc + j] : (int64_t)k * Nc + j; };
   int64_t products = 0, keyswitches = 0, tensor_launches = 0, tensor_fp_launches = 0;
   c->prof_used = 0;
   c->prof_cat.clear();
@@ -664,12 +696,22 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
       i += nr;
     }
     tstart.push_back((int)ek.size());
-    DevBuf<int> d_ts, d_ek, d_em, d_es;
+    if (bsp) {   // products: the visited k whose B_kj is stored
+      products = 0;
+      for (int i = 0; i < M; ++i) {
+        if (visits[i] == 0) continue;
+        row_pairs(A, i, pairs);
+        for (auto& pr : pairs)
+          for (int j = 0; j < Nc; ++j) products += bslot[(size_t)pr.first * Nc + j] >= 0;
+      }
+    }
+    DevBuf<int> d_ts, d_ek, d_em, d_es, d_bs;
     DevBuf<u64> D;
     int64_t max_out = 0;
     for (auto& bt : batches) max_out = std::max<int64_t>(max_out, (int64_t)bt.nr * Nc);
     if (!upload(c, d_ts, tstart, s) || !upload(c, d_ek, ek, s) || !upload(c, d_em, emask, s) ||
-        !upload(c, d_es, eslot, s) || !D.alloc(&c->alloc, (size_t)std::max<int64_t>(max_out, 1) * dw)) {
+        !upload(c, d_es, eslot, s) || (bsp && !upload(c, d_bs, bslot, s)) ||
+        !D.alloc(&c->alloc, (size_t)std::max<int64_t>(max_out, 1) * dw)) {
       rc = SFHE_E_NOMEM;
       set_error("device allocation failed");
     }
@@ -686,6 +728,7 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
       tl.Nc = Nc;
       tl.nA = A->n_ct;
       tl.nB = B->n_ct;
+      tl.bslot = bsp ? d_bs.ptr : nullptr;
       const int64_t cnt = (int64_t)bt.nr * Nc;
       {
         StepTimer tm(c, s, kCatTensor);
@@ -779,6 +822,8 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
       for (int j = 0; j < Nc && !rc; ++j) {
         bool opened = false;
         for (auto& pr : pairs) {
+          const int64_t bs = b_slot(pr.first, j);
+          if (bs < 0) continue;   // B_kj is zero
           if ((int64_t)aidx.size() >= tile_max) {
             rc = flush();
             if (rc) break;
@@ -790,7 +835,7 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
             opened = true;
           }
           aidx.push_back((int)pr.second);
-          bidx.push_back(pr.first * Nc + j);
+          bidx.push_back((int)bs);
         }
       }
     }

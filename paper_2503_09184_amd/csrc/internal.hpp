@@ -200,6 +200,7 @@ struct TileList {
   int rows;             // output rows in the batch
   int Nc;               // output columns (= B columns)
   int64_t nA, nB;       // ciphertexts stored by A and B (chunked layout)
+  const int* bslot;     // [K][Nc] stored slot of B_kj, -1 if B_kj is zero; nullptr for a dense B
 };
 // D[pos * Nc + j][3][L][N] = sum over the visited k of tensor(A[row pos, k], B[k, j]);
 // the fp64 kernel's launch is bracketed by fp_start / fp_stop when non-null

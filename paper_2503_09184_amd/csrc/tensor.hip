@@ -150,7 +150,11 @@ struct ArithInt {   // q < 2^61: 128-bit integer sums, Karatsuba middle term
 // one B row (a column's poly), and every wave reads what it needs from LDS,
 // so each operand word is loaded from memory once per block and entry.
 // Global loads run two entries ahead of the multiplies.
-template <typename Arith, int RPW, int CPW>
+//
+// BSP: the right operand is sparse too (tl.bslot gives the stored slot of
+// B_kj, or -1 for a zero): a wave skips the columns whose B_kj is zero, so a
+// product is skipped when either operand is zero.
+template <typename Arith, int RPW, int CPW, bool BSP>
 __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const u64* A, const u64* B, u64* D,
                                                              FpLimbs fl, DevParams dp) {
   typedef typename Arith::Val Val;
@@ -209,6 +213,7 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   struct Stage {
     u64 b, a00, a01, a10, a11;
     int mask;
+    int cmask;   // bit c: column cbase + c has B_kj (always all ones for a dense B)
   };
   // the tile's entry list goes through LDS in segments, so that the loads two
   // entries ahead need no scalar memory round trip
@@ -222,7 +227,22 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
     const int k = __builtin_amdgcn_readfirstlane(km.x);
     st.mask = __builtin_amdgcn_readfirstlane(km.y);
     st.b = 0;
-    if (bload && jb < Nc) st.b = Bb[((int64_t)k * Nc + jb) * 64 + pb_off];
+    if constexpr (BSP) {
+      const int* bs_k = tl.bslot + (int64_t)k * Nc;
+      st.cmask = 0;
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int jc = h * kCols + cbase + c;
+        if (jc < Nc && bs_k[jc] >= 0) st.cmask |= 1 << c;
+      }
+      if (bload && jb < Nc) {
+        const int sl = bs_k[jb];
+        if (sl >= 0) st.b = Bb[(int64_t)sl * 64 + pb_off];
+      }
+    } else {
+      st.cmask = (1 << CPW) - 1;
+      if (bload && jb < Nc) st.b = Bb[((int64_t)k * Nc + jb) * 64 + pb_off];
+    }
     if ((st.mask >> arow0) & 1) {
       const u64* ap = Ab + (int64_t)__builtin_amdgcn_readfirstlane(sl.x) * 64;
       st.a00 = ap[0];
@@ -251,6 +271,7 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   auto compute = [&](const Stage& st, int bf) {
     const int wmask = (st.mask >> rbase) & ((1 << RPW) - 1);
     if (!wmask) return;
+    if (BSP && !st.cmask) return;
     Val b0[CPW], b1[CPW], bs[CPW];
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
@@ -273,7 +294,8 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
         if (wmask & (1 << (g0 + r))) {
           const Val as = Arith::sum(a0[r], a1[r]);
 #pragma unroll
-          for (int c = 0; c < CPW; ++c) ar.mac(acc[g0 + r][c], a0[r], a1[r], as, b0[c], b1[c], bs[c]);
+          for (int c = 0; c < CPW; ++c)
+            if (!BSP || ((st.cmask >> c) & 1)) ar.mac(acc[g0 + r][c], a0[r], a1[r], as, b0[c], b1[c], bs[c]);
         }
       }
     }
@@ -361,7 +383,7 @@ int launch_tensor_gather(const sfhe_ctx* c, int lev, const u64* A, int64_t nA, c
   return SFHE_OK;
 }
 
-template <typename Arith, int RPW, int CPW>
+template <typename Arith, int RPW, int CPW, bool BSP>
 static int launch_block(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl, const u64* A, const u64* B, u64* D,
                         hipStream_t s) {
   if (fl.n == 0) return SFHE_OK;
@@ -370,7 +392,7 @@ static int launch_block(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl
   t2.n_col_tiles = (tl.Nc + kCols - 1) / kCols;
   const int64_t blocks = (int64_t)fl.n * (c->N / 64) * tl.n_row_tiles * t2.n_col_tiles;
   if (blocks > 0x7FFFFFFF) { set_error("tensor: grid too large"); return SFHE_E_INVALID_ARG; }
-  hipLaunchKernelGGL((tensor_block_kernel<Arith, RPW, CPW>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, t2, A,
+  hipLaunchKernelGGL((tensor_block_kernel<Arith, RPW, CPW, BSP>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, t2, A,
                      B, D, fl, c->dp);
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;
@@ -397,9 +419,13 @@ int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, con
     dst.l[dst.n++] = F;
   }
   if (fp_start) SFHE_HIP(hipEventRecord(fp_start, s));
-  int rc = launch_block<ArithFp, 4, 2>(c, tl, ffp, A, B, D, s);
+  const bool bsp = tl.bslot != nullptr;
+  int rc = bsp ? launch_block<ArithFp, 4, 2, true>(c, tl, ffp, A, B, D, s)
+               : launch_block<ArithFp, 4, 2, false>(c, tl, ffp, A, B, D, s);
   if (fp_stop) SFHE_HIP(hipEventRecord(fp_stop, s));
-  if (!rc) rc = launch_block<ArithInt, 4, 1>(c, tl, fint, A, B, D, s);
+  if (!rc)
+    rc = bsp ? launch_block<ArithInt, 4, 1, true>(c, tl, fint, A, B, D, s)
+             : launch_block<ArithInt, 4, 1, false>(c, tl, fint, A, B, D, s);
   return rc;
 }
 
