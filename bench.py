@@ -201,6 +201,120 @@ def ctpt_leg(torch, sfhe, W, count=32):
             "host_wall_s": wall, "per_product_launch_sample": sample}
 
 
+def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=8):
+    """The request loop over plaintext-weight products: encrypted MLP-layer
+    requests (weights 128x784, 256x256 or 128x512, i.e. layers 784->128,
+    256->256, 512->128, at 50, 75 or 90% zeros; activation batches of 1-16
+    columns) arriving as a Poisson process, admitted by memory and batched by
+    sfhe_server_step as they arrive.  The layers' weights are encoded once;
+    the encrypted activations come from a pool of pool_per_layer matrices per
+    layer, encrypted before the run (the client's side; requests only read
+    them).  The arrival rate is `load` times the service rate measured on one
+    request of each layer alone.  Latency is arrival to result, host clock."""
+    P = W.PARAMS["plain_n16384"]
+    cfg = 5
+    ctx = sfhe.Context(**P)
+    ctx.keygen(W.key_seed(cfg))
+    rng = np.random.default_rng(W.workload_seed(cfg))
+    layers = [(784, 128), (256, 256), (512, 128)]
+    sparsities = [0.5, 0.75, 0.9]
+    weights = {}
+    for li, (fin, fout) in enumerate(layers):
+        for si, sp in enumerate(sparsities):
+            Wt = W.sparse_matrix(fout, fin, sp, W.workload_seed(cfg) + 10 * li + si)
+            weights[(li, si)] = (Wt, ctx.encode_weights(Wt, "csr", 40))
+    pool = {}
+    for li in range(3):
+        for x in range(pool_per_layer):
+            b = int(rng.integers(1, 17))
+            X = W.uniform_matrix(layers[li][0], b, W.workload_seed(cfg) + 1000 + 100 * li + x)
+            pool[(li, x)] = (b, X, ctx.encrypt(X, "dense", W.enc_seed(cfg, 1) + 100 * li + x, 1))
+    reqs = []
+    for n in range(n_requests):
+        li, si, x = int(rng.integers(3)), int(rng.integers(3)), int(rng.integers(pool_per_layer))
+        b, X, EX = pool[(li, x)]
+        reqs.append({"layer": li, "sp": si, "b": b, "X": X, "EX": EX})
+    torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(0.5 * free, 64 << 30))
+    # service time of one request alone, per layer, at 8 columns
+    alone_ms = []
+    for li in range(3):
+        r = next((q for q in reqs if q["layer"] == li), reqs[0])
+        srv = sfhe.Server(ctx, budget)
+        t = srv.submit(weights[(r["layer"], 1)][1], r["EX"])
+        srv.step()
+        srv.poll(t, wait=True)[1].close()
+        t0 = time.perf_counter()
+        t = srv.submit(weights[(r["layer"], 1)][1], r["EX"])
+        srv.step()
+        srv.poll(t, wait=True)[1].close()
+        alone_ms.append((time.perf_counter() - t0) * 1e3 * 8.0 / r["b"])
+        srv.close()
+    mean_service_s = float(np.mean(alone_ms)) * (8.5 / 8.0) / 1e3
+    rate = load / mean_service_s
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+    srv = sfhe.Server(ctx, budget)
+    tickets, done_at, results, sizes = {}, {}, {}, []
+    t0 = time.perf_counter()
+    nxt = 0
+    while len(done_at) < n_requests:
+        now = time.perf_counter() - t0
+        while nxt < n_requests and arrivals[nxt] <= now:
+            r = reqs[nxt]
+            tickets[nxt] = srv.submit(weights[(r["layer"], r["sp"])][1], r["EX"])
+            nxt += 1
+        srv.step()
+        for n, t in tickets.items():
+            if n in done_at:
+                continue
+            d, C, ms, bs = srv.poll(t)
+            if d:
+                done_at[n] = time.perf_counter() - t0
+                if n in (0, n_requests // 2, n_requests - 1):
+                    results[n] = C          # kept for the checks below
+                else:
+                    C.close()
+                sizes.append(bs)
+        if nxt < n_requests and not any(n not in done_at for n in tickets):
+            time.sleep(max(0.0, min(arrivals[nxt] - (time.perf_counter() - t0), 0.002)))
+        else:
+            time.sleep(0.0002)
+    makespan = max(done_at.values()) - arrivals[0]
+    st = srv.status()
+    lat = np.array([(done_at[n] - arrivals[n]) * 1e3 for n in range(n_requests)])
+    products = st["products"]
+    # a result in the mix equals the same request alone, bit for bit
+    same = True
+    for n in (0, n_requests // 2, n_requests - 1):
+        r = reqs[n]
+        solo = sfhe.Server(ctx, budget)
+        t = solo.submit(weights[(r["layer"], r["sp"])][1], r["EX"])
+        solo.step()
+        C1 = solo.poll(t, wait=True)[1]
+        for (i, j) in [(0, 0), (layers[r["layer"]][1] - 1, r["b"] - 1)]:
+            same = same and np.array_equal(ctx.export_ct(C1, i, j), ctx.export_ct(results[n], i, j))
+        C1.close()
+        solo.close()
+    err = max(float(np.max(np.abs(ctx.decrypt(results[n]) - weights[(reqs[n]["layer"], reqs[n]["sp"])][0] @ reqs[n]["X"])))
+              for n in (0, n_requests - 1))
+    for C in results.values():
+        C.close()
+    srv.close()
+    for k in pool:
+        pool[k][2].close()
+    for k in weights:
+        weights[k][1].close()
+    ctx.close()
+    torch.cuda.empty_cache()
+    return {"requests": n_requests, "load": load, "arrival_rate_per_s": rate, "budget_gib": budget / 2 ** 30,
+            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+            "latency_ms_mean": float(lat.mean()), "makespan_s": makespan, "products": int(products),
+            "ctpt_mults_per_s": products / makespan, "batches": int(st["batches"]),
+            "mean_batch_size": float(np.mean(sizes)), "max_batch_size": int(max(sizes)),
+            "alone_equals_mix": bool(same), "max_abs_err_vs_fp64": err, "ring": "N=2^14, 5 data primes"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,7 +323,7 @@ def main():
     ap.add_argument("--sparsity", type=float, default=0.5)
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--only", default="", help="comma list of extra legs to run (default all): "
-                    "s90,dense,ell,naive,per_product,both,ctpt,cpu")
+                    "s90,dense,ell,naive,per_product,both,serve,ctpt,cpu")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -329,6 +443,12 @@ def main():
     EA.close()
     EB.close()
     torch.cuda.empty_cache()
+    if run("serve"):
+        log("serving: Poisson arrivals of encrypted MLP-layer requests")
+        legs["serving"] = serving_leg(torch, sfhe, W)
+        log("serving: p50 %.1f ms, p99 %.1f ms, %.4g ct-pt mults/s, %d batches" %
+            (legs["serving"]["latency_ms_p50"], legs["serving"]["latency_ms_p99"],
+             legs["serving"]["ctpt_mults_per_s"], legs["serving"]["batches"]))
     if run("ctpt"):
         log("plaintext weights x encrypted values: uneven batch of 32 products")
         legs["ctpt_uneven_batch"] = ctpt_leg(torch, sfhe, W)

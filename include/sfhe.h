@@ -218,6 +218,35 @@ typedef enum {
 int sfhe_matmul_plain_batch(sfhe_ctx* ctx, int32_t count, const sfhe_mat* const* W, const sfhe_mat* const* B,
                             sfhe_plain_launch launch, void* stream, sfhe_mat** C);
 
+/* ---- Serving: a request loop over plaintext-weight products ------------
+ * Requests W X (plaintext weights from sfhe_encode_matrix, encrypted DENSE
+ * activations X at the top level) queue in arrival order.  Each
+ * sfhe_server_step first retires the batches whose device work has ended,
+ * then admits queued requests, in order, while the device bytes they hold
+ * until they complete (2 (L) N words of sums and 2 (L - 1) N of results per
+ * output) fit budget_bytes beside the batches still running, and enqueues
+ * them as one fused sfhe_matmul_plain_batch on the server's stream: requests
+ * arriving while a batch runs join the next one, which starts when the
+ * running one ends.  A request's result is the same, bit for bit, alone or
+ * in any batch.  The caller keeps W and X alive until its request is done;
+ * a finished result belongs to the caller from sfhe_server_poll on.  Calls
+ * on one server must not overlap. */
+typedef struct sfhe_server sfhe_server;
+int sfhe_server_create(sfhe_ctx* ctx, uint64_t budget_bytes, void* stream, sfhe_server** out);
+/* queue W X; a request larger than the budget is SFHE_E_NOMEM */
+int sfhe_server_submit(sfhe_server* srv, const sfhe_mat* W, const sfhe_mat* X, int64_t* ticket);
+/* retire ended batches, admit and launch; *admitted = requests launched now */
+int sfhe_server_step(sfhe_server* srv, int32_t* admitted);
+/* whether ticket's request is done (waiting for the running batches if wait
+ * != 0); if so *C receives its result, *batch_ms the device time of its batch
+ * and *batch_size the requests in it (both nullable) */
+int sfhe_server_poll(sfhe_server* srv, int64_t ticket, int32_t wait, int32_t* done, sfhe_mat** C, double* batch_ms,
+                     int32_t* batch_size);
+int sfhe_server_status(const sfhe_server* srv, int64_t* queued, int64_t* running, uint64_t* bytes_in_flight,
+                       int64_t* batches, int64_t* products);
+/* waits for the running batches; results not yet polled are freed */
+void sfhe_server_destroy(sfhe_server* srv);
+
 int sfhe_matrix_info(const sfhe_mat* m, sfhe_mat_info* out);
 int sfhe_last_stats(const sfhe_ctx* ctx, sfhe_stats* out);
 

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -909,22 +911,38 @@ int sfhe_encode_matrix(sfhe_ctx* c, const double* vals, int32_t rows, int32_t co
   GUARD_END
 }
 
-// the plaintext-weight product of count (W, B) pairs: checks, tile tables,
-// one fused launch set (or one launch per product), then one rescale per pair
-static int plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, const sfhe_mat* const* Bm,
-                       sfhe_plain_launch launch, hipStream_t s, sfhe_mat** C) {
+// checks of one plaintext-weight product W B
+static int plain_check(const sfhe_ctx* c, const sfhe_mat* W, const sfhe_mat* B) {
+  if (!W || !B) { set_error("NULL matrix"); return SFHE_E_INVALID_ARG; }
+  if (W->ctx != c || B->ctx != c) { set_error("matrices belong to another context"); return SFHE_E_INVALID_ARG; }
+  if (!W->plain) { set_error("the left operand must be plaintext weights (sfhe_encode_matrix)"); return SFHE_E_INVALID_ARG; }
+  if (B->plain) { set_error("the right operand must be encrypted"); return SFHE_E_INVALID_ARG; }
+  if (B->enc != SFHE_ENC_DENSE) { set_error("the right operand must be DENSE"); return SFHE_E_UNSUPPORTED; }
+  if (W->cols != B->rows) { set_error("W.cols != B.rows"); return SFHE_E_SHAPE; }
+  if (B->level != c->L - 1) { set_error("the encrypted operand must be at the top level"); return SFHE_E_LEVEL; }
+  if (B->level < 1) { set_error("no prime left to rescale"); return SFHE_E_LEVEL; }
+  return SFHE_OK;
+}
+
+// device bytes a plaintext-weight product holds until it completes: its
+// outputs' sums (2 (lev + 1) N words each) and results (2 lev N words each)
+static uint64_t plain_bytes(const sfhe_ctx* c, const sfhe_mat* W, const sfhe_mat* B) {
+  const int lev = c->L - 1;
+  return (uint64_t)W->rows * B->cols * (uint64_t)(2 * (lev + 1) + 2 * lev) * c->N * sizeof(u64);
+}
+
+// Enqueue the plaintext-weight products of count (W, B) pairs on stream s:
+// tile tables, results, one fused launch set (or one launch per product),
+// then one rescale per output.  ev_start (nullable) is recorded after the
+// set-up, before the first product launch.  On failure every C[n] is NULL.
+static int plain_enqueue(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, const sfhe_mat* const* Bm,
+                         sfhe_plain_launch launch, hipStream_t s, sfhe_mat** C, hipEvent_t ev_start,
+                         int64_t* n_products, int64_t* n_launches, int64_t* n_outputs) {
   for (int n = 0; n < count; ++n) C[n] = nullptr;
   if (launch != SFHE_PLAIN_FUSED && launch != SFHE_PLAIN_LAUNCH_PER_PRODUCT) { set_error("bad launch mode"); return SFHE_E_INVALID_ARG; }
   for (int n = 0; n < count; ++n) {
-    const sfhe_mat *W = Wm[n], *B = Bm[n];
-    if (!W || !B) { set_error("NULL matrix"); return SFHE_E_INVALID_ARG; }
-    if (W->ctx != c || B->ctx != c) { set_error("matrices belong to another context"); return SFHE_E_INVALID_ARG; }
-    if (!W->plain) { set_error("the left operand must be plaintext weights (sfhe_encode_matrix)"); return SFHE_E_INVALID_ARG; }
-    if (B->plain) { set_error("the right operand must be encrypted"); return SFHE_E_INVALID_ARG; }
-    if (B->enc != SFHE_ENC_DENSE) { set_error("the right operand must be DENSE"); return SFHE_E_UNSUPPORTED; }
-    if (W->cols != B->rows) { set_error("W.cols != B.rows"); return SFHE_E_SHAPE; }
-    if (B->level != c->L - 1) { set_error("the encrypted operand must be at the top level"); return SFHE_E_LEVEL; }
-    if (B->level < 1) { set_error("no prime left to rescale"); return SFHE_E_LEVEL; }
+    const int rc = plain_check(c, Wm[n], Bm[n]);
+    if (rc) return rc;
   }
   const int N = c->N, lev = c->L - 1, nl = lev + 1;
   const int64_t dw = (int64_t)2 * nl * N;   // words per output sum
@@ -983,8 +1001,6 @@ static int plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, co
   }
   tstart.push_back((int)ek.size());
   if (ek.size() > (size_t)0x7FFFFFFF / 16) { set_error("plaintext-weight product: too many entries"); return SFHE_E_INVALID_ARG; }
-  c->prof_used = 0;
-  c->prof_cat.clear();
   int rc = SFHE_OK;
   for (int n = 0; n < count && !rc; ++n) {
     sfhe_mat* o = new sfhe_mat();
@@ -1010,7 +1026,10 @@ static int plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, co
     set_error("device allocation failed (the sums of every output are held at once)");
   }
   // the timed region: products and rescales (allocation and table uploads are set-up)
-  if (!rc) SFHE_HIP(hipEventRecord(c->ev0, s));
+  if (!rc && ev_start) {
+    hipError_t e = hipEventRecord(ev_start, s);
+    if (e != hipSuccess) { rc = SFHE_E_DEVICE; set_error(hipGetErrorString(e)); }
+  }
   int64_t launches = 0;
   if (!rc && launch == SFHE_PLAIN_FUSED) {
     PlainBatch pb{d_jobs.ptr, d_desc.ptr, (int)desc.size(), d_ts.ptr, d_ek.ptr, d_em.ptr, d_ew.ptr, d_ews.ptr, nl, D.ptr};
@@ -1058,14 +1077,31 @@ static int plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, co
       rc = c->logN == 14 ? rescale_n14(c, lev, Ds, dw, ol, m, s) : rescale_batch(c, lev, Ds, dw, ol, m, s);
     }
   }
-  if (!rc) {
-    hipError_t e = hipEventRecord(c->ev1, s);
-    if (e != hipSuccess) { rc = SFHE_E_DEVICE; set_error(hipGetErrorString(e)); }
-  }
   if (rc) {
     (void)hipStreamSynchronize(s);
     for (int n = 0; n < count; ++n) { delete C[n]; C[n] = nullptr; }
     return rc;
+  }
+  *n_products = products;
+  *n_launches = launches;
+  *n_outputs = outs;
+  return SFHE_OK;
+}
+
+// the synchronous-API form: timed by the context's event pair, stats recorded
+static int plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, const sfhe_mat* const* Bm,
+                       sfhe_plain_launch launch, hipStream_t s, sfhe_mat** C) {
+  int64_t products = 0, launches = 0, outs = 0;
+  c->prof_used = 0;
+  c->prof_cat.clear();
+  int rc = plain_enqueue(c, count, Wm, Bm, launch, s, C, c->ev0, &products, &launches, &outs);
+  if (rc) return rc;
+  hipError_t e = hipEventRecord(c->ev1, s);
+  if (e != hipSuccess) {
+    set_error(hipGetErrorString(e));
+    (void)hipStreamSynchronize(s);
+    for (int n = 0; n < count; ++n) { delete C[n]; C[n] = nullptr; }
+    return SFHE_E_DEVICE;
   }
   c->stats = sfhe_stats{};
   c->stats.products = products;
@@ -1096,6 +1132,172 @@ int sfhe_matmul_plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* W
   return plain_batch(c, count, W, B, launch, (hipStream_t)stream, C);
   GUARD_END
 }
+
+// ---------------------------------------------------------------- serving
+}  // extern "C"
+
+// A request loop over plaintext-weight products: requests queue in arrival
+// order; each step first retires the batches whose end event has passed,
+// then admits queued requests while the device bytes they hold until they
+// complete (sums and results) fit the budget, and enqueues them as one fused
+// batch on the server's stream.  Batches run in stream order, so a batch
+// admitted while another is on the device starts as soon as it ends, and the
+// host prepares the next batch meanwhile.
+struct sfhe_server {
+  sfhe_ctx* c = nullptr;
+  hipStream_t s = nullptr;
+  uint64_t budget = 0, in_flight = 0;
+  struct Req {
+    int64_t ticket;
+    const sfhe_mat *W, *X;
+    uint64_t bytes;
+  };
+  struct Run {
+    std::vector<int64_t> tickets;
+    std::vector<sfhe_mat*> C;
+    hipEvent_t start = nullptr, end = nullptr;
+    uint64_t bytes = 0;
+    int64_t products = 0;
+  };
+  struct Done {
+    sfhe_mat* C;
+    double ms;          // device time of the request's batch
+    int64_t batch;      // batch index
+    int32_t batch_size;
+  };
+  std::deque<Req> queue;
+  std::deque<Run> running;
+  std::map<int64_t, Done> done;
+  int64_t next_ticket = 0, batches = 0, products = 0;
+  // move the batches whose end event has passed to `done`; wait for them all if `all`
+  int retire(bool all) {
+    while (!running.empty()) {
+      Run& r = running.front();
+      hipError_t e = all ? hipEventSynchronize(r.end) : hipEventQuery(r.end);
+      if (e == hipErrorNotReady) return SFHE_OK;
+      if (e != hipSuccess) { set_error(hipGetErrorString(e)); return SFHE_E_DEVICE; }
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, r.start, r.end);
+      for (size_t x = 0; x < r.tickets.size(); ++x)
+        done[r.tickets[x]] = Done{r.C[x], ms, batches - (int64_t)running.size(), (int32_t)r.tickets.size()};
+      in_flight -= r.bytes;
+      products += r.products;
+      (void)hipEventDestroy(r.start);
+      (void)hipEventDestroy(r.end);
+      running.pop_front();
+    }
+    return SFHE_OK;
+  }
+  ~sfhe_server() {
+    (void)retire(true);
+    for (auto& d : done) delete d.second.C;
+  }
+};
+
+extern "C" {
+
+int sfhe_server_create(sfhe_ctx* c, uint64_t budget_bytes, void* stream, sfhe_server** out) {
+  GUARD_BEGIN
+  if (!out) { set_error("out is NULL"); return SFHE_E_INVALID_ARG; }
+  *out = nullptr;
+  if (!c || budget_bytes == 0) { set_error("NULL context or zero budget"); return SFHE_E_INVALID_ARG; }
+  sfhe_server* v = new sfhe_server();
+  v->c = c;
+  v->s = (hipStream_t)stream;
+  v->budget = budget_bytes;
+  *out = v;
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_server_submit(sfhe_server* v, const sfhe_mat* W, const sfhe_mat* X, int64_t* ticket) {
+  GUARD_BEGIN
+  if (!v || !ticket) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  const int rc = plain_check(v->c, W, X);
+  if (rc) return rc;
+  const uint64_t bytes = plain_bytes(v->c, W, X);
+  if (bytes > v->budget) { set_error("request larger than the server's memory budget"); return SFHE_E_NOMEM; }
+  *ticket = v->next_ticket++;
+  v->queue.push_back(sfhe_server::Req{*ticket, W, X, bytes});
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_server_step(sfhe_server* v, int32_t* admitted) {
+  GUARD_BEGIN
+  if (!v || !admitted) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  *admitted = 0;
+  int rc = v->retire(false);
+  if (rc) return rc;
+  std::vector<const sfhe_mat*> Ws, Xs;
+  sfhe_server::Run run;
+  while (!v->queue.empty() && v->in_flight + run.bytes + v->queue.front().bytes <= v->budget) {
+    const sfhe_server::Req& q = v->queue.front();
+    Ws.push_back(q.W);
+    Xs.push_back(q.X);
+    run.tickets.push_back(q.ticket);
+    run.bytes += q.bytes;
+    v->queue.pop_front();
+  }
+  if (Ws.empty()) return SFHE_OK;
+  run.C.assign(Ws.size(), nullptr);
+  if (hipEventCreate(&run.start) != hipSuccess || hipEventCreate(&run.end) != hipSuccess) {
+    set_error("event creation failed");
+    rc = SFHE_E_DEVICE;
+  }
+  int64_t launches = 0, outs = 0;
+  if (!rc)
+    rc = plain_enqueue(v->c, (int32_t)Ws.size(), Ws.data(), Xs.data(), SFHE_PLAIN_FUSED, v->s, run.C.data(), run.start,
+                       &run.products, &launches, &outs);
+  if (!rc && hipEventRecord(run.end, v->s) != hipSuccess) { set_error("event record failed"); rc = SFHE_E_DEVICE; }
+  if (rc) {
+    // the requests stay queued, in order, for a later step
+    for (size_t x = Ws.size(); x-- > 0;) v->queue.push_front(sfhe_server::Req{run.tickets[x], Ws[x], Xs[x], plain_bytes(v->c, Ws[x], Xs[x])});
+    for (auto* m : run.C) delete m;
+    if (run.start) (void)hipEventDestroy(run.start);
+    if (run.end) (void)hipEventDestroy(run.end);
+    return rc;
+  }
+  v->in_flight += run.bytes;
+  ++v->batches;
+  *admitted = (int32_t)Ws.size();
+  v->running.push_back(std::move(run));
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_server_poll(sfhe_server* v, int64_t ticket, int32_t wait, int32_t* is_done, sfhe_mat** C, double* batch_ms,
+                     int32_t* batch_size) {
+  GUARD_BEGIN
+  if (!v || !is_done || !C) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  *is_done = 0;
+  *C = nullptr;
+  if (ticket < 0 || ticket >= v->next_ticket) { set_error("unknown ticket"); return SFHE_E_INVALID_ARG; }
+  int rc = v->retire(wait != 0);
+  if (rc) return rc;
+  auto it = v->done.find(ticket);
+  if (it == v->done.end()) return SFHE_OK;
+  *is_done = 1;
+  *C = it->second.C;
+  if (batch_ms) *batch_ms = it->second.ms;
+  if (batch_size) *batch_size = it->second.batch_size;
+  v->done.erase(it);
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_server_status(const sfhe_server* v, int64_t* queued, int64_t* running, uint64_t* bytes_in_flight,
+                       int64_t* batches, int64_t* products) {
+  if (!v) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (queued) *queued = (int64_t)v->queue.size();
+  if (running) *running = (int64_t)v->running.size();
+  if (bytes_in_flight) *bytes_in_flight = v->in_flight;
+  if (batches) *batches = v->batches;
+  if (products) *products = v->products;
+  return SFHE_OK;
+}
+
+void sfhe_server_destroy(sfhe_server* v) { delete v; }
 
 int sfhe_last_stats(const sfhe_ctx* cc, sfhe_stats* out) {
   if (!cc || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }

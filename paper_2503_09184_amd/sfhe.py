@@ -29,6 +29,8 @@ EXPORTED = [
     "sfhe_matrix_info", "sfhe_last_stats", "sfhe_set_profiling", "sfhe_mat_destroy", "sfhe_last_error",
     "sfhe_ntt", "sfhe_tensor", "sfhe_keyswitch", "sfhe_rescale",
     "sfhe_encode_matrix", "sfhe_matmul_plain", "sfhe_matmul_plain_batch",
+    "sfhe_server_create", "sfhe_server_submit", "sfhe_server_step", "sfhe_server_poll", "sfhe_server_status",
+    "sfhe_server_destroy",
 ]
 
 PLAIN_LAUNCH = {"fused": 0, "per_product": 1}
@@ -106,6 +108,15 @@ def lib():
         L.sfhe_matmul_plain.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.sfhe_matmul_plain_batch.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp,
                                               ctypes.POINTER(vp)]
+        L.sfhe_server_create.argtypes = [vp, u64, vp, ctypes.POINTER(vp)]
+        L.sfhe_server_submit.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
+        L.sfhe_server_step.argtypes = [vp, ctypes.POINTER(i32)]
+        L.sfhe_server_poll.argtypes = [vp, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(vp),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
+        L.sfhe_server_status.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(u64),
+                                         ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.sfhe_server_destroy.argtypes = [vp]
+        L.sfhe_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -141,6 +152,57 @@ class Matrix:
     def close(self):
         if self._h is not None and self._h.value:
             lib().sfhe_mat_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The library's request loop over plaintext-weight products (a handle)."""
+
+    def __init__(self, ctx, budget_bytes, stream=None):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(lib().sfhe_server_create(ctx._h, ctypes.c_uint64(int(budget_bytes)), _stream_handle(stream),
+                                        ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, W, X):
+        t = ctypes.c_int64()
+        _check(lib().sfhe_server_submit(self._h, W.handle, X.handle, ctypes.byref(t)))
+        return t.value
+
+    def step(self):
+        n = ctypes.c_int32()
+        _check(lib().sfhe_server_step(self._h, ctypes.byref(n)))
+        return n.value
+
+    def poll(self, ticket, wait=False):
+        """(done, result Matrix or None, batch device ms, batch size)."""
+        d = ctypes.c_int32()
+        h = ctypes.c_void_p()
+        ms = ctypes.c_double()
+        bs = ctypes.c_int32()
+        _check(lib().sfhe_server_poll(self._h, int(ticket), 1 if wait else 0, ctypes.byref(d), ctypes.byref(h),
+                                      ctypes.byref(ms), ctypes.byref(bs)))
+        if not d.value:
+            return False, None, 0.0, 0
+        return True, Matrix(self.ctx, h), ms.value, bs.value
+
+    def status(self):
+        q, r, b, n, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().sfhe_server_status(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(b), ctypes.byref(n),
+                                        ctypes.byref(p)))
+        return {"queued": q.value, "running": r.value, "bytes_in_flight": b.value, "batches": n.value,
+                "products": p.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sfhe_server_destroy(self._h)
         self._h = None
 
     def __del__(self):
