@@ -201,7 +201,7 @@ def ctpt_leg(torch, sfhe, W, count=32):
             "host_wall_s": wall, "per_product_launch_sample": sample}
 
 
-def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=8):
+def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
     """The request loop over plaintext-weight products: encrypted MLP-layer
     requests (weights 128x784, 256x256 or 128x512, i.e. layers 784->128,
     256->256, 512->128, at 50, 75 or 90% zeros; activation batches of 1-16
@@ -211,7 +211,7 @@ def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=8):
     layer, encrypted before the run (the client's side; requests only read
     them).  The arrival rate is `load` times the service rate measured on one
     request of each layer alone.  Latency is arrival to result, host clock."""
-    P = W.PARAMS["plain_n16384"]
+    P = W.PARAMS["serving_n32768"]
     cfg = 5
     ctx = sfhe.Context(**P)
     ctx.keygen(W.key_seed(cfg))
@@ -312,7 +312,8 @@ def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=8):
             "latency_ms_mean": float(lat.mean()), "makespan_s": makespan, "products": int(products),
             "ctpt_mults_per_s": products / makespan, "batches": int(st["batches"]),
             "mean_batch_size": float(np.mean(sizes)), "max_batch_size": int(max(sizes)),
-            "alone_equals_mix": bool(same), "max_abs_err_vs_fp64": err, "ring": "N=2^14, 5 data primes"}
+            "alone_equals_mix": bool(same), "max_abs_err_vs_fp64": err,
+            "ring": "N=2^15, 9 data + 3 special primes (12 limbs), dnum=3"}
 
 
 def main():

@@ -73,7 +73,7 @@ typedef enum { SFHE_SCHED_PER_PRODUCT = 0, SFHE_SCHED_LAZY = 1 } sfhe_schedule;
  * size in order (data primes q_0..q_{n_q-1}, then the special primes), the
  * largest prime below 2^bits that is 1 mod 2N and not already taken.  The
  * special primes form P for hybrid key switching with dnum digits of n_p data
- * primes each (dnum must equal ceil(n_q / n_p)).  log_n in [10, 14]; bits in
+ * primes each (dnum must equal ceil(n_q / n_p)).  log_n in [10, 15]; bits in
  * [log_n + 2, 61]; n_q >= 2; n_q + n_p <= 16. */
 typedef struct {
   uint32_t log_n;
@@ -268,7 +268,9 @@ const char* sfhe_last_error(void);
  * keep each thread's registers contiguous, so position r * 512 + t holds
  * index ((r >> 4) << 13) | ((t & 63) << 4) | (t6 << 10) | (t8 << 11) |
  * (t7 << 12) | (r & 15), where 0 <= r < 32, 0 <= t < 512 and t6..t8 are
- * bits of t.  Every NTT-domain buffer of the library (matrices, keys,
+ * bits of t; for N = 2^15 each half of a row (positions h 2^14 ..
+ * h 2^14 + 2^14 - 1) holds indices h 2^14 .. h 2^14 + 2^14 - 1 in that
+ * N = 2^14 order.  Every NTT-domain buffer of the library (matrices, keys,
  * primitive inputs and outputs) uses that order; coefficient-domain rows are
  * always in natural order.  Buffers must not overlap unless stated. */
 

@@ -133,6 +133,37 @@ static int build_tables(sfhe_ctx* c) {
     P.twd = c->d_tables_d.ptr + ((size_t)r * 2 + 0) * N;
     P.itwd = c->d_tables_d.ptr + ((size_t)r * 2 + 1) * N;
   }
+  // N = 2^15: after the first stage (pairs x_i, x_{i + N/2}), each half is a
+  // 2^14-point transform whose twiddles, indexed as a transform of its own
+  // (m + g for m groups), are the full transform's (2 + h) m + g: tables
+  // [prime][direction][half][2^14], forward (tw) then inverse (itw)
+  if (c->logN == 15) {
+    const int H = N / 2;
+    std::vector<u64> sub((size_t)nb * 4 * H, 0), sub_s((size_t)nb * 4 * H, 0);
+    std::vector<double> subd((size_t)nb * 4 * H, 0.0);
+    for (int r = 0; r < nb; ++r)
+      for (int d = 0; d < 2; ++d) {
+        const u64* full = tab.data() + ((size_t)r * 4 + 2 * d) * N;
+        const u64* full_s = tab.data() + ((size_t)r * 4 + 2 * d + 1) * N;
+        for (int h = 0; h < 2; ++h) {
+          const size_t base = (((size_t)r * 2 + d) * 2 + h) * H;
+          for (int j = 1; j < H; ++j) {
+            int m = 1;
+            while (2 * m <= j) m *= 2;
+            const int src = (2 + h) * m + (j - m);
+            sub[base + j] = full[src];
+            sub_s[base + j] = full_s[src];
+            subd[base + j] = (double)full[src];
+          }
+        }
+      }
+    if (!c->d_sub.alloc(&c->alloc, sub.size()) || !c->d_sub_s.alloc(&c->alloc, sub_s.size()) ||
+        !c->d_sub_d.alloc(&c->alloc, subd.size()))
+      return SFHE_E_NOMEM;
+    SFHE_HIP(hipMemcpy(c->d_sub.ptr, sub.data(), sub.size() * sizeof(u64), hipMemcpyHostToDevice));
+    SFHE_HIP(hipMemcpy(c->d_sub_s.ptr, sub_s.data(), sub_s.size() * sizeof(u64), hipMemcpyHostToDevice));
+    SFHE_HIP(hipMemcpy(c->d_sub_d.ptr, subd.data(), subd.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
   // slot-0 decoding / encoding weights, from the host libm
   std::vector<double> cv(N);
   for (int t = 0; t < N; ++t) cv[t] = cos(M_PI * (double)t / (double)N);
@@ -419,7 +450,7 @@ int sfhe_ctx_create(const sfhe_params* p, const sfhe_device_hooks* hooks, sfhe_c
   if (!out) { set_error("out is NULL"); return SFHE_E_INVALID_ARG; }
   *out = nullptr;
   if (!p || !p->q_bits || !p->p_bits) { set_error("params or bit lists are NULL"); return SFHE_E_INVALID_ARG; }
-  if (p->log_n < 10 || p->log_n > 14) { set_error("log_n must be in [10, 14]"); return SFHE_E_PARAMS; }
+  if (p->log_n < 10 || p->log_n > 15) { set_error("log_n must be in [10, 15]"); return SFHE_E_PARAMS; }
   if (p->n_q < 2 || p->n_p < 1 || p->n_q + p->n_p > (uint32_t)kMaxBasis || p->n_p > (uint32_t)kMaxDigit) {
     set_error("need 2 <= n_q, 1 <= n_p <= 8, n_q + n_p <= 16");
     return SFHE_E_PARAMS;

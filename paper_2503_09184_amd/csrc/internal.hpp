@@ -87,6 +87,9 @@ struct sfhe_ctx {
   // device tables
   sfhe::DevBuf<sfhe::u64> d_tables;      // [nb][4][N]: tw, tws, itw, itws
   sfhe::DevBuf<double> d_tables_d;       // [nb][2][N]: tw, itw as doubles
+  // N = 2^15: the halves' twiddle tables (see build_tables)
+  sfhe::DevBuf<sfhe::u64> d_sub, d_sub_s;
+  sfhe::DevBuf<double> d_sub_d;
   sfhe::DevBuf<double> d_cos;            // cos(pi t / N)
   sfhe::DevBuf<sfhe::ModUpConst> d_modup;      // [L][dnum]
   sfhe::DevBuf<sfhe::ModDownConst> d_moddown;  // [L]

@@ -95,6 +95,55 @@ __global__ void __launch_bounds__(n14::kThreads, 4) ntt14_kernel(NttRows R, DevP
     ntt14_row<INV, NttInt>(p, P, lds);
 }
 
+// ---- N = 2^15: the first forward stage (last inverse stage) across the two
+// halves, then each half as a 2^14-point transform with its own tables ----
+// grid (2^14 / 256, rows): x_i, x_{i + 2^14} -> x_i + w x_{i+2^14}, x_i - w x_{i+2^14}
+__global__ void __launch_bounds__(256) ntt15_first_kernel(NttRows R, DevParams dp) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int64_t g = blockIdx.y / R.nrow;
+  const int r = blockIdx.y % R.nrow;
+  u64* p = R.base + g * R.bstride + (int64_t)R.pos[r] * (2 * n14::kN);
+  const PrimeDev& P = dp.pr[R.prime[r]];
+  const u64 q = P.q;
+  const u64 a = p[i], T = mul_shoup(p[i + n14::kN], P.tw[1], P.tws[1], q);
+  p[i] = add_mod(a, T, q);
+  p[i + n14::kN] = sub_mod(a, T, q);
+}
+// x_i, x_{i + 2^14} -> x_i + x_{i+2^14}, (x_i - x_{i+2^14}) w^-1 (N^-1 is
+// applied by the halves' transforms)
+__global__ void __launch_bounds__(256) ntt15_last_kernel(NttRows R, DevParams dp) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int64_t g = blockIdx.y / R.nrow;
+  const int r = blockIdx.y % R.nrow;
+  u64* p = R.base + g * R.bstride + (int64_t)R.pos[r] * (2 * n14::kN);
+  const PrimeDev& P = dp.pr[R.prime[r]];
+  const u64 q = P.q;
+  const u64 a = p[i], b = p[i + n14::kN];
+  p[i] = add_mod(a, b, q);
+  p[i + n14::kN] = mul_shoup(sub_mod(a, b, q), P.itw[1], P.itws[1], q);
+}
+// one half of a row (block = (row, half)) as a 2^14-point transform
+template <bool INV>
+__global__ void __launch_bounds__(n14::kThreads, 4) ntt15_half_kernel(NttRows R, DevParams dp) {
+  extern __shared__ u64 lds[];
+  const int64_t g = (blockIdx.x >> 1) / R.nrow;
+  const int r = (blockIdx.x >> 1) % R.nrow, h = blockIdx.x & 1;
+  u64* p = R.base + g * R.bstride + (int64_t)R.pos[r] * (2 * n14::kN) + (int64_t)h * n14::kN;
+  const int pr = R.prime[r];
+  PrimeDev P = dp.pr[pr];
+  const int64_t fo = (((int64_t)pr * 2 + 0) * 2 + h) * n14::kN, io = (((int64_t)pr * 2 + 1) * 2 + h) * n14::kN;
+  P.tw = R.sub + fo;
+  P.tws = R.sub_s + fo;
+  P.twd = R.subd + fo;
+  P.itw = R.sub + io;
+  P.itws = R.sub_s + io;
+  P.itwd = R.subd + io;
+  if (P.q < (1ull << 42))
+    ntt14_row<INV, NttFp>(p, P, lds);
+  else
+    ntt14_row<INV, NttInt>(p, P, lds);
+}
+
 int launch_ntt(const sfhe_ctx* c, u64* base, int64_t batch, int64_t bstride, int nrow, const int* pos,
                const int* prime, bool inverse, hipStream_t s) {
   if (batch <= 0 || nrow <= 0) return SFHE_OK;
@@ -104,9 +153,36 @@ int launch_ntt(const sfhe_ctx* c, u64* base, int64_t batch, int64_t bstride, int
   R.bstride = bstride;
   R.nrow = nrow;
   for (int i = 0; i < kMaxRows; ++i) { R.pos[i] = i < nrow ? pos[i] : 0; R.prime[i] = i < nrow ? prime[i] : 0; }
+  R.sub = c->d_sub.ptr;
+  R.sub_s = c->d_sub_s.ptr;
+  R.subd = c->d_sub_d.ptr;
   const int N = c->N;
   const int64_t blocks = batch * nrow;
-  if (blocks > 0x7FFFFFFF) { set_error("ntt: batch too large"); return SFHE_E_INVALID_ARG; }
+  if (blocks > 0x7FFFFFFF / 2) { set_error("ntt: batch too large"); return SFHE_E_INVALID_ARG; }
+  if (c->logN == n14::kLogN + 1) {
+    if (blocks > 65535) { set_error("ntt: batch too large"); return SFHE_E_INVALID_ARG; }
+    static bool attr15 = false;
+    if (!attr15) {
+      SFHE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&ntt15_half_kernel<false>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, n14::kLdsWords * 8));
+      SFHE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&ntt15_half_kernel<true>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, n14::kLdsWords * 8));
+      attr15 = true;
+    }
+    const size_t lds = (size_t)n14::kLdsWords * sizeof(u64);
+    const dim3 ew(n14::kN / 256, (unsigned)blocks);
+    if (!inverse) {
+      hipLaunchKernelGGL(ntt15_first_kernel, ew, dim3(256), 0, s, R, c->dp);
+      SFHE_HIP(hipGetLastError());
+      hipLaunchKernelGGL(ntt15_half_kernel<false>, dim3((unsigned)(2 * blocks)), dim3(n14::kThreads), lds, s, R, c->dp);
+    } else {
+      hipLaunchKernelGGL(ntt15_half_kernel<true>, dim3((unsigned)(2 * blocks)), dim3(n14::kThreads), lds, s, R, c->dp);
+      SFHE_HIP(hipGetLastError());
+      hipLaunchKernelGGL(ntt15_last_kernel, ew, dim3(256), 0, s, R, c->dp);
+    }
+    SFHE_HIP(hipGetLastError());
+    return SFHE_OK;
+  }
   if (c->logN == n14::kLogN) {
     static bool attr14 = false;
     if (!attr14) {

@@ -31,6 +31,11 @@ struct NttRows {
   int nrow;
   int pos[kMaxRows];
   int prime[kMaxRows];
+  // N = 2^15 only: twiddle tables of the two 2^14-point halves,
+  // [prime][direction][half][2^14] (values, Shoup companions, fp64 values)
+  const u64* sub;
+  const u64* sub_s;
+  const double* subd;
 };
 
 __device__ __forceinline__ int lpos(int x) { return x + (x >> kPadShift); }

@@ -58,6 +58,9 @@ PARAMS = {
     # N = 2^14 for plaintext weights times encrypted values: the same five data
     # primes and one 60-bit special prime (unused: no relinearisation)
     "plain_n16384": dict(log_n=14, q_bits=[60, 40, 40, 40, 40], p_bits=[60], dnum=5),
+    # N = 2^15 for the serving loop: a 60-bit and eight 40-bit data primes,
+    # three 60-bit special primes, dnum = 3
+    "serving_n32768": dict(log_n=15, q_bits=[60] + [40] * 8, p_bits=[60, 60, 60], dnum=3),
 }
 
 

@@ -62,7 +62,12 @@ def ntt_storage_order(n):
     """NTT index stored at each position of a row (include/sfhe.h): the
     bit-reversed transform order itself below N = 2^14; at N = 2^14 position
     r * 512 + t holds index ((r >> 4) << 13) | ((t & 63) << 4) | (t6 << 10)
-    | (t8 << 11) | (t7 << 12) | (r & 15), t6..t8 the bits of t."""
+    | (t8 << 11) | (t7 << 12) | (r & 15), t6..t8 the bits of t; at N = 2^15
+    each half (2^14 positions) holds its half of the indices in the N = 2^14
+    order."""
+    if n == 1 << 15:
+        o = ntt_storage_order(1 << 14)
+        return np.concatenate([o, o + (1 << 14)])
     if n != 1 << 14:
         return np.arange(n)
     order = np.zeros(n, dtype=np.int64)
@@ -110,7 +115,7 @@ def _from_ntt(ctx, t, nl):
     return ctx.to_host(t)
 
 
-@pytest.mark.parametrize("params", [HYB_SMALL, SINGLE_SMALL, W.PARAMS["realistic_n16384"]])
+@pytest.mark.parametrize("params", [HYB_SMALL, SINGLE_SMALL, W.PARAMS["realistic_n16384"], W.PARAMS["serving_n32768"]])
 def test_tensor_keyswitch_rescale_match_oracle(torch_cuda, params):
     ctx, orc = pair(params, 5)
     rng = np.random.default_rng(12)
