@@ -300,7 +300,7 @@ def test_errors_are_reported(torch_cuda):
         ctx.encrypt(np.full((1, 1), np.inf), "csr", 1, 0)
     assert e.value.code == -1
     with pytest.raises(sfhe.SfheError) as e:
-        sfhe.Context(log_n=15, q_bits=[60, 40], p_bits=[60], dnum=2)
+        sfhe.Context(log_n=16, q_bits=[60, 40], p_bits=[60], dnum=2)
     assert e.value.code == -2
 
 
