@@ -133,7 +133,8 @@ def ctpt_leg(torch, sfhe, W, count=32):
     the wave budget is split into column blocks of B, and each wave is one
     fused batch call.  Encryption and encoding are outside the timed calls.
     The one-launch-per-product form is timed on the job with the fewest
-    products, beside the fused form on that job."""
+    products, beside the fused form on that job, and both again captured into
+    a HIP graph and replayed."""
     P = W.PARAMS["plain_n16384"]
     cfg = 4
     ctx = sfhe.Context(**P)
@@ -188,9 +189,18 @@ def ctpt_leg(torch, sfhe, W, count=32):
         sample[mode + "_ms"] = stx.ms
         sample["products"] = int(stx.products)
         sample[mode + "_launches"] = int(stx.tensor_launches)
+    # the same launches captured into a HIP graph and replayed
+    for mode in ("fused", "per_product"):
+        g = sfhe.PlainGraph(ctx, [Wm], [Bm], mode)
+        g.launch()
+        g.launch()
+        sample["graph_" + mode + "_ms"] = ctx.last_stats().ms
+        g.close()
     sample["fused_over_per_product"] = sample["per_product_ms"] / sample["fused_ms"]
-    log("ctpt per-product launches on %s: %.2f ms vs fused %.2f ms" %
-        (sample["job"], sample["per_product_ms"], sample["fused_ms"]))
+    sample["graph_fused_over_graph_per_product"] = sample["graph_per_product_ms"] / sample["graph_fused_ms"]
+    log("ctpt per-product launches on %s: %.2f ms vs fused %.2f ms; as graphs %.2f vs %.2f ms" %
+        (sample["job"], sample["per_product_ms"], sample["fused_ms"], sample["graph_per_product_ms"],
+         sample["graph_fused_ms"]))
     Wm.close()
     Bm.close()
     ctx.close()

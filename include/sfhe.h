@@ -218,6 +218,22 @@ typedef enum {
 int sfhe_matmul_plain_batch(sfhe_ctx* ctx, int32_t count, const sfhe_mat* const* W, const sfhe_mat* const* B,
                             sfhe_plain_launch launch, void* stream, sfhe_mat** C);
 
+/* The launches of one sfhe_matmul_plain_batch (either form) captured into a
+ * HIP graph for replay: creation prepares the tables, sums, scratch and
+ * results once (on stream), runs the batch once, then captures its launches
+ * on a stream of its own.  Each sfhe_plain_graph_launch replays them on
+ * stream, recomputing the results from the current contents of the B
+ * matrices (which must outlive the graph); sfhe_last_stats reports the
+ * replay's device time.  The results belong to the graph
+ * (sfhe_plain_graph_result gives read-only handles for export and decrypt)
+ * and are freed with it.  Replays of one graph must not overlap. */
+typedef struct sfhe_plain_graph sfhe_plain_graph;
+int sfhe_plain_graph_create(sfhe_ctx* ctx, int32_t count, const sfhe_mat* const* W, const sfhe_mat* const* B,
+                            sfhe_plain_launch launch, void* stream, sfhe_plain_graph** out);
+int sfhe_plain_graph_launch(sfhe_plain_graph* graph, void* stream);
+int sfhe_plain_graph_result(const sfhe_plain_graph* graph, int32_t n, const sfhe_mat** out);
+void sfhe_plain_graph_destroy(sfhe_plain_graph* graph);
+
 /* ---- Serving: a request loop over plaintext-weight products ------------
  * Requests W X (plaintext weights from sfhe_encode_matrix, encrypted DENSE
  * activations X at the top level) queue in arrival order.  Each

@@ -962,24 +962,49 @@ static uint64_t plain_bytes(const sfhe_ctx* c, const sfhe_mat* W, const sfhe_mat
   return (uint64_t)W->rows * B->cols * (uint64_t)(2 * (lev + 1) + 2 * lev) * c->N * sizeof(u64);
 }
 
-// Enqueue the plaintext-weight products of count (W, B) pairs on stream s:
-// tile tables, results, one fused launch set (or one launch per product),
-// then one rescale per output.  ev_start (nullable) is recorded after the
-// set-up, before the first product launch.  On failure every C[n] is NULL.
-static int plain_enqueue(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, const sfhe_mat* const* Bm,
-                         sfhe_plain_launch launch, hipStream_t s, sfhe_mat** C, hipEvent_t ev_start,
-                         int64_t* n_products, int64_t* n_launches, int64_t* n_outputs) {
-  for (int n = 0; n < count; ++n) C[n] = nullptr;
+// Everything the plaintext-weight launches read or write, allocated and
+// uploaded before them, so that the launches alone can also be captured into
+// a graph: results, sums, tile tables, per-product weights, rescale scratch.
+struct PlainPrep {
+  int count = 0;
+  sfhe_plain_launch launch = SFHE_PLAIN_FUSED;
+  std::vector<sfhe_mat*> C;
+  std::vector<const sfhe_mat*> B;
+  std::vector<PlainJob> jobs;
+  DevBuf<u64> D, ew, ews, pw, pws, scratch;
+  DevBuf<int> ts, ek, em;
+  DevBuf<int4> desc;
+  DevBuf<PlainJob> d_jobs;
+  int n_desc = 0;
+  std::vector<int64_t> pb_slot, pd;   // one launch per product: B slot, output
+  std::vector<int> pjob;
+  int64_t products = 0, launches = 0, outs = 0;
+  ~PlainPrep() { for (auto* m : C) delete m; }
+  // the results, handed over: the caller owns them from here on
+  void release(sfhe_mat** out) {
+    for (size_t n = 0; n < C.size(); ++n) out[n] = C[n];
+    C.clear();
+  }
+};
+
+constexpr int64_t kRescaleSlice = 2048;   // outputs per rescale launch set
+
+// checks, tile tables, results, scratch and uploads (on stream s)
+static int plain_prepare(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, const sfhe_mat* const* Bm,
+                         sfhe_plain_launch launch, hipStream_t s, PlainPrep& P) {
   if (launch != SFHE_PLAIN_FUSED && launch != SFHE_PLAIN_LAUNCH_PER_PRODUCT) { set_error("bad launch mode"); return SFHE_E_INVALID_ARG; }
   for (int n = 0; n < count; ++n) {
     const int rc = plain_check(c, Wm[n], Bm[n]);
     if (rc) return rc;
   }
+  P.count = count;
+  P.launch = launch;
+  P.B.assign(Bm, Bm + count);
   const int N = c->N, lev = c->L - 1, nl = lev + 1;
   const int64_t dw = (int64_t)2 * nl * N;   // words per output sum
   // host tables: tiles of 16 rows per job, their entries (k, row mask) and
   // the weights of each entry, row and prime
-  std::vector<PlainJob> jobs(count);
+  P.jobs.resize(count);
   std::vector<int4> desc;
   std::vector<int> tstart, ek, emask;
   std::vector<u64> ew, ews;
@@ -989,7 +1014,7 @@ static int plain_enqueue(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, 
   for (int n = 0; n < count; ++n) {
     const sfhe_mat *W = Wm[n], *B = Bm[n];
     const int M = W->rows, K = W->cols, Nc = B->cols;
-    jobs[n] = PlainJob{B->data.ptr, B->n_ct, Nc, M, tiles, outs};
+    P.jobs[n] = PlainJob{B->data.ptr, B->n_ct, Nc, M, tiles, outs};
     const int ntile = (M + 15) / 16, ncg = (Nc + 3) / 4;
     std::vector<int> kmask(K);
     std::vector<int64_t> kslot((size_t)K * 16);
@@ -1032,10 +1057,13 @@ static int plain_enqueue(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, 
   }
   tstart.push_back((int)ek.size());
   if (ek.size() > (size_t)0x7FFFFFFF / 16) { set_error("plaintext-weight product: too many entries"); return SFHE_E_INVALID_ARG; }
-  int rc = SFHE_OK;
-  for (int n = 0; n < count && !rc; ++n) {
+  P.n_desc = (int)desc.size();
+  P.products = products;
+  P.outs = outs;
+  P.C.assign(count, nullptr);
+  for (int n = 0; n < count; ++n) {
     sfhe_mat* o = new sfhe_mat();
-    C[n] = o;
+    P.C[n] = o;
     o->ctx = c;
     o->rows = Wm[n]->rows;
     o->cols = Bm[n]->cols;
@@ -1044,33 +1072,20 @@ static int plain_enqueue(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, 
     o->enc = SFHE_ENC_DENSE;
     o->n_ct = (int64_t)o->rows * o->cols;
     o->nnz = o->n_ct;
-    if (!o->data.alloc(&c->alloc, (size_t)o->n_ct * 2 * lev * N)) { rc = SFHE_E_NOMEM; set_error("device allocation failed for a result"); }
+    if (!o->data.alloc(&c->alloc, (size_t)o->n_ct * 2 * lev * N)) { set_error("device allocation failed for a result"); return SFHE_E_NOMEM; }
   }
-  DevBuf<u64> D, d_ew, d_ews;
-  DevBuf<int> d_ts, d_ek, d_em;
-  DevBuf<int4> d_desc;
-  DevBuf<PlainJob> d_jobs;
-  if (!rc && (!D.alloc(&c->alloc, (size_t)std::max<int64_t>(outs, 1) * dw) || !upload(c, d_ts, tstart, s) ||
-              !upload(c, d_ek, ek, s) || !upload(c, d_em, emask, s) || !upload(c, d_ew, ew, s) ||
-              !upload(c, d_ews, ews, s) || !upload(c, d_desc, desc, s) || !upload(c, d_jobs, jobs, s))) {
-    rc = SFHE_E_NOMEM;
+  if (!P.D.alloc(&c->alloc, (size_t)std::max<int64_t>(outs, 1) * dw) || !upload(c, P.ts, tstart, s) ||
+      !upload(c, P.ek, ek, s) || !upload(c, P.em, emask, s) || !upload(c, P.ew, ew, s) || !upload(c, P.ews, ews, s) ||
+      !upload(c, P.desc, desc, s) || !upload(c, P.d_jobs, P.jobs, s) ||
+      !P.scratch.alloc(&c->alloc, (size_t)rescale_scratch_words(c, lev, kRescaleSlice))) {
     set_error("device allocation failed (the sums of every output are held at once)");
+    return SFHE_E_NOMEM;
   }
-  // the timed region: products and rescales (allocation and table uploads are set-up)
-  if (!rc && ev_start) {
-    hipError_t e = hipEventRecord(ev_start, s);
-    if (e != hipSuccess) { rc = SFHE_E_DEVICE; set_error(hipGetErrorString(e)); }
-  }
-  int64_t launches = 0;
-  if (!rc && launch == SFHE_PLAIN_FUSED) {
-    PlainBatch pb{d_jobs.ptr, d_desc.ptr, (int)desc.size(), d_ts.ptr, d_ek.ptr, d_em.ptr, d_ew.ptr, d_ews.ptr, nl, D.ptr};
-    rc = launch_plain_batch(c, pb, s);
-    launches = 1 + (tensor_fp_prime_count(c) > 0 && tensor_fp_prime_count(c) < nl);
-  } else if (!rc) {
-    // one launch per product: weights of every product uploaded once
+  if (launch == SFHE_PLAIN_FUSED) {
+    P.launches = 1 + (tensor_fp_prime_count(c) > 0 && tensor_fp_prime_count(c) < nl);
+  } else {
+    // one launch per product: the weights of every product uploaded once
     std::vector<u64> pw, pws;
-    std::vector<int64_t> pb_slot, pd;
-    std::vector<int> pjob;
     for (int n = 0; n < count; ++n) {
       const sfhe_mat *W = Wm[n], *B = Bm[n];
       for (int i = 0; i < W->rows; ++i) {
@@ -1082,40 +1097,70 @@ static int plain_enqueue(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, 
               pw.push_back(w);
               pws.push_back(hostmath::shoup(w, c->primes[l]));
             }
-            pb_slot.push_back((int64_t)pr.first * B->cols + j);
-            pd.push_back(jobs[n].d0 + (int64_t)i * B->cols + j);
-            pjob.push_back(n);
+            P.pb_slot.push_back((int64_t)pr.first * B->cols + j);
+            P.pd.push_back(P.jobs[n].d0 + (int64_t)i * B->cols + j);
+            P.pjob.push_back(n);
           }
       }
     }
-    DevBuf<u64> d_pw, d_pws;
-    if (!upload(c, d_pw, pw, s) || !upload(c, d_pws, pws, s)) { rc = SFHE_E_NOMEM; set_error("device allocation failed"); }
-    if (!rc) rc = launch_zero(D.ptr, std::max<int64_t>(outs, 1) * dw, s);
-    for (size_t x = 0; x < pb_slot.size() && !rc; ++x) {
-      const sfhe_mat* B = Bm[pjob[x]];
-      rc = launch_plain_product(c, B->data.ptr, B->n_ct, pb_slot[x], d_pw.ptr + x * nl, d_pws.ptr + x * nl,
-                                D.ptr + pd[x] * dw, nl, s);
-      ++launches;
+    if (!upload(c, P.pw, pw, s) || !upload(c, P.pws, pws, s)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
+    P.launches = (int64_t)P.pb_slot.size();
+  }
+  return SFHE_OK;
+}
+
+// the launches alone (nothing allocated, nothing copied): products, then one
+// rescale per output in slices of kRescaleSlice outputs
+static int plain_launch(sfhe_ctx* c, const PlainPrep& P, hipStream_t s) {
+  const int N = c->N, lev = c->L - 1, nl = lev + 1;
+  const int64_t dw = (int64_t)2 * nl * N;
+  int rc = SFHE_OK;
+  if (P.launch == SFHE_PLAIN_FUSED) {
+    PlainBatch pb{P.d_jobs.ptr, P.desc.ptr, P.n_desc, P.ts.ptr, P.ek.ptr, P.em.ptr, P.ew.ptr, P.ews.ptr, nl, P.D.ptr};
+    rc = launch_plain_batch(c, pb, s);
+  } else {
+    rc = launch_zero(P.D.ptr, std::max<int64_t>(P.outs, 1) * dw, s);
+    for (size_t x = 0; x < P.pb_slot.size() && !rc; ++x) {
+      const sfhe_mat* B = P.B[P.pjob[x]];
+      rc = launch_plain_product(c, B->data.ptr, B->n_ct, P.pb_slot[x], P.pw.ptr + x * nl, P.pws.ptr + x * nl,
+                                P.D.ptr + P.pd[x] * dw, nl, s);
     }
   }
-  // rescales in slices of 2048 outputs: the same scratch size every time
-  for (int n = 0; n < count && !rc; ++n) {
-    const int64_t cnt = (int64_t)C[n]->n_ct;
-    for (int64_t o0 = 0; o0 < cnt && !rc; o0 += 2048) {
-      const OutLayout ol{C[n]->data.ptr, 0, true, C[n]->n_ct, o0};
-      const int64_t m = std::min<int64_t>(2048, cnt - o0);
-      const u64* Ds = D.ptr + (jobs[n].d0 + o0) * dw;
-      rc = c->logN == 14 ? rescale_n14(c, lev, Ds, dw, ol, m, s) : rescale_batch(c, lev, Ds, dw, ol, m, s);
+  for (int n = 0; n < P.count && !rc; ++n) {
+    const int64_t cnt = (int64_t)P.C[n]->n_ct;
+    for (int64_t o0 = 0; o0 < cnt && !rc; o0 += kRescaleSlice) {
+      const OutLayout ol{P.C[n]->data.ptr, 0, true, P.C[n]->n_ct, o0};
+      const int64_t m = std::min<int64_t>(kRescaleSlice, cnt - o0);
+      const u64* Ds = P.D.ptr + (P.jobs[n].d0 + o0) * dw;
+      rc = c->logN == 14 ? rescale_n14(c, lev, Ds, dw, ol, m, s, P.scratch.ptr)
+                         : rescale_batch(c, lev, Ds, dw, ol, m, s, P.scratch.ptr);
     }
   }
+  return rc;
+}
+
+// Enqueue the plaintext-weight products of count (W, B) pairs on stream s.
+// ev_start (nullable) is recorded after the set-up, before the first product
+// launch.  On failure every C[n] is NULL.
+static int plain_enqueue(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, const sfhe_mat* const* Bm,
+                         sfhe_plain_launch launch, hipStream_t s, sfhe_mat** C, hipEvent_t ev_start,
+                         int64_t* n_products, int64_t* n_launches, int64_t* n_outputs) {
+  for (int n = 0; n < count; ++n) C[n] = nullptr;
+  PlainPrep P;
+  int rc = plain_prepare(c, count, Wm, Bm, launch, s, P);
+  if (!rc && ev_start) {
+    hipError_t e = hipEventRecord(ev_start, s);
+    if (e != hipSuccess) { rc = SFHE_E_DEVICE; set_error(hipGetErrorString(e)); }
+  }
+  if (!rc) rc = plain_launch(c, P, s);
   if (rc) {
     (void)hipStreamSynchronize(s);
-    for (int n = 0; n < count; ++n) { delete C[n]; C[n] = nullptr; }
-    return rc;
+    return rc;   // P frees the partial results
   }
-  *n_products = products;
-  *n_launches = launches;
-  *n_outputs = outs;
+  *n_products = P.products;
+  *n_launches = P.launches;
+  *n_outputs = P.outs;
+  P.release(C);
   return SFHE_OK;
 }
 
@@ -1163,6 +1208,91 @@ int sfhe_matmul_plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* W
   return plain_batch(c, count, W, B, launch, (hipStream_t)stream, C);
   GUARD_END
 }
+
+// ---------------------------------------------------------------- graphs
+}  // extern "C"
+
+// a plaintext-weight batch captured once into a HIP graph: its tables, sums,
+// scratch and results stay allocated, and every replay recomputes the results
+// from the current contents of the B matrices
+struct sfhe_plain_graph {
+  sfhe_ctx* c = nullptr;
+  PlainPrep P;
+  hipStream_t cs = nullptr;       // the capture stream (default priority)
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  ~sfhe_plain_graph() {
+    if (cs) (void)hipStreamSynchronize(cs);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
+
+extern "C" {
+
+int sfhe_plain_graph_create(sfhe_ctx* c, int32_t count, const sfhe_mat* const* W, const sfhe_mat* const* B,
+                            sfhe_plain_launch launch, void* stream, sfhe_plain_graph** out) {
+  GUARD_BEGIN
+  if (!out) { set_error("out is NULL"); return SFHE_E_INVALID_ARG; }
+  *out = nullptr;
+  if (!c || !W || !B || count < 1) { set_error("NULL argument or count < 1"); return SFHE_E_INVALID_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  sfhe_plain_graph* G = new sfhe_plain_graph();
+  G->c = c;
+  int rc = plain_prepare(c, count, W, B, launch, s, G->P);
+  if (!rc && hipStreamSynchronize(s) != hipSuccess) { set_error("stream synchronize failed"); rc = SFHE_E_DEVICE; }
+  if (!rc && hipStreamCreate(&G->cs) != hipSuccess) { set_error("stream creation failed"); rc = SFHE_E_DEVICE; }
+  // one run outside the capture (sets the kernels' attributes), then the capture
+  if (!rc) rc = plain_launch(c, G->P, G->cs);
+  if (!rc && hipStreamSynchronize(G->cs) != hipSuccess) { set_error("stream synchronize failed"); rc = SFHE_E_DEVICE; }
+  if (!rc && hipStreamBeginCapture(G->cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    set_error("stream capture failed");
+    rc = SFHE_E_DEVICE;
+  }
+  if (!rc) {
+    const int lrc = plain_launch(c, G->P, G->cs);
+    const hipError_t e = hipStreamEndCapture(G->cs, &G->g);
+    if (lrc) rc = lrc;
+    else if (e != hipSuccess) { set_error(hipGetErrorString(e)); rc = SFHE_E_DEVICE; }
+  }
+  if (!rc && hipGraphInstantiate(&G->ge, G->g, nullptr, nullptr, 0) != hipSuccess) {
+    set_error("graph instantiation failed");
+    rc = SFHE_E_DEVICE;
+  }
+  if (rc) { delete G; return rc; }
+  *out = G;
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_plain_graph_launch(sfhe_plain_graph* G, void* stream) {
+  GUARD_BEGIN
+  if (!G) { set_error("NULL graph"); return SFHE_E_INVALID_ARG; }
+  sfhe_ctx* c = G->c;
+  hipStream_t s = (hipStream_t)stream;
+  c->prof_used = 0;
+  c->prof_cat.clear();
+  SFHE_HIP(hipEventRecord(c->ev0, s));
+  SFHE_HIP(hipGraphLaunch(G->ge, s));
+  SFHE_HIP(hipEventRecord(c->ev1, s));
+  c->stats = sfhe_stats{};
+  c->stats.products = G->P.products;
+  c->stats.outputs = G->P.outs;
+  c->stats.tensor_launches = G->P.launches;
+  c->stats_pending = true;
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_plain_graph_result(const sfhe_plain_graph* G, int32_t n, const sfhe_mat** out) {
+  if (!G || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (n < 0 || n >= G->P.count) { set_error("result index out of range"); return SFHE_E_INVALID_ARG; }
+  *out = G->P.C[n];
+  return SFHE_OK;
+}
+
+void sfhe_plain_graph_destroy(sfhe_plain_graph* G) { delete G; }
 
 // ---------------------------------------------------------------- serving
 }  // extern "C"

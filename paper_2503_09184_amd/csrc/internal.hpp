@@ -252,14 +252,21 @@ struct OutLayout {
   bool chunked;
   int64_t n_ct, elem_base;
 };
-int rescale_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, OutLayout out, int64_t batch, hipStream_t s);
+// scratch (nullable): rescale_scratch_words(c, lev, batch) words the call
+// uses instead of allocating (for launches captured into a graph)
+int rescale_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, OutLayout out, int64_t batch, hipStream_t s,
+                  u64* scratch = nullptr);
+inline int64_t rescale_scratch_words(const sfhe_ctx* c, int lev, int64_t batch) {
+  return c->logN == 14 ? batch * 2 * c->N : batch * 2 * c->N * (1 + lev);
+}
 // N = 2^14 only: Rescale((d0, d1) + KeySwitch(d2)) for n lazy sums D[b]
 // (stride dw words; rows d0, d1, d2 of lev + 1 primes, NTT domain) in four
 // fused transform kernels; the result goes to out (NTT domain, lev primes)
 int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s);
 // N = 2^14 only: Rescale((d0, d1)) for n sums D[b] (stride dw words, rows d0,
 // d1 of lev + 1 primes, NTT domain) in two transform kernels
-int rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s);
+int rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s,
+                u64* scratch = nullptr);
 bool keyswitch_rescale_n14_supported(const sfhe_ctx* c);
 // chunked out[oidx[o]] += sum of limb-major t[p] for p in seg[o] .. seg[o+1]-1 (rows [2][nl][N])
 int launch_segment_sum(const sfhe_ctx* c, int nl, const u64* t, u64* out, int64_t n_ct, const int* d_seg,

@@ -244,32 +244,35 @@ __global__ void rescale_finish_kernel(const u64* in, int64_t istride, int lev, c
     ol.base[b * ol.stride + ((int64_t)p * lev + i) * N + t] = v;
 }
 
-int rescale_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, OutLayout out, int64_t batch, hipStream_t s) {
+int rescale_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, OutLayout out, int64_t batch, hipStream_t s,
+                  u64* scratch) {
   if (batch <= 0) return SFHE_OK;
   if (lev < 1) { set_error("rescale: level 0 has no prime to drop"); return SFHE_E_LEVEL; }
   const int N = c->N, nl = lev + 1;
-  DevBuf<u64> last, R;
-  if (!last.alloc(&c->alloc, (size_t)batch * 2 * N) || !R.alloc(&c->alloc, (size_t)batch * 2 * lev * N)) {
+  DevBuf<u64> last_b, R_b;
+  if (!scratch && (!last_b.alloc(&c->alloc, (size_t)batch * 2 * N) || !R_b.alloc(&c->alloc, (size_t)batch * 2 * lev * N))) {
     set_error("rescale: device allocation failed");
     return SFHE_E_NOMEM;
   }
+  u64* last = scratch ? scratch : last_b.ptr;
+  u64* R = scratch ? scratch + (size_t)batch * 2 * N : R_b.ptr;
   unsigned gy, gz;
   grid_rows(batch * 2, gy, gz);
   hipLaunchKernelGGL(gather_last_kernel, dim3((N + 255) / 256, gy, gz), dim3(256), 0, s, in, istride, nl, lev,
-                     last.ptr, batch, c->dp);
+                     last, batch, c->dp);
   SFHE_HIP(hipGetLastError());
   int pos[2 * kMaxBasis], pr[2 * kMaxBasis];
   pos[0] = 0; pr[0] = lev;
-  int rc = launch_ntt(c, last.ptr, batch * 2, N, 1, pos, pr, true, s);
+  int rc = launch_ntt(c, last, batch * 2, N, 1, pos, pr, true, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(rescale_lift_kernel, dim3((N + 255) / 256, gy, gz), dim3(256), 0, s, last.ptr, lev, R.ptr, batch,
+  hipLaunchKernelGGL(rescale_lift_kernel, dim3((N + 255) / 256, gy, gz), dim3(256), 0, s, last, lev, R, batch,
                      c->dp);
   SFHE_HIP(hipGetLastError());
   for (int r = 0; r < 2 * lev; ++r) { pos[r] = r; pr[r] = r % lev; }
-  rc = launch_ntt(c, R.ptr, batch, (int64_t)2 * lev * N, 2 * lev, pos, pr, false, s);
+  rc = launch_ntt(c, R, batch, (int64_t)2 * lev * N, 2 * lev, pos, pr, false, s);
   if (rc) return rc;
   grid_rows(batch * 2 * lev, gy, gz);
-  hipLaunchKernelGGL(rescale_finish_kernel, dim3((N + 255) / 256, gy, gz), dim3(256), 0, s, in, istride, lev, R.ptr,
+  hipLaunchKernelGGL(rescale_finish_kernel, dim3((N + 255) / 256, gy, gz), dim3(256), 0, s, in, istride, lev, R,
                      out, c->d_rescale.ptr + lev, batch, c->dp);
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;

@@ -591,7 +591,7 @@ bool keyswitch_rescale_n14_supported(const sfhe_ctx* c) {
   return c->logN == n14::kLogN && c->alpha >= 1 && c->alpha <= 4 && c->dnum <= 4;
 }
 
-int rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s) {
+int rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s, u64* scratch) {
   if (n <= 0) return SFHE_OK;
   if (c->logN != n14::kLogN) { set_error("rescale_n14: N = 2^14 only"); return SFHE_E_INVALID_ARG; }
   if (lev < 1) { set_error("rescale: level 0 has no prime to drop"); return SFHE_E_LEVEL; }
@@ -606,8 +606,8 @@ int rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, i
     attr = true;
   }
   DevBuf<u64> r;
-  if (!r.alloc(&c->alloc, (size_t)n * 2 * kN)) { set_error("rescale: device allocation failed"); return SFHE_E_NOMEM; }
-  Rs14Args a{D, dw, r.ptr, c->d_rescale.ptr + lev, lev, lev + 1};
+  if (!scratch && !r.alloc(&c->alloc, (size_t)n * 2 * kN)) { set_error("rescale: device allocation failed"); return SFHE_E_NOMEM; }
+  Rs14Args a{D, dw, scratch ? scratch : r.ptr, c->d_rescale.ptr + lev, lev, lev + 1};
   const dim3 blk(n14::kThreads);
   hipLaunchKernelGGL(rs14_a_kernel, dim3((unsigned)(n * 2)), blk, lds, s, a, c->dp);
   SFHE_HIP(hipGetLastError());

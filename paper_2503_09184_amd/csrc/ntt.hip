@@ -98,10 +98,12 @@ __global__ void __launch_bounds__(n14::kThreads, 4) ntt14_kernel(NttRows R, DevP
 // ---- N = 2^15: the first forward stage (last inverse stage) across the two
 // halves, then each half as a 2^14-point transform with its own tables ----
 // grid (2^14 / 256, rows): x_i, x_{i + 2^14} -> x_i + w x_{i+2^14}, x_i - w x_{i+2^14}
-__global__ void __launch_bounds__(256) ntt15_first_kernel(NttRows R, DevParams dp) {
+__global__ void __launch_bounds__(256) ntt15_first_kernel(NttRows R, int64_t rows, DevParams dp) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  const int64_t g = blockIdx.y / R.nrow;
-  const int r = blockIdx.y % R.nrow;
+  const int64_t row = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
+  if (row >= rows) return;
+  const int64_t g = row / R.nrow;
+  const int r = (int)(row % R.nrow);
   u64* p = R.base + g * R.bstride + (int64_t)R.pos[r] * (2 * n14::kN);
   const PrimeDev& P = dp.pr[R.prime[r]];
   const u64 q = P.q;
@@ -111,10 +113,12 @@ __global__ void __launch_bounds__(256) ntt15_first_kernel(NttRows R, DevParams d
 }
 // x_i, x_{i + 2^14} -> x_i + x_{i+2^14}, (x_i - x_{i+2^14}) w^-1 (N^-1 is
 // applied by the halves' transforms)
-__global__ void __launch_bounds__(256) ntt15_last_kernel(NttRows R, DevParams dp) {
+__global__ void __launch_bounds__(256) ntt15_last_kernel(NttRows R, int64_t rows, DevParams dp) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  const int64_t g = blockIdx.y / R.nrow;
-  const int r = blockIdx.y % R.nrow;
+  const int64_t row = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
+  if (row >= rows) return;
+  const int64_t g = row / R.nrow;
+  const int r = (int)(row % R.nrow);
   u64* p = R.base + g * R.bstride + (int64_t)R.pos[r] * (2 * n14::kN);
   const PrimeDev& P = dp.pr[R.prime[r]];
   const u64 q = P.q;
@@ -160,7 +164,6 @@ int launch_ntt(const sfhe_ctx* c, u64* base, int64_t batch, int64_t bstride, int
   const int64_t blocks = batch * nrow;
   if (blocks > 0x7FFFFFFF / 2) { set_error("ntt: batch too large"); return SFHE_E_INVALID_ARG; }
   if (c->logN == n14::kLogN + 1) {
-    if (blocks > 65535) { set_error("ntt: batch too large"); return SFHE_E_INVALID_ARG; }
     static bool attr15 = false;
     if (!attr15) {
       SFHE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&ntt15_half_kernel<false>),
@@ -170,15 +173,17 @@ int launch_ntt(const sfhe_ctx* c, u64* base, int64_t batch, int64_t bstride, int
       attr15 = true;
     }
     const size_t lds = (size_t)n14::kLdsWords * sizeof(u64);
-    const dim3 ew(n14::kN / 256, (unsigned)blocks);
+    // element-wise grid: (2^14 / 256, rows split over y and z)
+    const unsigned gy = blocks < 65535 ? (unsigned)blocks : 65535u;
+    const dim3 ew(n14::kN / 256, gy, (unsigned)((blocks + gy - 1) / gy));
     if (!inverse) {
-      hipLaunchKernelGGL(ntt15_first_kernel, ew, dim3(256), 0, s, R, c->dp);
+      hipLaunchKernelGGL(ntt15_first_kernel, ew, dim3(256), 0, s, R, blocks, c->dp);
       SFHE_HIP(hipGetLastError());
       hipLaunchKernelGGL(ntt15_half_kernel<false>, dim3((unsigned)(2 * blocks)), dim3(n14::kThreads), lds, s, R, c->dp);
     } else {
       hipLaunchKernelGGL(ntt15_half_kernel<true>, dim3((unsigned)(2 * blocks)), dim3(n14::kThreads), lds, s, R, c->dp);
       SFHE_HIP(hipGetLastError());
-      hipLaunchKernelGGL(ntt15_last_kernel, ew, dim3(256), 0, s, R, c->dp);
+      hipLaunchKernelGGL(ntt15_last_kernel, ew, dim3(256), 0, s, R, blocks, c->dp);
     }
     SFHE_HIP(hipGetLastError());
     return SFHE_OK;

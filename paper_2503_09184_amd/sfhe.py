@@ -30,7 +30,8 @@ EXPORTED = [
     "sfhe_ntt", "sfhe_tensor", "sfhe_keyswitch", "sfhe_rescale",
     "sfhe_encode_matrix", "sfhe_matmul_plain", "sfhe_matmul_plain_batch",
     "sfhe_server_create", "sfhe_server_submit", "sfhe_server_step", "sfhe_server_poll", "sfhe_server_status",
-    "sfhe_server_destroy",
+    "sfhe_server_destroy", "sfhe_plain_graph_create", "sfhe_plain_graph_launch", "sfhe_plain_graph_result",
+    "sfhe_plain_graph_destroy",
 ]
 
 PLAIN_LAUNCH = {"fused": 0, "per_product": 1}
@@ -117,6 +118,12 @@ def lib():
                                          ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.sfhe_server_destroy.argtypes = [vp]
         L.sfhe_server_destroy.restype = None
+        L.sfhe_plain_graph_create.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp,
+                                              ctypes.POINTER(vp)]
+        L.sfhe_plain_graph_launch.argtypes = [vp, vp]
+        L.sfhe_plain_graph_result.argtypes = [vp, i32, ctypes.POINTER(vp)]
+        L.sfhe_plain_graph_destroy.argtypes = [vp]
+        L.sfhe_plain_graph_destroy.restype = None
         _lib = L
     return _lib
 
@@ -152,6 +159,48 @@ class Matrix:
     def close(self):
         if self._h is not None and self._h.value:
             lib().sfhe_mat_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Borrowed(Matrix):
+    """A matrix handle owned by another object (never destroyed here)."""
+
+    def close(self):
+        self._h = None
+
+
+class PlainGraph:
+    """A plaintext-weight batch captured into a HIP graph (library handle)."""
+
+    def __init__(self, ctx, Ws, Bs, launch="fused", stream=None):
+        self.ctx = ctx
+        self._keep = (list(Ws), list(Bs))
+        n = len(Ws)
+        wh = (ctypes.c_void_p * n)(*[W.handle.value for W in Ws])
+        bh = (ctypes.c_void_p * n)(*[B.handle.value for B in Bs])
+        h = ctypes.c_void_p()
+        _check(lib().sfhe_plain_graph_create(ctx._h, n, wh, bh, PLAIN_LAUNCH[launch], _stream_handle(stream),
+                                             ctypes.byref(h)))
+        self._h = h
+        self.count = n
+
+    def launch(self, stream=None):
+        _check(lib().sfhe_plain_graph_launch(self._h, _stream_handle(stream)))
+
+    def result(self, n):
+        h = ctypes.c_void_p()
+        _check(lib().sfhe_plain_graph_result(self._h, int(n), ctypes.byref(h)))
+        return _Borrowed(self.ctx, h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sfhe_plain_graph_destroy(self._h)
         self._h = None
 
     def __del__(self):

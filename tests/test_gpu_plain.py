@@ -176,3 +176,34 @@ def test_plain_n14_large_last_prime(torch_cuda):
     cts, _, _ = orc.matmul_plain(Wt, B, "ell", 13, 40, outputs=sample, threads=_threads())
     for n, (i, j) in enumerate(sample):
         assert np.array_equal(ctx.export_ct(C, i, j), cts[n]), (i, j)
+
+
+@pytest.mark.parametrize("launch", ["fused", "per_product"])
+def test_plain_graph_replays_match_eager(torch_cuda, launch):
+    """The batch captured into a HIP graph: three replays, with eager library
+    work between them, each give the eager results bit for bit."""
+    from paper_2503_09184_amd import sfhe
+    ctx, _ = pair(HYB_SMALL, 21)
+    shapes = [(5, 9, 3, 0.5), (33, 4, 6, 0.7), (16, 20, 1, 0.0)]
+    Ws, Bs = [], []
+    for n, (M, K, Nc, s) in enumerate(shapes):
+        Wt, B = W.operands(M, K, Nc, s, 70 + n)
+        Ws.append(ctx.encode_weights(Wt, "csr", 40))
+        Bs.append(ctx.encrypt(B, "dense", 95 + n, 1))
+    eager = ctx.matmul_plain_batch(Ws, Bs, "fused")
+    want = [[ctx.export_ct(eager[n], i, j) for i in range(M) for j in range(Nc)]
+            for n, (M, K, Nc, s) in enumerate(shapes)]
+    note("plain graph %s" % launch)
+    g = sfhe.PlainGraph(ctx, Ws, Bs, launch)
+    for rep in range(3):
+        g.launch()
+        st = ctx.last_stats()
+        assert st.products == sum(int(np.count_nonzero(W.operands(M, K, Nc, s, 70 + n)[0])) * Nc
+                                  for n, (M, K, Nc, s) in enumerate(shapes))
+        for n, (M, K, Nc, s) in enumerate(shapes):
+            C = g.result(n)
+            got = [ctx.export_ct(C, i, j) for i in range(M) for j in range(Nc)]
+            for x, y in zip(got, want[n]):
+                assert np.array_equal(x, y), (rep, n)
+        ctx.matmul_plain(Ws[0], Bs[0]).close()          # eager work between replays
+    g.close()
