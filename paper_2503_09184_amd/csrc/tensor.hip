@@ -85,6 +85,7 @@ struct ArithFp {   // q < 2^42: fp64 residues, Karatsuba middle term
     a.ss += fp_mulmod_lazy(as, bs, q, qinv);
   }
   static constexpr int kFold = 1024;   // each product adds < 1.5 q to a sum: stay below 2^53
+  static constexpr int kGroup = 4;     // rows whose operands are read from LDS together
   __device__ void fold(Acc& a) const {
     a.d0 = fp_fold(a.d0, q, qinv);
     a.d2 = fp_fold(a.d2, q, qinv);
@@ -127,6 +128,7 @@ struct ArithInt {   // q < 2^61: 128-bit integer sums, Karatsuba middle term
     mac_wide(a.ss, as, bs);
   }
   static constexpr int kFold = 16;     // 16 terms below 2^124 (plus a residue) stay below 2^128
+  static constexpr int kGroup = 4;
   __device__ void fold(Acc& a) const {
     a.d0 = U128{reduce_wide(a.d0, q, mu_hi, mu_lo), 0};
     a.d2 = U128{reduce_wide(a.d2, q, mu_hi, mu_lo), 0};
@@ -137,6 +139,79 @@ struct ArithInt {   // q < 2^61: 128-bit integer sums, Karatsuba middle term
     d0 = reduce_wide(a.d0, q, mu_hi, mu_lo);
     d2 = reduce_wide(a.d2, q, mu_hi, mu_lo);
     d1 = sub_mod(sub_mod(reduce_wide(a.ss, q, mu_hi, mu_lo), d0, q), d2, q);
+  }
+};
+
+// Primes q = 2^60 - c with c < 2^20 (the largest NTT primes below 2^60):
+// carry-save sums without Karatsuba.  An operand x < 2^60 is staged as its
+// 30-bit halves (xl, xh) in the two 32-bit words of a u64, and a product x y
+// adds its partials xl yl, xl yh + xh yl, xh yh (each below 2^60) to sums L,
+// M, H of weights 1, 2^30, 2^60 with one v_mad_u64_u32 each: 16 per
+// ciphertext product, no carries.  Every kFold entries the sums are folded
+// back: carries move up (L into M, M into H), and since 2^60 = c (mod q),
+// H 2^60 = (H mod 2^32) c + t 2^32 with t = (H >> 32) c < 2^52, of which
+// (H mod 2^32) c goes into L, (t mod 2^28) 4 into M and t >> 28 stays in H.
+// Afterwards L < 2^53, M < 2^31, H < 2^24, and kFold more entries add at most
+// 16 partials below 2^60 - 2^31 to a sum: every sum stays below 2^64.
+__device__ __forceinline__ u32 lo32(u64 x) { return (u32)x; }
+__device__ __forceinline__ u32 hi32(u64 x) { return (u32)(x >> 32); }
+__device__ __forceinline__ u64 madw(u32 a, u32 b, u64 acc) { return (u64)a * b + acc; }
+
+struct ArithInt60 {
+  typedef u64 Val;   // (x mod 2^30) | (x >> 30) << 32
+  struct Sums {
+    u64 L, M, H;
+  };
+  struct Acc {
+    Sums d0, d1, d2;
+  };
+  u64 q, mu_hi, mu_lo;
+  u32 c;   // 2^60 - q
+  __device__ ArithInt60(const FpLimb&, const PrimeDev& P)
+      : q(P.q), mu_hi(P.mu_hi), mu_lo(P.mu_lo), c((u32)((1ull << 60) - P.q)) {}
+  __device__ static Val load(u64 x) { return (x & 0x3fffffffull) | ((x >> 30) << 32); }
+  __device__ static void zero(Acc& a) { a.d0 = a.d1 = a.d2 = Sums{0, 0, 0}; }
+  __device__ static Val sum(Val x, Val) { return x; }   // no Karatsuba term
+  __device__ static void mac1(Sums& s, Val x, Val y) {
+    s.L = madw(lo32(x), lo32(y), s.L);
+    s.M = madw(lo32(x), hi32(y), s.M);
+    s.M = madw(hi32(x), lo32(y), s.M);
+    s.H = madw(hi32(x), hi32(y), s.H);
+  }
+  __device__ void mac(Acc& a, Val a0, Val a1, Val, Val b0, Val b1, Val) const {
+    mac1(a.d0, a0, b0);
+    mac1(a.d1, a0, b1);
+    mac1(a.d1, a1, b0);
+    mac1(a.d2, a1, b1);
+  }
+  static constexpr int kFold = 4;   // entries between folds (each adds at most 4 partials to a sum)
+  static constexpr int kGroup = 2;
+  __device__ void fold1(Sums& s) const {
+    s.M += s.L >> 30;
+    s.H += s.M >> 30;
+    const u64 t = madw(hi32(s.H), c, 0);
+    s.L = madw(lo32(s.H), c, s.L & 0x3fffffffull);
+    s.M = (s.M & 0x3fffffffull) + ((t & 0xfffffffull) << 2);
+    s.H = t >> 28;
+  }
+  __device__ void fold(Acc& a) const {
+    fold1(a.d0);
+    fold1(a.d1);
+    fold1(a.d2);
+  }
+  // L + M 2^30 + H 2^60 (after a fold) as 128 bits, reduced
+  __device__ u64 residue(const Sums& s) const {
+    U128 v{s.L, 0};
+    add_wide(v, U128{s.M << 30, s.M >> 34});
+    add_wide(v, U128{s.H << 60, s.H >> 4});
+    return reduce_wide(v, q, mu_hi, mu_lo);
+  }
+  __device__ void final(const Acc& a, u64& d0, u64& d1, u64& d2) const {
+    Acc f = a;
+    fold(f);
+    d0 = residue(f.d0);
+    d1 = residue(f.d1);
+    d2 = residue(f.d2);
   }
 };
 
@@ -280,7 +355,7 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
     }
 #pragma unroll
     for (int c = 0; c < CPW; ++c) bs[c] = Arith::sum(b0[c], b1[c]);
-    constexpr int G = RPW > 4 ? 4 : RPW;   // rows read from LDS together
+    constexpr int G = RPW > Arith::kGroup ? Arith::kGroup : RPW;   // rows read from LDS together
 #pragma unroll
     for (int g0 = 0; g0 < RPW; g0 += G) {
       Val a0[G], a1[G];
@@ -408,14 +483,15 @@ int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, con
                         hipEvent_t fp_start, hipEvent_t fp_stop) {
   if (tl.rows <= 0) return SFHE_OK;
   // primes below 2^42 use the fp64 residue arithmetic, the others 128-bit integers
-  FpLimbs ffp{}, fint{};
+  FpLimbs ffp{}, fint{}, f60{};
   for (int l = 0; l < c->L; ++l) {
     const u64 q = c->primes[l];
     FpLimb F{};
     F.limb = l;
     F.q = (double)q;
     F.qinv = 1.0 / (double)q;
-    FpLimbs& dst = q < (1ull << 42) ? ffp : fint;
+    const bool near60 = q < (1ull << 60) && (1ull << 60) - q < (1ull << 20);
+    FpLimbs& dst = q < (1ull << 42) ? ffp : near60 ? f60 : fint;
     dst.l[dst.n++] = F;
   }
   if (fp_start) SFHE_HIP(hipEventRecord(fp_start, s));
@@ -426,6 +502,9 @@ int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, con
   if (!rc)
     rc = bsp ? launch_block<ArithInt, 4, 1, true>(c, tl, fint, A, B, D, s)
              : launch_block<ArithInt, 4, 1, false>(c, tl, fint, A, B, D, s);
+  if (!rc)
+    rc = bsp ? launch_block<ArithInt60, 4, 1, true>(c, tl, f60, A, B, D, s)
+             : launch_block<ArithInt60, 4, 1, false>(c, tl, f60, A, B, D, s);
   return rc;
 }
 

@@ -251,10 +251,13 @@ def test_matmul_mixed_prime_sizes_all_outputs(torch_cuda, sched):
     _all_outputs_equal(ctx, C, cts, 6, 5, sched)
 
 
-def test_long_rows_fold_the_sums(torch_cuda):
-    """K = 600 dense: every lazy sum crosses the fold points of all three
-    tensor arithmetics (32, 256 and 512 products)."""
-    P = dict(log_n=10, q_bits=[61, 59, 40], p_bits=[61, 61], dnum=2)
+@pytest.mark.parametrize("q_bits", [[61, 59, 40], [60, 60, 40]])
+def test_long_rows_fold_the_sums(torch_cuda, q_bits):
+    """K = 600 dense: every lazy sum crosses the fold points of the tensor
+    arithmetics many times (the 128-bit sums for the 61- and 59-bit primes,
+    the carry-save sums for primes just below 2^60, the fp64 sums below
+    2^42)."""
+    P = dict(log_n=10, q_bits=q_bits, p_bits=[61, 61], dnum=2)
     ctx, orc = pair(P, 18)
     A, B = W.operands(3, 600, 2, 0.0, 42)
     note("K=600 lazy")
