@@ -94,6 +94,23 @@ def lib():
                                   ctypes.c_uint64, ctypes.c_uint64, _i32p, _i32p, ctypes.c_int,
                                   ctypes.c_int, _u64p, _f64p, _f64p]
         L.orc_matmul2.restype = ctypes.c_int
+        L.orc_galois.argtypes = [ctypes.c_void_p, ctypes.c_long]
+        L.orc_galois.restype = ctypes.c_uint64
+        L.orc_encode_slots.argtypes = [ctypes.c_void_p, _f64p, ctypes.c_int, _i64p]
+        L.orc_encode_slots.restype = ctypes.c_int
+        L.orc_decrypt_slot.argtypes = [ctypes.c_void_p, ctypes.c_int, _u64p, ctypes.c_double, ctypes.c_int]
+        L.orc_decrypt_slot.restype = ctypes.c_double
+        L.orc_automorphism.argtypes = [ctypes.c_void_p, ctypes.c_int, _u64p, ctypes.c_uint64, _u64p]
+        L.orc_rotkey.argtypes = [ctypes.c_void_p, ctypes.c_uint64, _u64p, _i64p]
+        L.orc_rotate.argtypes = [ctypes.c_void_p, ctypes.c_int, _u64p, ctypes.c_long, _u64p]
+        L.orc_rotate.restype = ctypes.c_int
+        L.orc_encrypt_slots.argtypes = [ctypes.c_void_p, _f64p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.c_uint64, _u64p]
+        L.orc_encrypt_slots.restype = ctypes.c_int
+        L.orc_matmul_chunked.argtypes = [ctypes.c_void_p, _f64p, ctypes.c_int, ctypes.c_int, _f64p, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_uint64, ctypes.c_uint64, _i32p, _i32p, ctypes.c_int, _u64p, _f64p]
+        L.orc_matmul_chunked.restype = ctypes.c_int
         L.orc_weight.argtypes = [ctypes.c_double, ctypes.c_double, _i64p]
         L.orc_weight.restype = ctypes.c_int
         L.orc_matmul_plain.argtypes = [ctypes.c_void_p, _f64p, ctypes.c_int, ctypes.c_int, _f64p, ctypes.c_int,
@@ -322,6 +339,76 @@ class Oracle:
     def plain_out_scale(self, log2_scale_w=40):
         """Scale of a plaintext-weight product after its rescale."""
         return 2.0 ** (log2_scale_w + self.log2_scale) / float(self.q[-1])
+
+    # ---- chunks of several values per ciphertext (Sec. 3.2, R10) ----------
+    def galois(self, r):
+        return int(lib().orc_galois(self._h, int(r)))
+
+    def encode_slots(self, z):
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        m = np.zeros(self.n, dtype=np.int64)
+        if lib().orc_encode_slots(self._h, _p(z, _f64p), len(z), _p(m, _i64p)) != 0:
+            raise ValueError("values do not fit")
+        return m
+
+    def decrypt_slot(self, level, ct, scale, slot):
+        ct = _u64(ct)
+        return lib().orc_decrypt_slot(self._h, int(level), _p(ct, _u64p), float(scale), int(slot))
+
+    def automorphism(self, a, g):
+        a = _u64(a)
+        out = np.zeros_like(a)
+        lib().orc_automorphism(self._h, a.shape[0], _p(a, _u64p), ctypes.c_uint64(g), _p(out, _u64p))
+        return out
+
+    def rotkey(self, g):
+        nb = self.L + self.alpha
+        key = np.zeros((self.dnum, 2, nb, self.n), dtype=np.uint64)
+        e = np.zeros((self.dnum, self.n), dtype=np.int64)
+        lib().orc_rotkey(self._h, ctypes.c_uint64(g), _p(key, _u64p), _p(e, _i64p))
+        return key, e
+
+    def rotate(self, level, ct, r):
+        ct = _u64(ct)
+        out = np.zeros_like(ct)
+        if lib().orc_rotate(self._h, int(level), _p(ct, _u64p), int(r), _p(out, _u64p)) != 0:
+            raise ValueError("rotate failed")
+        return out
+
+    def encrypt_slots(self, z, seed, operand, chunk):
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        ct = np.zeros((2, self.L, self.n), dtype=np.uint64)
+        if lib().orc_encrypt_slots(self._h, _p(z, _f64p), len(z), ctypes.c_uint64(seed), ctypes.c_uint64(operand),
+                                   ctypes.c_uint64(chunk), _p(ct, _u64p)) != 0:
+            raise ValueError("encrypt failed")
+        return ct
+
+    def chunked_scale(self):
+        """Scale of a chunked product's result: Delta^3 / (q_{L-1} q_{L-2})."""
+        return 2.0 ** (3 * self.log2_scale) / float(self.q[-1]) / float(self.q[-2])
+
+    def matmul_chunked(self, A, B, enc, sched, chunk, seedA, seedB, outputs=None, opA=0, opB=1, decrypt=True):
+        """Algorithm 1 at chunk size `chunk`: (result chunks [n][2][L-3][N], values of
+        the listed outputs or None)."""
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        M, K = A.shape
+        K2, Nc = B.shape
+        assert K == K2
+        if outputs is None:
+            outputs = [(i, j) for i in range(M) for j in range(Nc)]
+        rows = np.asarray([o[0] for o in outputs], dtype=np.int32)
+        cols = np.asarray([o[1] for o in outputs], dtype=np.int32)
+        nchunks = (M * Nc + chunk - 1) // chunk
+        out = np.zeros((nchunks, 2, self.L - 2, self.n), dtype=np.uint64)
+        vals = np.zeros(len(outputs), dtype=np.float64)
+        rc = lib().orc_matmul_chunked(self._h, _p(A, _f64p), M, K, _p(B, _f64p), Nc, ENC[enc], SCHED[sched], int(chunk),
+                                      ctypes.c_uint64(seedA), ctypes.c_uint64(opA), ctypes.c_uint64(seedB),
+                                      ctypes.c_uint64(opB), _p(rows, _i32p), _p(cols, _i32p), len(outputs),
+                                      _p(out, _u64p), _p(vals, _f64p) if decrypt else None)
+        if rc != 0:
+            raise ValueError("oracle chunked matmul failed (%d)" % rc)
+        return out, (vals if decrypt else None)
 
 
 def weight(w, log2_scale_w):

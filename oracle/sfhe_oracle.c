@@ -56,7 +56,7 @@ typedef unsigned __int128 u128;
 
 enum { ORC_ENC_DENSE = 0, ORC_ENC_NAIVE = 1, ORC_ENC_CSR = 2, ORC_ENC_ELL = 3 };
 enum { ORC_SCHED_PER_PRODUCT = 0, ORC_SCHED_LAZY = 1 };
-enum { TAG_SK = 1, TAG_RLK_A = 2, TAG_RLK_E = 3, TAG_ENC_A = 4, TAG_ENC_E = 5 };
+enum { TAG_SK = 1, TAG_RLK_A = 2, TAG_RLK_E = 3, TAG_ENC_A = 4, TAG_ENC_E = 5, TAG_ROT_A = 6, TAG_ROT_E = 7 };
 
 /* ------------------------------------------------------------------ */
 /* modular arithmetic, plain                                           */
@@ -498,7 +498,11 @@ void orc_moddown(const orc_ctx* c, int lev, const u64* acc, u64* out) {
  * in d2[lev+1][N], out ks[2][lev+1][N], both coefficient domain, with
  * ks0 + ks1*s = d2*s^2 + small (mod Q_lev).  Per digit: ModUp, then the
  * products with the key (b_j, a_j) summed over the digits, then ModDown. */
-void orc_keyswitch(const orc_ctx* c, int lev, const u64* d2, u64* ks) {
+static void ks_with(const orc_ctx* c, int lev, const u64* d2, const u64* key_ntt, u64* ks);
+void orc_keyswitch(const orc_ctx* c, int lev, const u64* d2, u64* ks) { ks_with(c, lev, d2, c->rlk_ntt, ks); }
+/* the same with any key [dnum][2][nb][N] (NTT domain) switching from its
+ * target secret to s */
+static void ks_with(const orc_ctx* c, int lev, const u64* d2, const u64* key_ntt, u64* ks) {
   int N = c->N, nl = lev + 1, eb[ORC_MAXB];
   int ne = ext_basis(c, lev, eb);
   u64* acc = calloc((size_t)2 * ne * N, sizeof(u64));   /* NTT domain */
@@ -511,7 +515,7 @@ void orc_keyswitch(const orc_ctx* c, int lev, const u64* d2, u64* ks) {
       u64* xe = x + (size_t)e * N;
       ntt_fwd(c, r, xe);
       for (int p = 0; p < 2; p++) {
-        const u64* kp = c->rlk_ntt + (((size_t)j * 2 + p) * c->nb + r) * N;
+        const u64* kp = key_ntt + (((size_t)j * 2 + p) * c->nb + r) * N;
         u64* A = acc + ((size_t)p * ne + e) * N;
         for (int t = 0; t < N; t++) A[t] = addm(A[t], mulm(xe[t], kp[t], c->q[r]), c->q[r]);
       }
@@ -1014,4 +1018,339 @@ int orc_matmul_plain(const orc_ctx* c, const double* W, int M, int K, const doub
   free(encB);
   struct_free(&S);
   return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* chunks of several values per ciphertext (Sec. 3.2) and Algorithm 1   */
+/* with its rotations and slot-zero mask (Sec. 3.3.1)                   */
+/* ------------------------------------------------------------------ */
+/* R10 slot j of a ciphertext is its plaintext's value at zeta^(5^j),
+ *     zeta = exp(i pi / N).  Real values z_0..z_{n-1} in slots 0..n-1 are the
+ *     polynomial m_t = nearbyint(sum_j z_j 2 Delta / N cos(pi (5^j t mod 2N) / N)),
+ *     summed in j order (n = 1 is R1's encoding).  A rotation by r (slot j
+ *     receives slot j + r, indices mod N/2) applies X -> X^g, g = 5^r mod 2N,
+ *     to both polys and switches c1(X^g) from s(X^g) back to s with a key
+ *     built like the relinearisation key (target s(X^g) for s^2; randomness
+ *     tags 6 and 7 with fields (g, j[, r])).  The slot-zero mask is the
+ *     plaintext encoding 1.0 in slot 0 (R1) at scale Delta. */
+
+/* 5^r mod 2N for any integer r (5 has order N/2 modulo 2N) */
+u64 orc_galois(const orc_ctx* c, long r) {
+  long h = c->N / 2;
+  long e = ((r % h) + h) % h;
+  u64 g = 1, m = 2 * (u64)c->N;
+  for (long x = 0; x < e; x++) g = (g * 5) % m;
+  return g;
+}
+
+/* cos(pi e / N) for 0 <= e < 2N from the host libm table (sign flip above N) */
+static double cos2n(const orc_ctx* c, u64 e) { return e < (u64)c->N ? c->cosv[e] : -c->cosv[e - c->N]; }
+
+int orc_encode_slots(const orc_ctx* c, const double* z, int n, i64* m) {
+  double sz[64];
+  u64 g[64], m2 = 2 * (u64)c->N;
+  if (n < 1 || n > 64 || n > c->N / 2) return -1;
+  for (int j = 0; j < n; j++) {
+    sz[j] = ldexp(z[j], (int)c->log2_scale + 1 - c->logN);
+    if (!(fabs(sz[j]) < 4.0e18 / n)) return -1;
+    g[j] = orc_galois(c, j);
+  }
+  for (int t = 0; t < c->N; t++) {
+    double acc = 0.0;
+    for (int j = 0; j < n; j++) acc += sz[j] * cos2n(c, (g[j] * (u64)t) % m2);
+    m[t] = (i64)nearbyint(acc);
+  }
+  return 0;
+}
+
+/* slot `slot` of the plaintext m[lev+1][N] (coefficient domain) at `scale` */
+double orc_decode_slot(const orc_ctx* c, int lev, const u64* m, double scale, int slot) {
+  u64 g = orc_galois(c, slot), m2 = 2 * (u64)c->N;
+  long double s = 0.0L;
+  for (int t = 0; t < c->N; t++) s += crt_centered(c, lev + 1, m + t, c->N) * (long double)cos2n(c, (g * (u64)t) % m2);
+  return (double)(s / (long double)scale);
+}
+double orc_decrypt_slot(const orc_ctx* c, int lev, const u64* ct, double scale, int slot) {
+  u64* m = malloc(sizeof(u64) * (size_t)(lev + 1) * c->N);
+  orc_decrypt_poly(c, lev, ct, m);
+  double v = orc_decode_slot(c, lev, m, scale, slot);
+  free(m);
+  return v;
+}
+
+/* X -> X^g on nl rows a[nl][N] (coefficient domain): X^(g t) = -X^(g t - N) above N */
+void orc_automorphism(const orc_ctx* c, int nl, const u64* a, u64 g, u64* out) {
+  int N = c->N;
+  u64 m2 = 2 * (u64)N;
+  for (int r = 0; r < nl; r++) {
+    u64 q = c->q[r];
+    const u64* ar = a + (size_t)r * N;
+    u64* o = out + (size_t)r * N;
+    for (int t = 0; t < N; t++) {
+      u64 e = (g * (u64)t) % m2;
+      if (e < (u64)N) o[e] = ar[t];
+      else o[e - N] = ar[t] ? q - ar[t] : 0;
+    }
+  }
+}
+
+/* the rotation key for g: [dnum][2][nb][N] coefficient domain, digit j =
+ * (-a_j s + e_j + gadget_j s(X^g), a_j) over Q u P; errors to e_out[dnum][N] */
+void orc_rotkey(const orc_ctx* c, u64 g, u64* key, i64* e_out) {
+  int N = c->N, nb = c->nb;
+  u64* sr = malloc(sizeof(u64) * N);
+  u64* sg = malloc(sizeof(u64) * N);
+  u64* as = malloc(sizeof(u64) * N);
+  i64* e = malloc(sizeof(i64) * N);
+  for (int j = 0; j < c->dnum; j++) {
+    u64 fe[2] = {g, (u64)j};
+    u64 ke = key_of(c->seed, TAG_ROT_E, 2, fe);
+    for (int t = 0; t < N; t++) { e[t] = cdt_sample(c->cdt, word(ke, t)); if (e_out) e_out[(size_t)j * N + t] = e[t]; }
+    for (int r = 0; r < nb; r++) {
+      u64 q = c->q[r];
+      u64* b = key + (((size_t)j * 2 + 0) * nb + r) * N;
+      u64* a = key + (((size_t)j * 2 + 1) * nb + r) * N;
+      u64 fa[3] = {g, (u64)j, (u64)r};
+      u64 ka = key_of(c->seed, TAG_ROT_A, 3, fa);
+      for (int t = 0; t < N; t++) a[t] = uniform_at(ka, t, q);
+      for (int t = 0; t < N; t++) sr[t] = redi(c->s[t], q);
+      polymul(c, r, a, sr, as);
+      /* s(X^g) on this prime */
+      u64 m2 = 2 * (u64)N;
+      for (int t = 0; t < N; t++) {
+        u64 ex = (g * (u64)t) % m2;
+        if (ex < (u64)N) sg[ex] = sr[t];
+        else sg[ex - N] = sr[t] ? q - sr[t] : 0;
+      }
+      u64 gd = 0;
+      if (r >= digit_lo(c, j) && r < digit_hi(c, j)) {
+        gd = 1;
+        for (int k = c->L; k < nb; k++) gd = mulm(gd, c->q[k] % q, q);
+      }
+      for (int t = 0; t < N; t++) b[t] = addm(subm(redi(e[t], q), as[t], q), mulm(gd, sg[t], q), q);
+    }
+  }
+  free(sr); free(sg); free(as); free(e);
+}
+
+/* rotation by r of ct[2][lev+1][N] (coefficient domain) with key_ntt the
+ * rotation key of g = 5^r (NTT domain) */
+static void rotate_with(const orc_ctx* c, int lev, const u64* ct, u64 g, const u64* key_ntt, u64* out) {
+  int N = c->N, nl = lev + 1;
+  u64* t = malloc(sizeof(u64) * (size_t)2 * nl * N);
+  u64* ks = malloc(sizeof(u64) * (size_t)2 * nl * N);
+  orc_automorphism(c, nl, ct, g, t);
+  orc_automorphism(c, nl, ct + (size_t)nl * N, g, t + (size_t)nl * N);
+  ks_with(c, lev, t + (size_t)nl * N, key_ntt, ks);
+  for (int p = 0; p < 2; p++)
+    for (int r = 0; r < nl; r++)
+      for (int x = 0; x < N; x++) {
+        size_t i = ((size_t)p * nl + r) * N + x;
+        out[i] = p == 0 ? addm(t[i], ks[i], c->q[r]) : ks[i];
+      }
+  free(t); free(ks);
+}
+static u64* rotkey_ntt(const orc_ctx* c, u64 g) {
+  size_t kn = (size_t)c->dnum * 2 * c->nb * c->N;
+  u64* k = malloc(sizeof(u64) * kn);
+  orc_rotkey(c, g, k, NULL);
+  for (int j = 0; j < c->dnum; j++)
+    for (int p = 0; p < 2; p++)
+      for (int r = 0; r < c->nb; r++) ntt_fwd(c, r, k + (((size_t)j * 2 + p) * c->nb + r) * c->N);
+  return k;
+}
+int orc_rotate(const orc_ctx* c, int lev, const u64* ct, long r, u64* out) {
+  if (!c->has_keys) return -1;
+  u64 g = orc_galois(c, r);
+  u64* k = rotkey_ntt(c, g);
+  rotate_with(c, lev, ct, g, k, out);
+  free(k);
+  return 0;
+}
+
+/* encryption of the values z[0..n-1] in slots 0..n-1 (R2, R10), keyed by
+ * (operand, chunk, 2^40 + n) */
+int orc_encrypt_slots(const orc_ctx* c, const double* z, int n, u64 seed, u64 operand, u64 chunk, u64* ct) {
+  int N = c->N, L = c->L;
+  i64* m = malloc(sizeof(i64) * N);
+  i64* e = malloc(sizeof(i64) * N);
+  u64* sr = malloc(sizeof(u64) * N);
+  u64* as = malloc(sizeof(u64) * N);
+  if (orc_encode_slots(c, z, n, m) != 0) { free(m); free(e); free(sr); free(as); return -1; }
+  u64 jf = ((u64)1 << 40) + (u64)n;
+  orc_enc_error(c, seed, operand, chunk, jf, e);
+  for (int r = 0; r < L; r++) {
+    u64 q = c->q[r];
+    u64* c0 = ct + (size_t)r * N;
+    u64* c1 = ct + (size_t)(L + r) * N;
+    u64 f[4] = {operand, chunk, jf, (u64)r};
+    u64 ka = key_of(seed, TAG_ENC_A, 4, f);
+    for (int t = 0; t < N; t++) c1[t] = uniform_at(ka, t, q);
+    for (int t = 0; t < N; t++) sr[t] = redi(c->s[t], q);
+    polymul(c, r, c1, sr, as);
+    for (int t = 0; t < N; t++) c0[t] = subm(addm(redi(e[t], q), redi(m[t], q), q), as[t], q);
+  }
+  free(m); free(e); free(sr); free(as);
+  return 0;
+}
+
+/* the stored value list of an encoding (R10: chunks of c consecutive stored
+ * values): dense and naive sparse store all rows x cols, CSR the nonzeros in
+ * row order, ELLPACK rows x width (pads hold 0); slot_of = index of (i, k) */
+static long stored_slot(const orc_struct* S, int i, int k) {
+  switch (S->enc) {
+    case ORC_ENC_DENSE: case ORC_ENC_NAIVE: return (long)i * S->K + k;
+    case ORC_ENC_CSR:
+      for (int p = S->row_ptr[i]; p < S->row_ptr[i + 1]; p++) if (S->col_idx[p] == k) return p;
+      return -1;
+    case ORC_ENC_ELL:
+      for (int s = 0; s < S->ell_w; s++) if (S->ell_col[(size_t)i * S->ell_w + s] == k) return (long)i * S->ell_w + s;
+      return -1;
+  }
+  return -1;
+}
+static long stored_count(const orc_struct* S) {
+  switch (S->enc) {
+    case ORC_ENC_DENSE: case ORC_ENC_NAIVE: return (long)S->M * S->K;
+    case ORC_ENC_CSR: return S->row_ptr[S->M];
+    case ORC_ENC_ELL: return (long)S->M * S->ell_w;
+  }
+  return 0;
+}
+static void stored_values(const orc_struct* S, const double* A, double* v) {
+  long n = stored_count(S);
+  for (long x = 0; x < n; x++) v[x] = 0.0;
+  for (int i = 0; i < S->M; i++)
+    for (int k = 0; k < S->K; k++) {
+      long sl = stored_slot(S, i, k);
+      if (sl >= 0) v[sl] = A[(size_t)i * S->K + k];
+    }
+}
+
+/* Algorithm 1 at chunk size cs (Sec. 3.2, 3.3) for the outputs listed: per
+ * output (i, j), for every k that row i visits, the A and B values are
+ * rotated into slot 0, multiplied, relinearised and rescaled; then (per
+ * product for PER_PRODUCT, once on the sum for LAZY) multiplied by the
+ * slot-zero mask, rescaled, rotated to the output's slot and added into its
+ * output chunk.  out receives the result chunks touched, [nchunks][2][L-3][N]
+ * coefficient domain (chunks of the outputs not listed stay trivial zeros);
+ * vals (nullable) the listed outputs decrypted at Delta^3 / (q_{L-1} q_{L-2}). */
+int orc_matmul_chunked(const orc_ctx* c, const double* A, int M, int K, const double* B, int Nc, int enc, int sched,
+                       int cs, u64 seedA, u64 opA, u64 seedB, u64 opB, const int* orow, const int* ocol, int nout,
+                       u64* out, double* vals) {
+  int N = c->N, L = c->L, top = L - 1, lo = L - 3;
+  if (!c->has_keys || L < 4 || cs < 1 || cs > 64 || cs > N / 2) return -1;
+  orc_struct S; struct_build(&S, A, M, K, enc);
+  orc_struct SB; struct_build(&SB, B, K, Nc, ORC_ENC_DENSE);
+  long na = stored_count(&S), nbv = (long)K * Nc;
+  double* av = malloc(sizeof(double) * (na + 1));
+  double* bv = malloc(sizeof(double) * (nbv + 1));
+  stored_values(&S, A, av);
+  stored_values(&SB, B, bv);
+  long nca = (na + cs - 1) / cs, ncb = (nbv + cs - 1) / cs, ncr = ((long)M * Nc + cs - 1) / cs;
+  size_t ct_top = (size_t)2 * L * N, ct_lo = (size_t)2 * (lo + 1) * N;
+  u64** ea = calloc(nca + 1, sizeof(u64*));
+  u64** eb = calloc(ncb + 1, sizeof(u64*));
+  memset(out, 0, sizeof(u64) * ncr * ct_lo);
+  /* rotation keys for offsets -(cs-1) .. cs-1 */
+  u64* keys[129] = {0};
+  for (long r = -(cs - 1); r <= cs - 1; r++) if (r) keys[r + 64] = rotkey_ntt(c, orc_galois(c, r));
+  /* the slot-zero mask */
+  i64* mk = malloc(sizeof(i64) * N);
+  orc_encode(c, 1.0, mk);
+  u64* mask = malloc(sizeof(u64) * (size_t)L * N);
+  for (int r = 0; r < L; r++) for (int t = 0; t < N; t++) mask[(size_t)r * N + t] = redi(mk[t], c->q[r]);
+  u64* ra = malloc(sizeof(u64) * ct_top);
+  u64* rb = malloc(sizeof(u64) * ct_top);
+  u64* d = malloc(sizeof(u64) * 3 * L * N);
+  u64* dsum = malloc(sizeof(u64) * 3 * L * N);
+  u64* ks = malloc(sizeof(u64) * ct_top);
+  u64* x1 = malloc(sizeof(u64) * ct_top);
+  u64* x2 = malloc(sizeof(u64) * ct_top);
+  u64* x3 = malloc(sizeof(u64) * ct_top);
+  u64* tmp = malloc(sizeof(u64) * N);
+  int* ks_k = malloc(sizeof(int) * (K + 1));
+  int rc = 0;
+  /* mask, rescale, rotate to the output slot and add: x holds a relinearised
+   * product at level top - 1 */
+  #define FINISH(x, rn, roff) do {                                                        \
+    int l1 = top - 1;                                                                        \
+    for (int p = 0; p < 2; p++) for (int r = 0; r <= l1; r++) {                              \
+      polymul(c, r, (x) + ((size_t)p * (l1 + 1) + r) * N, mask + (size_t)r * N, tmp);       \
+      memcpy((x) + ((size_t)p * (l1 + 1) + r) * N, tmp, sizeof(u64) * N);                   \
+    }                                                                                        \
+    orc_rescale(c, l1, (x), x3);                                                             \
+    if (roff) rotate_with(c, lo, x3, orc_galois(c, -(long)(roff)), keys[64 - (roff)], x2);   \
+    else memcpy(x2, x3, sizeof(u64) * ct_lo);                                                \
+    u64* o = out + (size_t)(rn) * ct_lo;                                                     \
+    for (int p = 0; p < 2; p++) for (int r = 0; r <= lo; r++) for (int t = 0; t < N; t++) {  \
+      size_t ix = ((size_t)p * (lo + 1) + r) * N + t;                                        \
+      o[ix] = addm(o[ix], x2[ix], c->q[r]);                                                  \
+    }                                                                                        \
+  } while (0)
+  for (int n = 0; n < nout && !rc; n++) {
+    int i = orow[n], j = ocol[n];
+    long rs = (long)i * Nc + j, rn = rs / cs;
+    int roff = (int)(rs % cs);
+    int nk = row_ks(&S, i, ks_k);
+    if (nk == 0) continue;                                 /* R6: nothing added */
+    memset(dsum, 0, sizeof(u64) * 3 * L * N);
+    for (int x = 0; x < nk; x++) {
+      int k = ks_k[x];
+      long sa = stored_slot(&S, i, k), sb = (long)k * Nc + j;
+      long an = sa / cs, bn = sb / cs;
+      int aoff = (int)(sa % cs), boff = (int)(sb % cs);
+      if (!ea[an]) {
+        ea[an] = malloc(sizeof(u64) * ct_top);
+        int cnt = (int)((an + 1) * cs <= na ? cs : na - an * cs);
+        orc_encrypt_slots(c, av + an * cs, cnt, seedA, opA, (u64)an, ea[an]);
+      }
+      if (!eb[bn]) {
+        eb[bn] = malloc(sizeof(u64) * ct_top);
+        int cnt = (int)((bn + 1) * cs <= nbv ? cs : nbv - bn * cs);
+        orc_encrypt_slots(c, bv + bn * cs, cnt, seedB, opB, (u64)bn, eb[bn]);
+      }
+      if (aoff) rotate_with(c, top, ea[an], orc_galois(c, aoff), keys[64 + aoff], ra); else memcpy(ra, ea[an], sizeof(u64) * ct_top);
+      if (boff) rotate_with(c, top, eb[bn], orc_galois(c, boff), keys[64 + boff], rb); else memcpy(rb, eb[bn], sizeof(u64) * ct_top);
+      orc_tensor(c, top, ra, rb, d);
+      if (sched == ORC_SCHED_LAZY) {
+        for (size_t y = 0; y < (size_t)3 * L * N; y++) dsum[y] = addm(dsum[y], d[y], c->q[(y / N) % L]);
+        continue;
+      }
+      /* PER_PRODUCT (Algorithm 1's order) */
+      orc_keyswitch(c, top, d + (size_t)2 * L * N, ks);
+      for (int p = 0; p < 2; p++) for (int r = 0; r < L; r++) for (int t = 0; t < N; t++) {
+        size_t ix = ((size_t)p * L + r) * N + t;
+        x1[ix] = addm(d[ix], ks[ix], c->q[r]);
+      }
+      orc_rescale(c, top, x1, x2);
+      memcpy(x1, x2, sizeof(u64) * 2 * (size_t)top * N);
+      FINISH(x1, rn, roff);
+    }
+    if (sched == ORC_SCHED_LAZY) {
+      orc_keyswitch(c, top, dsum + (size_t)2 * L * N, ks);
+      for (int p = 0; p < 2; p++) for (int r = 0; r < L; r++) for (int t = 0; t < N; t++) {
+        size_t ix = ((size_t)p * L + r) * N + t;
+        x1[ix] = addm(dsum[ix], ks[ix], c->q[r]);
+      }
+      orc_rescale(c, top, x1, x2);
+      memcpy(x1, x2, sizeof(u64) * 2 * (size_t)top * N);
+      FINISH(x1, rn, roff);
+    }
+  }
+  #undef FINISH
+  if (vals) {
+    double scale = ldexp(1.0, 3 * (int)c->log2_scale) / (double)c->q[top] / (double)c->q[top - 1];
+    for (int n = 0; n < nout; n++) {
+      long rs = (long)orow[n] * Nc + ocol[n];
+      vals[n] = orc_decrypt_slot(c, lo, out + (size_t)(rs / cs) * ct_lo, scale, (int)(rs % cs));
+    }
+  }
+  for (long x = 0; x < nca; x++) free(ea[x]);
+  for (long x = 0; x < ncb; x++) free(eb[x]);
+  for (int x = 0; x < 129; x++) free(keys[x]);
+  free(ea); free(eb); free(av); free(bv); free(mk); free(mask); free(ra); free(rb); free(d); free(dsum); free(ks);
+  free(x1); free(x2); free(x3); free(tmp); free(ks_k);
+  struct_free(&S); struct_free(&SB);
+  return rc;
 }

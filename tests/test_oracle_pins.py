@@ -604,3 +604,87 @@ def test_both_sparse_decrypts_to_fp64_product():
     for sched in ("lazy", "per_product"):
         _, vals, _ = o.matmul(A, B, "naive", sched, 1, 2, encB="naive", threads=3)
         assert np.max(np.abs(vals - (A @ B).ravel())) < 1e-6
+
+
+# ------------------------- chunks of several values, rotations (R10, Sec. 3.2)
+def test_slot_encoding_closed_form():
+    """Decoding slot j (sum_t m_t cos(pi (5^j t mod 2N) / N) / Delta, computed
+    here in numpy) returns z_j: the cosines of distinct slots are orthogonal.
+    One value in slot 0 is R1's encoding, bit for bit."""
+    o = Oracle(**SMALL)
+    n = o.n
+    z = np.array([0.5, -0.75, 0.125, 0.3, -0.9, 0.01, 0.0, 0.66])
+    m = o.encode_slots(z).astype(np.float64)
+    t = np.arange(n)
+    for j in range(len(z)):
+        e = (pow(5, j, 2 * n) * t) % (2 * n)
+        zj = float(np.sum(m * np.cos(np.pi * e / n))) / 2.0 ** o.log2_scale
+        assert abs(zj - z[j]) < n * 1e-12, j
+    assert np.array_equal(o.encode_slots(z[:1]), o.encode(z[0]))
+
+
+@pytest.mark.parametrize("r", [1, 3, -1, -2])
+def test_automorphism_is_evaluation_at_powers(r):
+    """(X -> X^g)(a) at psi^k equals a at psi^(g k) for every odd k."""
+    o = Oracle(**TINY_SINGLE)
+    g = o.galois(r)
+    assert g == pow(5, r % (o.n // 2), 2 * o.n)
+    rng = np.random.default_rng(4)
+    a = np.stack([rng.integers(0, q, size=o.n, dtype=np.uint64) for q in o.q])
+    b = o.automorphism(a, g)
+    for ri, q in enumerate(o.q):
+        psi = int(o.psi[ri])
+        for k in range(1, 2 * o.n, 2):
+            assert brute.evaluate([int(x) for x in b[ri]], pow(psi, k, q), q) == \
+                brute.evaluate([int(x) for x in a[ri]], pow(psi, g * k % (2 * o.n), q), q)
+
+
+def test_rotation_key_identity():
+    """b_j + a_j s = e_j + g_j s(X^g) on every prime (g_j = P on digit j)."""
+    o = make(TINY_HYBRID)
+    s = [int(x) for x in o.secret()]
+    P = brute.prod(o.p)
+    basis = o.q + o.p
+    g = o.galois(3)
+    key, e = o.rotkey(g)
+    for j in range(o.dnum):
+        ej = [int(x) for x in e[j]]
+        assert max(abs(x) for x in ej) <= 19
+        for r, q in enumerate(basis):
+            sr = [x % q for x in s]
+            sg = [0] * o.n
+            for t in range(o.n):
+                ex = g * t % (2 * o.n)
+                if ex < o.n:
+                    sg[ex] = sr[t]
+                else:
+                    sg[ex - o.n] = (-sr[t]) % q
+            gd = P % q if (r < o.L and j * o.alpha <= r < (j + 1) * o.alpha) else 0
+            lhs = brute.poly_add([int(x) for x in key[j, 0, r]], brute.negacyclic([int(x) for x in key[j, 1, r]], sr, q), q)
+            assert lhs == [(x + gd * y) % q for x, y in zip(ej, sg)], (j, r)
+
+
+@pytest.mark.parametrize("r", [1, 2, -1, -3])
+def test_rotation_moves_slots(r):
+    o = make(SMALL_HYBRID, seed=9)
+    z = np.array([0.5, -0.25, 0.75, 0.1, -0.6])
+    ct = o.encrypt_slots(z, 3, 0, 0)
+    rot = o.rotate(o.L - 1, ct, r)
+    h = o.n // 2
+    for j in range(8):
+        src = (j + r) % h
+        want = z[src] if src < len(z) else 0.0
+        assert abs(o.decrypt_slot(o.L - 1, rot, 2.0 ** o.log2_scale, j) - want) < 1e-6, (r, j)
+
+
+@pytest.mark.parametrize("chunk", [1, 2, 4])
+@pytest.mark.parametrize("sched", ["lazy", "per_product"])
+def test_chunked_algorithm1_decrypts_to_fp64_product(chunk, sched):
+    """Algorithm 1 with rotations into slot 0, the slot-zero mask and the
+    rotation to the output slot: the decrypted chunks hold A B."""
+    o = make(SMALL_HYBRID, seed=10)
+    A, B = W.operands(3, 5, 3, 0.4, 88)
+    A[1, :] = 0.0
+    for enc in ("csr", "ell", "dense"):
+        _, vals = o.matmul_chunked(A, B, enc, sched, chunk, 4, 5)
+        assert np.max(np.abs(vals - (A @ B).ravel())) < 1e-6, (enc, chunk, sched)
