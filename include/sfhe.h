@@ -102,6 +102,7 @@ typedef struct {
   int64_t nnz;              /* nonzero elements (the values that are encrypted) */
   int32_t ell_width;        /* ELL only, else 0 */
   uint64_t device_bytes;    /* ciphertext bytes held on the device (Sec. 4.4 memory) */
+  int32_t slots;            /* values per ciphertext (the chunk size c of Sec. 3.2) */
 } sfhe_mat_info;
 
 typedef struct {
@@ -170,6 +171,53 @@ int sfhe_decrypt_matrix(sfhe_ctx* ctx, const sfhe_mat* m, double* out, int64_t l
  * (SFHE_E_SHAPE); an ELL padding slot is not addressable. */
 int sfhe_export_ct(sfhe_ctx* ctx, const sfhe_mat* m, int32_t i, int32_t j, uint64_t* out, size_t cap,
                    void* stream);
+
+/* ---- Several values per ciphertext (Sec. 3.2, Algorithm 1) -------------
+ * A matrix is a list of ciphertexts ("chunks") holding up to c = slots
+ * values each.  The stored values of an encoding (all rows x cols entries
+ * row-major for DENSE and NAIVE_SPARSE, the nonzeros in row order for CSR,
+ * rows x width for ELLPACK with 0.0 in the padding) are cut into chunks of c
+ * consecutive values: stored value v sits in slot v mod c of ciphertext
+ * v / c.  Slot j of a ciphertext is its plaintext's value at zeta^(5^j),
+ * zeta = exp(i pi / N): values z_0 .. z_{n-1} encode as
+ * m_t = nearbyint(sum_j z_j 2 Delta / N cos(pi (5^j t mod 2N) / N)), summed
+ * in slot order (n = 1 is the one-value encoding).  Secret-key encryption as
+ * sfhe_encrypt_matrix, the randomness of chunk x keyed by (operand_id, x,
+ * 2^40 + n).  sfhe_matmul, sfhe_matmul_plain and sfhe_export_ct reject
+ * matrices with slots > 1 (SFHE_E_UNSUPPORTED); sfhe_decrypt_matrix decodes
+ * every slot; sfhe_export_stored reads any ciphertext. */
+
+/* Encrypt the stored values of vals (rows x cols, leading dimension ld) in
+ * chunks of `slots` values, 1 <= slots <= min(64, N/2).  Every value of a
+ * chunk of n values must satisfy |value| 2^(log2_scale + 1 - log_n) < 4e18 / n
+ * (else SFHE_E_INVALID_ARG).  Needs keys. */
+int sfhe_encrypt_matrix_slots(sfhe_ctx* ctx, const double* vals, int32_t rows, int32_t cols, int64_t ld,
+                              sfhe_encoding enc, int32_t slots, uint64_t seed, uint32_t operand_id,
+                              void* stream, sfhe_mat** out);
+
+/* C = A * B by Algorithm 1 with chunks (Sec. 3.3.1): for output (i, j) and
+ * every k that A's row i visits (its zeros skipped per its encoding), the
+ * chunks holding A_ik and B_kj are rotated so that the two values sit in
+ * slot 0, multiplied, relinearised and rescaled.  LAZY sums these products
+ * of an output before the relinearisation; PER_PRODUCT does not.  Each
+ * product (PER_PRODUCT) or sum (LAZY) is then multiplied by the slot-zero
+ * mask (the plaintext of 1.0 in slot 0 at scale 2^log2_scale), rescaled,
+ * rotated from slot 0 to slot (i Nc + j) mod c and added into result chunk
+ * (i Nc + j) / c.  A and B hold the same number of values per ciphertext, B
+ * is DENSE, both are at the top level, and the context has at least four
+ * data primes.  C: DENSE, rows x cols of the product, c values per
+ * ciphertext, level L - 3, scale scale_A scale_B 2^log2_scale / (q_{L-1}
+ * q_{L-2}); chunks no product reaches stay trivial zeros.  Rotation keys
+ * (for offsets -(c-1) .. c-1) are generated on first use and kept by the
+ * context.  sfhe_last_stats: products, relinearisations plus rotations (as
+ * keyswitches), result ciphertexts and the device time of the whole call. */
+int sfhe_matmul_slots(sfhe_ctx* ctx, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched,
+                      void* stream, sfhe_mat** C);
+
+/* Copy stored ciphertext n (0 <= n < n_ciphertexts) of any encrypted matrix,
+ * in the coefficient domain, to host memory: out[2][level+1][N]. */
+int sfhe_export_stored(sfhe_ctx* ctx, const sfhe_mat* m, int64_t n, uint64_t* out, size_t cap,
+                       void* stream);
 
 /* ---- Plaintext weights times encrypted values -------------------------
  * Sec. 3.3.2: a server that holds a layer's weights in plaintext multiplies
@@ -312,6 +360,16 @@ int sfhe_keyswitch(sfhe_ctx* ctx, int32_t level, const uint64_t* d2, uint64_t* o
  * rounding (centered lift): in [batch][2][level+1][N] -> out [batch][2][level][N]. */
 int sfhe_rescale(sfhe_ctx* ctx, int32_t level, const uint64_t* in, uint64_t* out, int32_t batch,
                  void* stream);
+
+/* Rotation by r slots (slot j receives slot j + r, indices mod N/2) of
+ * ciphertexts at `level`, NTT domain: in [batch][2][level+1][N] -> out, same
+ * shape (Sec. 3.3.1: the automorphism X -> X^g, g = 5^r mod 2N, of both
+ * polys, then a key switch of c1(X^g) from s(X^g) back to s with the
+ * rotation key of g: digit j = (-a s + e + [P]_{q} s(X^g) on digit j's
+ * primes, a), built like the relinearisation key; randomness keyed by
+ * (g, j[, prime])).  in and out must not overlap.  Needs keys. */
+int sfhe_rotate(sfhe_ctx* ctx, int32_t level, const uint64_t* in, uint64_t* out, int32_t batch, int32_t r,
+                void* stream);
 
 #ifdef __cplusplus
 }

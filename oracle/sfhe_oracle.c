@@ -29,7 +29,9 @@
  *   R3  randomness from SplitMix64 used as a counter-based generator, one
  *       stream per (seed, tag, fields); see key_of() and word().
  *   R4  hybrid key switching with contiguous digits of alpha data primes,
- *       uncentered fast base conversion in ModUp and ModDown.
+ *       uncentered fast base conversion in ModUp, centered in ModDown (the
+ *       special part's residues taken in (-p_k/2, p_k/2)), so that the
+ *       division by P carries no bias.
  *   R5  rescale by the last prime with the centered lift (exact rounding).
  *   R6  outputs with no product are trivial zero ciphertexts.
  *   R7  NTT-domain index k holds a(psi^(2*brv(k)+1)), psi the smallest
@@ -462,9 +464,13 @@ void orc_modup(const orc_ctx* c, int lev, int j, const u64* d2, u64* x) {
 }
 
 /* ModDown: divide by P = prod p_k.  out_i = (acc_i - F_i) * P^-1 mod q_i with
- * F = sum_k [acc_{p_k} (P/p_k)^-1]_{p_k} (P/p_k), the uncentered fast base
- * conversion of the special part.  in: acc[lev+1+alpha][N], out: [lev+1][N],
- * both coefficient domain. */
+ * F = sum_k y_k (P/p_k), y_k = [acc_{p_k} (P/p_k)^-1]_{p_k} taken in
+ * (-p_k/2, p_k/2): the centered fast base conversion of the special part, so
+ * F = (acc mod P) + u P with u symmetric about zero (R4).  With y_k in
+ * [0, p_k) instead, u would lie in [0, alpha) with mean near (alpha - 1)/2,
+ * and the bias u s that the second component carries, a random walk over the
+ * coefficients, would add a low-frequency error of order N^1.5 to every key
+ * switch.  in: acc[lev+1+alpha][N], out: [lev+1][N], both coefficient domain. */
 void orc_moddown(const orc_ctx* c, int lev, const u64* acc, u64* out) {
   int N = c->N, nl = lev + 1, al = c->alpha;
   u64* yk = malloc(sizeof(u64) * (size_t)al * N);
@@ -484,9 +490,11 @@ void orc_moddown(const orc_ctx* c, int lev, const u64* acc, u64* out) {
     for (int t = 0; t < N; t++) {
       u64 z = 0;
       for (int k = 0; k < al; k++) {
-        u64 Pq = 1;                                       /* [P/p_k]_{q_i} */
+        u64 pk = c->q[SP(c, k)], Pq = 1;                  /* [P/p_k]_{q_i} */
         for (int k2 = 0; k2 < al; k2++) if (k2 != k) Pq = mulm(Pq, c->q[SP(c, k2)] % qi, qi);
-        z = addm(z, mulm(yk[(size_t)k * N + t] % qi, Pq, qi), qi);
+        u64 y = yk[(size_t)k * N + t];
+        i64 yc = y > (pk - 1) / 2 ? -(i64)(pk - y) : (i64)y;   /* centered representative */
+        z = addm(z, mulm(redi(yc, qi), Pq, qi), qi);
       }
       o[t] = mulm(subm(ai[t], z, qi), Pinv, qi);
     }

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -244,6 +245,7 @@ static int build_tables(sfhe_ctx* c) {
       for (int k = 0; k < al; ++k) P = mulmod(P, c->primes[L + k] % qi, qi);
       d.Pinv[i] = invmod(P, qi);
       d.Pinv_s[i] = shoup(d.Pinv[i], qi);
+      d.Pq[i] = P;
     }
     RescaleConst& rc = rs[lev];
     for (int i = 0; i < lev; ++i) {
@@ -617,6 +619,7 @@ int sfhe_encrypt_matrix(sfhe_ctx* c, const double* vals, int32_t rows, int32_t c
   }
   if (!rc && hipStreamSynchronize(s) != hipSuccess) { rc = SFHE_E_DEVICE; set_error("stream synchronize failed"); }
   if (rc) { delete m; return rc; }
+  m->n_vals = m->n_ct;
   *out = m;
   return SFHE_OK;
   GUARD_END
@@ -633,13 +636,18 @@ int sfhe_matrix_info(const sfhe_mat* m, sfhe_mat_info* out) {
   out->nnz = m->nnz;
   out->ell_width = m->ell_w;
   out->device_bytes = m->plain ? 0 : (uint64_t)m->n_ct * 2 * (m->level + 1) * m->ctx->N * sizeof(u64);
+  out->slots = m->slots;
   return SFHE_OK;
 }
 
 void sfhe_mat_destroy(sfhe_mat* m) { delete m; }
 
-int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched, void* stream, sfhe_mat** C) {
-  GUARD_BEGIN
+}  // extern "C"
+
+// The one-value-per-ciphertext product (chunk size 1).  With timed, the
+// call's device time is bracketed by the context's event pair.
+static int matmul_c1(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched, hipStream_t s,
+                     sfhe_mat** C, bool timed) {
   if (!C) { set_error("C is NULL"); return SFHE_E_INVALID_ARG; }
   *C = nullptr;
   if (!c || !A || !B) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
@@ -653,9 +661,8 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
   if (A->level != c->L - 1) { set_error("operands must be at the top level"); return SFHE_E_LEVEL; }
   if (A->level < 1) { set_error("no prime left to rescale"); return SFHE_E_LEVEL; }
   if (A->scale != B->scale) { set_error("operand scales differ"); return SFHE_E_SCALE; }
-  hipStream_t s = (hipStream_t)stream;
   const int N = c->N, lev = A->level, nl = lev + 1, M = A->rows, Nc = B->cols;
-  SFHE_HIP(hipEventRecord(c->ev0, s));
+  if (timed) SFHE_HIP(hipEventRecord(c->ev0, s));
   sfhe_mat* out = new sfhe_mat();
   out->ctx = c;
   out->rows = M;
@@ -879,7 +886,7 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
     if (!upload(c, d_e, empty, s)) { rc = SFHE_E_NOMEM; set_error("device allocation failed"); }
     if (!rc) rc = launch_zero_outputs(c, out->data.ptr, out->n_ct, lev, d_e.ptr, (int64_t)empty.size(), s);
   }
-  if (!rc) {
+  if (!rc && timed) {
     hipError_t e = hipEventRecord(c->ev1, s);
     if (e != hipSuccess) { rc = SFHE_E_DEVICE; set_error(hipGetErrorString(e)); }
   }
@@ -888,6 +895,7 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
     delete out;
     return rc;
   }
+  out->n_vals = out->n_ct;
   c->stats = sfhe_stats{};
   c->stats.products = products;
   c->stats.keyswitches = keyswitches;
@@ -895,9 +903,21 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
   c->stats.tensor_launches = tensor_launches;
   c->stats.tensor_fp_launches = tensor_fp_launches;
   c->stats.tensor_fp_primes = tensor_fp_prime_count(c);
-  c->stats_pending = true;
+  c->stats_pending = timed;
   *C = out;
   return SFHE_OK;
+}
+
+extern "C" {
+
+int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched, void* stream, sfhe_mat** C) {
+  GUARD_BEGIN
+  if (A && B && (A->slots > 1 || B->slots > 1)) {
+    if (C) *C = nullptr;
+    set_error("several values per ciphertext: use sfhe_matmul_slots");
+    return SFHE_E_UNSUPPORTED;
+  }
+  return matmul_c1(c, A, B, sched, (hipStream_t)stream, C, true);
   GUARD_END
 }
 
@@ -949,6 +969,7 @@ static int plain_check(const sfhe_ctx* c, const sfhe_mat* W, const sfhe_mat* B) 
   if (!W->plain) { set_error("the left operand must be plaintext weights (sfhe_encode_matrix)"); return SFHE_E_INVALID_ARG; }
   if (B->plain) { set_error("the right operand must be encrypted"); return SFHE_E_INVALID_ARG; }
   if (B->enc != SFHE_ENC_DENSE) { set_error("the right operand must be DENSE"); return SFHE_E_UNSUPPORTED; }
+  if (B->slots > 1) { set_error("the encrypted operand must hold one value per ciphertext"); return SFHE_E_UNSUPPORTED; }
   if (W->cols != B->rows) { set_error("W.cols != B.rows"); return SFHE_E_SHAPE; }
   if (B->level != c->L - 1) { set_error("the encrypted operand must be at the top level"); return SFHE_E_LEVEL; }
   if (B->level < 1) { set_error("no prime left to rescale"); return SFHE_E_LEVEL; }
@@ -1492,16 +1513,21 @@ int sfhe_decrypt_matrix(sfhe_ctx* c, const sfhe_mat* m, double* out, int64_t ld,
   if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
   if (ld < m->cols) { set_error("ld < cols"); return SFHE_E_SHAPE; }
   hipStream_t s = (hipStream_t)stream;
-  std::vector<double> vals(m->n_ct > 0 ? m->n_ct : 1, 0.0);
-  if (m->n_ct > 0) {
+  const int64_t nv = m->slots > 1 ? m->n_vals : m->n_ct;   // stored values
+  std::vector<double> vals(nv > 0 ? nv : 1, 0.0);
+  if (m->slots > 1) {
+    int rc = slot_table(c);
+    if (rc) return rc;
+  }
+  if (nv > 0) {
     DevBuf<double> d_v;
     DevBuf<int> d_flag;
-    if (!d_v.alloc(&c->alloc, m->n_ct) || !d_flag.alloc(&c->alloc, 1)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
+    if (!d_v.alloc(&c->alloc, nv) || !d_flag.alloc(&c->alloc, 1)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
     SFHE_HIP(hipMemsetAsync(d_flag.ptr, 0, sizeof(int), s));
-    int rc = decrypt_values(c, m->data.ptr, m->n_ct, m->level, m->scale, d_v.ptr, d_flag.ptr, s);
+    int rc = decrypt_values(c, m->data.ptr, m->n_ct, m->level, m->scale, d_v.ptr, d_flag.ptr, s, m->slots, nv);
     if (rc) return rc;
     int flag = 0;
-    SFHE_HIP(hipMemcpyAsync(vals.data(), d_v.ptr, m->n_ct * sizeof(double), hipMemcpyDeviceToHost, s));
+    SFHE_HIP(hipMemcpyAsync(vals.data(), d_v.ptr, nv * sizeof(double), hipMemcpyDeviceToHost, s));
     SFHE_HIP(hipMemcpyAsync(&flag, d_flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
     SFHE_HIP(hipStreamSynchronize(s));
     if (flag) { set_error("a decrypted coefficient is outside the decodable range"); return SFHE_E_DECRYPT; }
@@ -1534,6 +1560,7 @@ int sfhe_export_ct(sfhe_ctx* c, const sfhe_mat* m, int32_t i, int32_t j, uint64_
   GUARD_BEGIN
   if (!c || !m || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
   if (m->plain) { set_error("plaintext weights hold no ciphertexts"); return SFHE_E_UNSUPPORTED; }
+  if (m->slots > 1) { set_error("several values per ciphertext: use sfhe_export_stored"); return SFHE_E_UNSUPPORTED; }
   if (i < 0 || i >= m->rows || j < 0 || j >= m->cols) { set_error("index out of range"); return SFHE_E_SHAPE; }
   const int N = c->N, nl = m->level + 1;
   const size_t words = (size_t)2 * nl * N;
@@ -1596,6 +1623,354 @@ int sfhe_rescale(sfhe_ctx* c, int32_t level, const uint64_t* in, uint64_t* out, 
   if (level < 1 || level >= c->L || batch < 0) { set_error("bad level or batch"); return SFHE_E_LEVEL; }
   const int64_t nl = level + 1, N = c->N;
   return rescale_batch(c, level, in, 2 * nl * N, OutLayout{out, 2 * level * N, false, 0, 0}, batch, (hipStream_t)stream);
+  GUARD_END
+}
+
+
+// ---------------------------------------------------------------- several values per ciphertext
+int sfhe_encrypt_matrix_slots(sfhe_ctx* c, const double* vals, int32_t rows, int32_t cols, int64_t ld,
+                              sfhe_encoding enc, int32_t slots, uint64_t seed, uint32_t operand_id, void* stream,
+                              sfhe_mat** out) {
+  GUARD_BEGIN
+  if (!out) { set_error("out is NULL"); return SFHE_E_INVALID_ARG; }
+  *out = nullptr;
+  if (!c || !vals) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
+  if (rows < 1 || cols < 1 || ld < cols) { set_error("bad shape or leading dimension"); return SFHE_E_SHAPE; }
+  if ((int)enc < 0 || (int)enc > 3) { set_error("bad encoding"); return SFHE_E_INVALID_ARG; }
+  if (slots < 1 || slots > 64 || slots > c->N / 2) { set_error("slots must be in [1, min(64, N/2)]"); return SFHE_E_INVALID_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  sfhe_mat* m = new sfhe_mat();
+  m->ctx = c;
+  m->rows = rows;
+  m->cols = cols;
+  m->level = c->L - 1;
+  m->scale = ldexp(1.0, (int)c->log2_scale);
+  m->enc = enc;
+  m->slots = slots;
+  std::vector<std::pair<int64_t, double>> stored;
+  build_structure(m, vals, ld, [&](int i, int j, int64_t sl) { stored.push_back({sl, vals[(int64_t)i * ld + j]}); });
+  const int64_t nv = m->n_ct;   // stored values (ELL padding included, as zeros)
+  std::vector<double> v((size_t)std::max<int64_t>(nv, 1), 0.0);
+  for (auto& st : stored) v[st.first] = st.second;
+  m->n_vals = nv;
+  m->n_ct = (nv + slots - 1) / slots;
+  // every scaled value of a chunk of cnt values must stay below 4e18 / cnt
+  const double pow2 = ldexp(1.0, (int)c->log2_scale + 1 - c->logN);
+  for (int64_t x = 0; x < nv; ++x) {
+    const int64_t cnt = std::min<int64_t>(slots, nv - x / slots * slots);
+    if (!(fabs(v[x] * pow2) < 4.0e18 / (double)cnt)) {
+      delete m;
+      set_error("value not finite or too large to encode");
+      return SFHE_E_INVALID_ARG;
+    }
+  }
+  const int N = c->N, L = c->L;
+  int rc = SFHE_OK;
+  const size_t words = (size_t)m->n_ct * 2 * L * N;
+  if (!m->data.alloc(&c->alloc, words)) { delete m; set_error("device allocation failed for the ciphertexts"); return SFHE_E_NOMEM; }
+  DevBuf<double> d_v;
+  DevBuf<u64> tmp;
+  const int64_t chunk = std::min<int64_t>(std::max<int64_t>(m->n_ct, 1), 1024);
+  if (!upload(c, d_v, v, s) || !tmp.alloc(&c->alloc, (size_t)chunk * 2 * L * N)) {
+    rc = SFHE_E_NOMEM;
+    set_error("device allocation failed");
+  }
+  for (int64_t x0 = 0; x0 < m->n_ct && !rc; x0 += chunk) {
+    const int64_t n = std::min(chunk, m->n_ct - x0);
+    rc = encrypt_slots(c, tmp.ptr, n, x0, d_v.ptr, nv, slots, seed, operand_id, s);
+    if (!rc) rc = launch_to_chunked(c, tmp.ptr, (int64_t)2 * L * N, L, n, m->data.ptr, m->n_ct, nullptr, x0, s);
+  }
+  if (!rc && hipStreamSynchronize(s) != hipSuccess) { rc = SFHE_E_DEVICE; set_error("stream synchronize failed"); }
+  if (rc) { delete m; return rc; }
+  *out = m;
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_rotate(sfhe_ctx* c, int32_t level, const uint64_t* in, uint64_t* out, int32_t batch, int32_t r,
+                void* stream) {
+  GUARD_BEGIN
+  if (!c || !in || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
+  if (level < 0 || level >= c->L || batch < 0) { set_error("bad level or batch"); return SFHE_E_LEVEL; }
+  if (in == out) { set_error("in and out must not overlap"); return SFHE_E_INVALID_ARG; }
+  int rc = prepare_rotations(c, {(int64_t)r});
+  if (rc) return rc;
+  const int64_t w = (int64_t)2 * (level + 1) * c->N;
+  return rotate_batch(c, level, in, w, r, out, w, batch, (hipStream_t)stream);
+  GUARD_END
+}
+
+int sfhe_export_stored(sfhe_ctx* c, const sfhe_mat* m, int64_t n, uint64_t* out, size_t cap, void* stream) {
+  GUARD_BEGIN
+  if (!c || !m || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (m->plain) { set_error("plaintext weights hold no ciphertexts"); return SFHE_E_UNSUPPORTED; }
+  if (n < 0 || n >= m->n_ct) { set_error("ciphertext index out of range"); return SFHE_E_SHAPE; }
+  const int N = c->N, nl = m->level + 1;
+  const size_t words = (size_t)2 * nl * N;
+  if (cap < words) { set_error("capacity below 2*(level+1)*N"); return SFHE_E_INVALID_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  DevBuf<u64> tmp;
+  if (!tmp.alloc(&c->alloc, words)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
+  int rc = launch_from_chunked(c, m->data.ptr, m->n_ct, nl, 1, nullptr, n, tmp.ptr, (int64_t)words, s);
+  if (rc) return rc;
+  int pos[2 * kMaxBasis], pr[2 * kMaxBasis];
+  for (int r = 0; r < 2 * nl; ++r) { pos[r] = r; pr[r] = r % nl; }
+  rc = launch_ntt(c, tmp.ptr, 1, 0, 2 * nl, pos, pr, true, s);
+  if (rc) return rc;
+  SFHE_HIP(hipMemcpyAsync(out, tmp.ptr, words * sizeof(u64), hipMemcpyDeviceToHost, s));
+  SFHE_HIP(hipStreamSynchronize(s));
+  return SFHE_OK;
+  GUARD_END
+}
+
+}  // extern "C"
+
+// Stored values `list` of the chunked matrix src, each rotated from its slot
+// v mod slots into slot 0, become the one-value ciphertexts dst[v] (top level).
+static int unpack_values(sfhe_ctx* c, const sfhe_mat* src, const std::vector<int64_t>& list, sfhe_mat* dst,
+                         hipStream_t s, int64_t& rotations) {
+  const int N = c->N, lev = src->level, nl = lev + 1, cs = src->slots;
+  const int64_t w = (int64_t)2 * nl * N, slice = 256;
+  std::vector<std::vector<int64_t>> by_off(cs);
+  for (int64_t v : list) by_off[v % cs].push_back(v);
+  DevBuf<u64> a, b;
+  DevBuf<int64_t> d_src, d_dst;
+  const int64_t cap = std::min<int64_t>(slice, std::max<int64_t>((int64_t)list.size(), 1));
+  if (!a.alloc(&c->alloc, (size_t)cap * w) || !b.alloc(&c->alloc, (size_t)cap * w)) {
+    set_error("device allocation failed");
+    return SFHE_E_NOMEM;
+  }
+  for (int o = 0; o < cs; ++o) {
+    const std::vector<int64_t>& vs = by_off[o];
+    for (size_t x0 = 0; x0 < vs.size(); x0 += slice) {
+      const int64_t n = std::min<int64_t>(slice, (int64_t)(vs.size() - x0));
+      std::vector<int64_t> es(vs.begin() + x0, vs.begin() + x0 + n), ed(es);
+      for (auto& e : es) e /= cs;
+      if (!upload(c, d_src, es, s) || !upload(c, d_dst, ed, s)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
+      int rc = launch_from_chunked(c, src->data.ptr, src->n_ct, nl, n, d_src.ptr, 0, a.ptr, w, s);
+      const u64* res = a.ptr;
+      if (!rc && o) {
+        rc = rotate_batch(c, lev, a.ptr, w, o, b.ptr, w, n, s);
+        res = b.ptr;
+        rotations += n;
+      }
+      if (!rc) rc = launch_to_chunked(c, res, w, nl, n, dst->data.ptr, dst->n_ct, d_dst.ptr, 0, s);
+      if (rc) return rc;
+    }
+  }
+  return SFHE_OK;
+}
+
+// The end of Algorithm 1 for n relinearised, rescaled products or sums x[b]
+// (rows [2][lev+1][N], level lev, stride lev-wide ciphertexts), all bound for
+// slot roff of their output chunk: multiply by the slot-zero mask, rescale,
+// rotate from slot 0 to slot roff and add into the output chunks; segment o
+// (items seg[o] .. seg[o+1]-1) goes to chunk oidx[o] of out.
+static int finish_products(sfhe_ctx* c, int lev, u64* x, int64_t n, int roff, const std::vector<int>& seg,
+                           const std::vector<int64_t>& oidx, sfhe_mat* out, hipStream_t s, int64_t& rotations) {
+  const int N = c->N, nl = lev + 1;
+  const int64_t wx = (int64_t)2 * nl * N, wy = (int64_t)2 * lev * N;
+  int rc = mask_batch(c, lev, x, wx, n, s);
+  DevBuf<u64> y, z;
+  DevBuf<int> d_seg;
+  DevBuf<int64_t> d_o;
+  if (!rc && (!y.alloc(&c->alloc, (size_t)n * wy) || (roff && !z.alloc(&c->alloc, (size_t)n * wy)) ||
+              !upload(c, d_seg, seg, s) || !upload(c, d_o, oidx, s))) {
+    set_error("device allocation failed");
+    rc = SFHE_E_NOMEM;
+  }
+  if (!rc) rc = rescale_batch(c, lev, x, wx, OutLayout{y.ptr, wy, false, 0, 0}, n, s);
+  const u64* res = y.ptr;
+  if (!rc && roff) {
+    rc = rotate_batch(c, lev - 1, y.ptr, wy, -(int64_t)roff, z.ptr, wy, n, s);
+    res = z.ptr;
+    rotations += n;
+  }
+  if (!rc) rc = launch_segment_sum(c, lev, res, out->data.ptr, out->n_ct, d_seg.ptr, d_o.ptr, (int64_t)oidx.size(), s);
+  return rc;
+}
+
+extern "C" {
+
+int sfhe_matmul_slots(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched, void* stream,
+                      sfhe_mat** C) {
+  GUARD_BEGIN
+  if (!C) { set_error("C is NULL"); return SFHE_E_INVALID_ARG; }
+  *C = nullptr;
+  if (!c || !A || !B) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  if (A->ctx != c || B->ctx != c) { set_error("matrices belong to another context"); return SFHE_E_INVALID_ARG; }
+  if (A->plain || B->plain) { set_error("plaintext weights: use sfhe_matmul_plain"); return SFHE_E_UNSUPPORTED; }
+  if (sched != SFHE_SCHED_PER_PRODUCT && sched != SFHE_SCHED_LAZY) { set_error("bad schedule"); return SFHE_E_INVALID_ARG; }
+  if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
+  if (A->slots != B->slots) { set_error("operands hold different numbers of values per ciphertext"); return SFHE_E_SHAPE; }
+  if (B->enc != SFHE_ENC_DENSE) { set_error("the right operand must be DENSE"); return SFHE_E_UNSUPPORTED; }
+  if (A->cols != B->rows) { set_error("A.cols != B.rows"); return SFHE_E_SHAPE; }
+  if ((int64_t)B->rows * B->cols > 0x7FFFFFFF) { set_error("B too large"); return SFHE_E_INVALID_ARG; }
+  if (A->level != c->L - 1 || B->level != c->L - 1) { set_error("operands must be at the top level"); return SFHE_E_LEVEL; }
+  if (c->L < 4) { set_error("Algorithm 1 with the mask needs four data primes"); return SFHE_E_LEVEL; }
+  if (A->scale != B->scale) { set_error("operand scales differ"); return SFHE_E_SCALE; }
+  hipStream_t s = (hipStream_t)stream;
+  const int N = c->N, top = c->L - 1, M = A->rows, K = A->cols, Nc = B->cols, cs = A->slots;
+  // rotation keys first: their generation synchronises the device
+  std::vector<int64_t> offs;
+  for (int o = 1; o < cs; ++o) { offs.push_back(o); offs.push_back(-o); }
+  int rc = prepare_rotations(c, offs);
+  if (rc) return rc;
+  SFHE_HIP(hipEventRecord(c->ev0, s));
+  int64_t rotations = 0, products = 0, keyswitches = 0;
+  // 1. one-value operands: A's visited values and all of B rotated into slot 0
+  auto one_value = [&](const sfhe_mat* X) {
+    sfhe_mat* R = new sfhe_mat();
+    R->ctx = c;
+    R->rows = X->rows;
+    R->cols = X->cols;
+    R->level = X->level;
+    R->scale = X->scale;
+    R->enc = X->enc;
+    R->nnz = X->nnz;
+    R->row_ptr = X->row_ptr;
+    R->col_idx = X->col_idx;
+    R->ell_w = X->ell_w;
+    R->ell_col = X->ell_col;
+    R->zero_mask = X->zero_mask;
+    R->n_ct = X->n_vals;
+    R->n_vals = X->n_vals;
+    return R;
+  };
+  std::unique_ptr<sfhe_mat> RA(one_value(A)), RB(one_value(B));
+  const int64_t w_top = (int64_t)2 * (top + 1) * N;
+  if (!RA->data.alloc(&c->alloc, (size_t)std::max<int64_t>(RA->n_ct, 1) * w_top) ||
+      !RB->data.alloc(&c->alloc, (size_t)std::max<int64_t>(RB->n_ct, 1) * w_top)) {
+    set_error("device allocation failed");
+    return SFHE_E_NOMEM;
+  }
+  std::vector<int64_t> visits(M);
+  std::vector<std::pair<int, int64_t>> pairs;
+  std::vector<int64_t> used;
+  {
+    std::vector<char> seen((size_t)std::max<int64_t>(A->n_vals, 1), 0);
+    for (int i = 0; i < M; ++i) {
+      row_pairs(A, i, pairs);
+      visits[i] = (int64_t)pairs.size();
+      for (auto& pr : pairs) seen[pr.second] = 1;
+    }
+    for (int64_t v = 0; v < A->n_vals; ++v)
+      if (seen[v]) used.push_back(v);
+  }
+  std::vector<int64_t> allb((size_t)K * Nc);
+  for (int64_t v = 0; v < (int64_t)K * Nc; ++v) allb[v] = v;
+  if (A->enc == SFHE_ENC_ELL || A->enc == SFHE_ENC_NAIVE_SPARSE)
+    rc = launch_zero(RA->data.ptr, RA->n_ct * w_top, s);   // values no product visits stay trivial zeros
+  if (!rc) rc = unpack_values(c, A, used, RA.get(), s, rotations);
+  if (!rc) rc = unpack_values(c, B, allb, RB.get(), s, rotations);
+  if (rc) return rc;
+  // 2. the result: ceil(M Nc / cs) chunks at level top - 2, trivial zeros to start
+  const int lo = top - 2;
+  std::unique_ptr<sfhe_mat> out(new sfhe_mat());
+  out->ctx = c;
+  out->rows = M;
+  out->cols = Nc;
+  out->level = lo;
+  out->scale = A->scale * B->scale / (double)c->primes[top] * ldexp(1.0, (int)c->log2_scale) / (double)c->primes[top - 1];
+  out->enc = SFHE_ENC_DENSE;
+  out->slots = cs;
+  out->n_vals = (int64_t)M * Nc;
+  out->n_ct = (out->n_vals + cs - 1) / cs;
+  out->nnz = out->n_vals;
+  if (!out->data.alloc(&c->alloc, (size_t)out->n_ct * 2 * (lo + 1) * N)) {
+    set_error("device allocation failed for the result");
+    return SFHE_E_NOMEM;
+  }
+  rc = launch_zero(out->data.ptr, out->n_ct * 2 * (lo + 1) * N, s);
+  if (rc) return rc;
+  const int l1 = top - 1;                            // level after the first rescale
+  const int64_t w1 = (int64_t)2 * (l1 + 1) * N;
+  const int64_t slice = 256;
+  if (sched == SFHE_SCHED_LAZY) {
+    // sums of the one-value products, relinearised and rescaled (level top - 1)
+    sfhe_mat* C1 = nullptr;
+    rc = matmul_c1(c, RA.get(), RB.get(), SFHE_SCHED_LAZY, s, &C1, false);
+    if (rc) return rc;
+    std::unique_ptr<sfhe_mat> C1p(C1);
+    products = c->stats.products;
+    keyswitches += c->stats.keyswitches;
+    // outputs with a product, by their slot in the output chunk
+    std::vector<std::vector<int64_t>> by_off(cs);
+    for (int i = 0; i < M; ++i)
+      if (visits[i])
+        for (int j = 0; j < Nc; ++j) by_off[((int64_t)i * Nc + j) % cs].push_back((int64_t)i * Nc + j);
+    DevBuf<u64> X;
+    DevBuf<int64_t> d_e;
+    if (!X.alloc(&c->alloc, (size_t)slice * w1)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
+    for (int o = 0; o < cs && !rc; ++o)
+      for (size_t x0 = 0; x0 < by_off[o].size() && !rc; x0 += slice) {
+        const int64_t n = std::min<int64_t>(slice, (int64_t)(by_off[o].size() - x0));
+        std::vector<int64_t> es(by_off[o].begin() + x0, by_off[o].begin() + x0 + n), oidx(es);
+        std::vector<int> seg(n + 1);
+        for (int64_t x = 0; x <= n; ++x) seg[x] = (int)x;
+        for (auto& e : oidx) e /= cs;
+        if (!upload(c, d_e, es, s)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
+        rc = launch_from_chunked(c, C1->data.ptr, C1->n_ct, l1 + 1, n, d_e.ptr, 0, X.ptr, w1, s);
+        if (!rc) rc = finish_products(c, l1, X.ptr, n, o, seg, oidx, out.get(), s, rotations);
+      }
+  } else {
+    // Algorithm 1's order: every product relinearised, rescaled, masked,
+    // rescaled and rotated on its own, then added into its output chunk
+    struct Item { int64_t rs, sa, sb; };
+    std::vector<std::vector<Item>> by_off(cs);
+    for (int i = 0; i < M; ++i) {
+      if (!visits[i]) continue;
+      row_pairs(A, i, pairs);
+      for (int j = 0; j < Nc; ++j) {
+        const int64_t rs = (int64_t)i * Nc + j;
+        for (auto& pr : pairs) by_off[rs % cs].push_back(Item{rs, pr.second, (int64_t)pr.first * Nc + j});
+      }
+    }
+    const int64_t dw = (int64_t)3 * (top + 1) * N;
+    DevBuf<u64> D, T;
+    DevBuf<int> d_a, d_b;
+    if (!D.alloc(&c->alloc, (size_t)slice * dw) || !T.alloc(&c->alloc, (size_t)slice * w1)) {
+      set_error("device allocation failed");
+      return SFHE_E_NOMEM;
+    }
+    for (int o = 0; o < cs && !rc; ++o)
+      for (size_t x0 = 0; x0 < by_off[o].size() && !rc; x0 += slice) {
+        const int64_t n = std::min<int64_t>(slice, (int64_t)(by_off[o].size() - x0));
+        std::vector<int> ai(n), bi(n), seg;
+        std::vector<int64_t> oidx;
+        for (int64_t x = 0; x < n; ++x) {
+          const Item& it = by_off[o][x0 + x];
+          ai[x] = (int)it.sa;
+          bi[x] = (int)it.sb;
+          if (x == 0 || it.rs != by_off[o][x0 + x - 1].rs) { seg.push_back((int)x); oidx.push_back(it.rs / cs); }
+        }
+        seg.push_back((int)n);
+        if (!upload(c, d_a, ai, s) || !upload(c, d_b, bi, s)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
+        rc = launch_tensor_gather(c, top, RA->data.ptr, RA->n_ct, RB->data.ptr, RB->n_ct, d_a.ptr, d_b.ptr, D.ptr, n, s);
+        const OutLayout ol{T.ptr, w1, false, 0, 0};
+        if (!rc && keyswitch_rescale_n14_supported(c)) {
+          rc = keyswitch_rescale_n14(c, top, D.ptr, dw, ol, n, s);
+        } else if (!rc) {
+          rc = keyswitch_batch(c, top, D.ptr + (int64_t)2 * (top + 1) * N, dw, D.ptr, dw, true, n, s);
+          if (!rc) rc = rescale_batch(c, top, D.ptr, dw, ol, n, s);
+        }
+        if (!rc) rc = finish_products(c, l1, T.ptr, n, o, seg, oidx, out.get(), s, rotations);
+        products += n;
+        keyswitches += n;
+      }
+  }
+  if (rc) return rc;
+  SFHE_HIP(hipEventRecord(c->ev1, s));
+  c->stats = sfhe_stats{};
+  c->stats.products = products;
+  c->stats.keyswitches = keyswitches + rotations;   // relinearisations and rotations
+  c->stats.outputs = out->n_ct;
+  c->stats.tensor_fp_primes = tensor_fp_prime_count(c);
+  c->stats_pending = true;
+  *C = out.release();
+  return SFHE_OK;
   GUARD_END
 }
 

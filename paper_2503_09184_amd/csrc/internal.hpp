@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -25,13 +26,17 @@ struct ModUpConst {
   u64 inv_n[kMaxDigit], inv_n_s[kMaxDigit];   // inv * N^-1 mod q_i (applied with an inverse NTT)
   u64 conv[kMaxDigit][kMaxBasis], conv_s[kMaxDigit][kMaxBasis];
 };
-// ModDown at level lev: y_k = [acc_{p_k} (P/p_k)^-1]_{p_k};
-// out_i = (acc_i - sum_k y_k [P/p_k]_{q_i}) [P^-1]_{q_i}.
+// ModDown at level lev: y_k = [acc_{p_k} (P/p_k)^-1]_{p_k} taken in
+// (-p_k/2, p_k/2) (the centered conversion: y_k above (p_k - 1)/2 stands for
+// y_k - p_k); out_i = (acc_i - sum_k y_k [P/p_k]_{q_i}) [P^-1]_{q_i}, i.e. the
+// uncentered sum minus c [P]_{q_i}, c the count of such y_k, before the
+// product with P^-1 (or c added after it).
 struct ModDownConst {
   u64 pinv[kMaxDigit], pinv_s[kMaxDigit];            // (P/p_k)^-1 mod p_k
   u64 pinv_n[kMaxDigit], pinv_n_s[kMaxDigit];        // (P/p_k)^-1 N^-1 mod p_k
   u64 conv[kMaxDigit][kMaxBasis], conv_s[kMaxDigit][kMaxBasis];   // [P/p_k]_{q_i}
   u64 Pinv[kMaxBasis], Pinv_s[kMaxBasis];            // P^-1 mod q_i
+  u64 Pq[kMaxBasis];                                 // P mod q_i
 };
 // Rescale at level lev: q_lev^-1 mod q_i for i < lev.
 struct RescaleConst {
@@ -110,6 +115,13 @@ struct sfhe_ctx {
   size_t prof_used = 0;
   std::vector<int> prof_cat;
   hipEvent_t prof_event();
+  // several values per ciphertext (rotate.hip): the key seed, then per Galois
+  // element g its NTT-domain automorphism table and rotation key, built on
+  // first use; 5^j mod 2N for j < 64; the slot-zero mask, NTT domain [L][N]
+  sfhe::u64 key_seed = 0;
+  std::map<sfhe::u64, sfhe::DevBuf<int>> auto_perm;
+  std::map<sfhe::u64, sfhe::DevBuf<sfhe::u64>> rot_keys;
+  sfhe::DevBuf<sfhe::u64> d_gal, d_mask0;
 };
 
 struct sfhe_mat {
@@ -130,6 +142,10 @@ struct sfhe_mat {
   // each stored weight per data prime, host side, [n_ct][L]
   bool plain = false;
   std::vector<uint64_t> w_res;
+  // several values per ciphertext (Sec. 3.2): stored value v sits in slot
+  // v mod slots of ciphertext v / slots; n_ct = ceil(n_vals / slots)
+  int slots = 1;
+  int64_t n_vals = 0;
 };
 
 namespace sfhe {
@@ -177,9 +193,10 @@ int launch_to_chunked(const sfhe_ctx* c, const u64* src, int64_t sstride, int nl
 int launch_from_chunked(const sfhe_ctx* c, const u64* src, int64_t n_ct, int nl, int64_t count, const int64_t* elem,
                         int64_t elem_base, u64* dst, int64_t dstride, hipStream_t s);
 int keygen_device(sfhe_ctx* c, u64 seed, hipStream_t s);
-// decrypt + decode: values[e] for every ciphertext of a chunked matrix at level lev
+// decrypt + decode: value v = e slots + j (slot j of ciphertext e, v < nvals)
+// for every ciphertext of a chunked matrix at level lev
 int decrypt_values(sfhe_ctx* c, const u64* data, int64_t n_ct, int lev, double scale, double* d_out, int* d_flag,
-                   hipStream_t s);
+                   hipStream_t s, int slots = 1, int64_t nvals = -1);
 
 // tensor products
 int launch_tensor_pointwise(const sfhe_ctx* c, int lev, const u64* a, int64_t astride, const u64* b,
@@ -242,8 +259,9 @@ int launch_plain_product(const sfhe_ctx* c, const u64* B, int64_t nB, int64_t sl
 
 // key switch of d2 rows (batch stride d2stride), result added into out
 // (batch stride ostride, [2][nl][N]) if add_in, else written.
+// key: [dnum][2][nb][N] NTT domain, the relinearisation key when null
 int keyswitch_batch(sfhe_ctx* c, int lev, const u64* d2, int64_t d2stride, u64* out, int64_t ostride,
-                    bool add_in, int64_t batch, hipStream_t s);
+                    bool add_in, int64_t batch, hipStream_t s, const u64* key = nullptr);
 // where rescale writes: limb-major rows (stride words apart) or ciphertexts
 // elem_base + b of a chunked matrix holding n_ct ciphertexts
 struct OutLayout {
@@ -274,5 +292,27 @@ int launch_segment_sum(const sfhe_ctx* c, int nl, const u64* t, u64* out, int64_
 // zero ciphertexts oidx[0..n) of a chunked matrix at nl primes
 int launch_zero_outputs(const sfhe_ctx* c, u64* out, int64_t n_ct, int nl, const int64_t* d_oidx, int64_t n,
                         hipStream_t s);
+
+// ---- several values per ciphertext and rotations (rotate.hip) ----
+// 5^r mod 2N (slot j + r moves to slot j)
+u64 galois_element(const sfhe_ctx* c, int64_t r);
+// device table of X -> X^g on NTT-domain rows (out[p] = in[table[p]]), cached
+const int* automorphism_table(sfhe_ctx* c, u64 g);
+// rotation key of g, NTT domain [dnum][2][nb][N], generated on first use
+const u64* rotation_key(sfhe_ctx* c, u64 g);
+// the device table 5^j mod 2N, j < 64 (slot decoding), built once
+int slot_table(sfhe_ctx* c);
+// build the keys of the rotations by each of offsets (before enqueuing work)
+int prepare_rotations(sfhe_ctx* c, const std::vector<int64_t>& offsets);
+// rotate n ciphertexts in[x] ([2][lev+1][N] NTT domain, stride istride) by r
+// slots into out (stride ostride); in and out must not overlap
+int rotate_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, int64_t r, u64* out, int64_t ostride,
+                 int64_t n, hipStream_t s);
+// encrypt chunks x0 .. x0 + count - 1 of nvals stored values (slots per
+// chunk) into tmp[count][2][L][N], NTT domain
+int encrypt_slots(sfhe_ctx* c, u64* tmp, int64_t count, int64_t x0, const double* d_vals, int64_t nvals, int slots,
+                  u64 seed, u64 operand, hipStream_t s);
+// multiply n ciphertexts x[b] ([2][lev+1][N], stride words) by the slot-zero mask
+int mask_batch(sfhe_ctx* c, int lev, u64* x, int64_t stride, int64_t n, hipStream_t s);
 
 }  // namespace sfhe

@@ -82,7 +82,8 @@ __global__ void ks_inner_kernel(const u64* d2n, int64_t d2stride, const u64* xbu
   }
 }
 
-// z[b][p][i][t] = sum_k [acc_{p_k} (P/p_k)^-1]_{p_k} [P/p_k]_{q_i}  (coefficient domain)
+// z[b][p][i][t] = sum_k y_k [P/p_k]_{q_i}, y_k = [acc_{p_k} (P/p_k)^-1]_{p_k}
+// centered (coefficient domain)
 __global__ void moddown_kernel(const u64* acc, int nl, int ne, u64* z, const ModDownConst* __restrict__ md,
                                int64_t batch, DevParams dp) {
   const int N = dp.N, alpha = dp.alpha, L = dp.L;
@@ -91,11 +92,13 @@ __global__ void moddown_kernel(const u64* acc, int nl, int ne, u64* z, const Mod
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N) return;
   u64 y[kMaxDigit];
+  u64 neg = 0;   // residues above (p_k - 1) / 2: they stand for y_k - p_k
 #pragma unroll
   for (int k = 0; k < kMaxDigit; ++k) {
     if (k < alpha) {
       const u64 pk = dp.pr[L + k].q;
       y[k] = mul_shoup(acc[(row * ne + nl + k) * N + t], md->pinv[k], md->pinv_s[k], pk);
+      neg += y[k] > (pk - 1) / 2;
     } else {
       y[k] = 0;
     }
@@ -106,7 +109,7 @@ __global__ void moddown_kernel(const u64* acc, int nl, int ne, u64* z, const Mod
 #pragma unroll
     for (int k = 0; k < kMaxDigit; ++k)
       if (k < alpha) s = add_mod(s, mul_shoup(y[k], md->conv[k][i], md->conv_s[k][i], qi), qi);
-    z[(row * nl + i) * N + t] = s;
+    z[(row * nl + i) * N + t] = sub_mod(s, mul_mod(neg, md->Pq[i], dp.pr[i]), qi);
   }
 }
 
@@ -131,8 +134,9 @@ __global__ void moddown_finish_kernel(const u64* acc, int nl, int ne, const u64*
 }
 
 int keyswitch_batch(sfhe_ctx* c, int lev, const u64* d2, int64_t d2stride, u64* out, int64_t ostride, bool add_in,
-                    int64_t batch, hipStream_t s) {
+                    int64_t batch, hipStream_t s, const u64* key) {
   if (batch <= 0) return SFHE_OK;
+  if (!key) key = c->d_rlk.ptr;
   const int N = c->N, nl = lev + 1, ne = nl + c->alpha;
   DevBuf<u64> d2c, xbuf, acc, z;
   if (!d2c.alloc(&c->alloc, (size_t)batch * nl * N) || !xbuf.alloc(&c->alloc, (size_t)batch * ne * N) ||
@@ -170,7 +174,7 @@ int keyswitch_batch(sfhe_ctx* c, int lev, const u64* d2, int64_t d2stride, u64* 
     if (rc) return rc;
     grid_rows(batch * ne, gy, gz);
     hipLaunchKernelGGL(ks_inner_kernel, dim3((N + 255) / 256, gy, gz), dim3(256), 0, s, d2, d2stride, xbuf.ptr,
-                       acc.ptr, j, first, mc, c->d_rlk.ptr, c->dp, batch);
+                       acc.ptr, j, first, mc, key, c->dp, batch);
     SFHE_HIP(hipGetLastError());
     first = false;
   }

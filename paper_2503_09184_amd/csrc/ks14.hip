@@ -298,13 +298,20 @@ __global__ void __launch_bounds__(256) ks14_k2own_kernel(Ks14Args a, DevParams d
 }
 
 // ---------------------------------------------------------------- K3a
-// z = sum_k yP_k [P/p_k]_{q_i} at one position (yb = yP rows of (b, p) at it)
+// z P^-1 mod q_i at one position (yb = yP rows of (b, p) at it), z = sum_k
+// yP_k [P/p_k]_{q_i} with yP_k centered: the uncentered sum times P^-1, minus
+// the count of yP_k above (p_k - 1) / 2
 template <int ALPHA>
-__device__ __forceinline__ u64 moddown_z(const u64* yb, const ModDownConst* md, int i, u64 q) {
-  u64 z = 0;
+__device__ __forceinline__ u64 moddown_zp(const u64* yb, const ModDownConst* md, int i, u64 q, u64 Pi, u64 Pis,
+                                          const DevParams& dp) {
+  u64 z = 0, neg = 0;
 #pragma unroll
-  for (int k = 0; k < ALPHA; ++k) z = add_mod(z, mul_shoup(yb[(int64_t)k * kN], md->conv[k][i], md->conv_s[k][i], q), q);
-  return z;
+  for (int k = 0; k < ALPHA; ++k) {
+    const u64 y = yb[(int64_t)k * kN];
+    z = add_mod(z, mul_shoup(y, md->conv[k][i], md->conv_s[k][i], q), q);
+    neg += y > (dp.pr[dp.L + k].q - 1) / 2;
+  }
+  return sub_mod(mul_shoup(z, Pi, Pis, q), neg, q);
 }
 
 // instantiated per alpha: a run-time trip count inside the unrolled
@@ -333,7 +340,7 @@ __device__ __forceinline__ void k3a_body(const Ks14Args& a, const DevParams& dp,
 #pragma unroll
   for (int u = 0; u < 32; ++u) {
     const int x = pos_a(tt, u);
-    const u64 z = mul_shoup(moddown_z<ALPHA>(yb + x, a.md, lev, q), Pi, Pis, q);
+    const u64 z = moddown_zp<ALPHA>(yb + x, a.md, lev, q, Pi, Pis, dp);
     o[x] = sub_mod(ar.out_inv(v[u], P), z, q);
     group_fence<4>(u);
   }
@@ -360,27 +367,32 @@ __global__ void __launch_bounds__(kEwThreads) ks14_lift_kernel(Ks14Args a, DevPa
   const PrimeDev& P = dp.pr[i];
   const u64 q = P.q;
   const u64 Pi = a.md->Pinv[i], Pis = a.md->Pinv_s[i];
-  u64 cv[ALPHA], cs[ALPHA];
+  u64 cv[ALPHA], cs[ALPHA], ph[ALPHA];
 #pragma unroll
   for (int k = 0; k < ALPHA; ++k) {
     cv[k] = a.md->conv[k][i];
     cs[k] = a.md->conv_s[k][i];
+    ph[k] = (dp.pr[dp.L + k].q - 1) / 2;
   }
   const u64* yb = a.yP + (int64_t)bp * ALPHA * kN + x0;
   const u64* rb = a.r + (int64_t)bp * kN + x0;
   u64* o = a.w + (int64_t)blockIdx.y * kN + x0;
 #pragma unroll
   for (int m = 0; m < kEwPer; ++m) {
-    u64 z = 0;
+    u64 z = 0, above = 0;   // centered conversion: residues above (p_k - 1) / 2 stand for y - p_k
 #pragma unroll
-    for (int k = 0; k < ALPHA; ++k) z = add_mod(z, mul_shoup(yb[(int64_t)k * kN + m * kEwThreads], cv[k], cs[k], q), q);
+    for (int k = 0; k < ALPHA; ++k) {
+      const u64 y = yb[(int64_t)k * kN + m * kEwThreads];
+      z = add_mod(z, mul_shoup(y, cv[k], cs[k], q), q);
+      above += y > ph[k];
+    }
     // centered lift of the last prime, reduced mod q_i
     const u64 c = rb[m * kEwThreads];
     const bool neg = c > (ql - 1) / 2;
     const u64 mag = neg ? ql - c : c;
     u64 r = mag < q ? mag : reduce_wide(U128{mag, 0}, q, P.mu_hi, P.mu_lo);
     r = (neg && r) ? q - r : r;
-    o[m * kEwThreads] = add_mod(mul_shoup(z, Pi, Pis, q), r, q);
+    o[m * kEwThreads] = add_mod(sub_mod(mul_shoup(z, Pi, Pis, q), above, q), r, q);
   }
 }
 

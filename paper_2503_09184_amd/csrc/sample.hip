@@ -139,6 +139,8 @@ __global__ void rlk_finish_kernel(u64* rlk, const u64* s_ntt, const u64* gad, De
 
 int keygen_device(sfhe_ctx* c, u64 seed, hipStream_t s) {
   const int N = c->N, nb = c->nb, dnum = c->dnum;
+  c->key_seed = seed;
+  c->rot_keys.clear();
   if (!c->d_s.alloc(&c->alloc, (size_t)nb * N) || !c->d_rlk.alloc(&c->alloc, (size_t)dnum * 2 * nb * N)) {
     set_error("keygen: device allocation failed");
     return SFHE_E_NOMEM;
@@ -204,15 +206,20 @@ __global__ void dec_phase_kernel(const u64* ct, int64_t count, int64_t ctstride,
   m[(x * nl + r) * N + t] = add_mod(c0[t], mul_mod(c1[t], s_ntt[(int64_t)r * N + t], P), P.q);
 }
 
-// decode slot 0: sum_t m_t cos(pi t / N) / scale, m_t the centered integer.
-// The candidate comes from the largest prime's residue; every other residue
-// must agree with it, else the coefficient is out of the decodable range.
+// decode slot j = blockIdx.y: sum_t m_t cos(pi (g t mod 2N) / N) / scale,
+// g = 5^j, m_t the centered integer (slot 0: g = 1).  The candidate comes
+// from the largest prime's residue; every other residue must agree with it,
+// else the coefficient is out of the decodable range.  Value x slots + j goes
+// to out[x slots + j] when below nvals.
 __global__ void __launch_bounds__(256) dec_decode_kernel(const u64* m, int nl, int big, double inv_scale,
-                                                         const double* cosv, double* out, int* flag,
-                                                         DevParams dp) {
+                                                         const double* cosv, const u64* gal, int slots,
+                                                         int64_t nvals, double* out, int* flag, DevParams dp) {
   __shared__ double red[256];
   const int N = dp.N;
   const int64_t x = blockIdx.x;
+  const int64_t v = x * slots + blockIdx.y;
+  if (v >= nvals) return;   // uniform across the block
+  const u64 g = blockIdx.y ? gal[blockIdx.y] : 1, m2 = 2 * (u64)N;
   const u64* mx = m + x * nl * N;
   const u64 qb = dp.pr[big].q;
   double acc = 0.0;
@@ -222,7 +229,8 @@ __global__ void __launch_bounds__(256) dec_decode_kernel(const u64* m, int nl, i
     const i64 cv = v > (qb - 1) / 2 ? -(i64)(qb - v) : (i64)v;
     for (int r = 0; r < nl; ++r)
       if (r != big && signed_mod(cv, dp.pr[r]) != mx[(int64_t)r * N + t]) bad = 1;
-    acc += (double)cv * cosv[t];
+    const u64 e = g * (u64)t % m2;
+    acc += (double)cv * (e < (u64)N ? cosv[e] : -cosv[e - N]);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -231,12 +239,17 @@ __global__ void __launch_bounds__(256) dec_decode_kernel(const u64* m, int nl, i
     __syncthreads();
   }
   if (bad) atomicOr(flag, 1);
-  if (threadIdx.x == 0) out[x] = red[0] * inv_scale;
+  if (threadIdx.x == 0) out[v] = red[0] * inv_scale;
 }
 
 int decrypt_values(sfhe_ctx* c, const u64* data, int64_t n_ct, int lev, double scale, double* d_out, int* d_flag,
-                   hipStream_t s) {
+                   hipStream_t s, int slots, int64_t nvals) {
   const int N = c->N, nl = lev + 1;
+  if (nvals < 0) nvals = n_ct * slots;
+  if (slots > 1 && !c->d_gal.ptr) {
+    set_error("decrypt: slot table missing");
+    return SFHE_E_STATE;
+  }
   const int64_t chunk = 512;
   const int64_t ctw = (int64_t)2 * nl * N;
   DevBuf<u64> ct, m;
@@ -261,8 +274,9 @@ int decrypt_values(sfhe_ctx* c, const u64* data, int64_t n_ct, int lev, double s
     SFHE_HIP(hipGetLastError());
     rc = launch_ntt(c, m.ptr, n, (int64_t)nl * N, nl, pos, pr, true, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(dec_decode_kernel, dim3((unsigned)n), dim3(256), 0, s, m.ptr, nl, big, 1.0 / scale,
-                       c->d_cos.ptr, d_out + x0, d_flag, c->dp);
+    hipLaunchKernelGGL(dec_decode_kernel, dim3((unsigned)n, (unsigned)slots), dim3(256), 0, s, m.ptr, nl, big,
+                       1.0 / scale, c->d_cos.ptr, c->d_gal.ptr, slots, nvals - x0 * slots, d_out + x0 * slots, d_flag,
+                       c->dp);
     SFHE_HIP(hipGetLastError());
   }
   SFHE_HIP(hipStreamSynchronize(s));

@@ -31,7 +31,8 @@ EXPORTED = [
     "sfhe_encode_matrix", "sfhe_matmul_plain", "sfhe_matmul_plain_batch",
     "sfhe_server_create", "sfhe_server_submit", "sfhe_server_step", "sfhe_server_poll", "sfhe_server_status",
     "sfhe_server_destroy", "sfhe_plain_graph_create", "sfhe_plain_graph_launch", "sfhe_plain_graph_result",
-    "sfhe_plain_graph_destroy",
+    "sfhe_plain_graph_destroy", "sfhe_encrypt_matrix_slots", "sfhe_matmul_slots", "sfhe_export_stored",
+    "sfhe_rotate",
 ]
 
 PLAIN_LAUNCH = {"fused": 0, "per_product": 1}
@@ -61,7 +62,8 @@ class Hooks(ctypes.Structure):
 class MatInfo(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("cols", ctypes.c_int32), ("level", ctypes.c_int32),
                 ("scale", ctypes.c_double), ("enc", ctypes.c_int), ("n_ciphertexts", ctypes.c_int64),
-                ("nnz", ctypes.c_int64), ("ell_width", ctypes.c_int32), ("device_bytes", ctypes.c_uint64)]
+                ("nnz", ctypes.c_int64), ("ell_width", ctypes.c_int32), ("device_bytes", ctypes.c_uint64),
+                ("slots", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -124,6 +126,11 @@ def lib():
         L.sfhe_plain_graph_result.argtypes = [vp, i32, ctypes.POINTER(vp)]
         L.sfhe_plain_graph_destroy.argtypes = [vp]
         L.sfhe_plain_graph_destroy.restype = None
+        L.sfhe_encrypt_matrix_slots.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, i32, i64, ctypes.c_int, i32,
+                                                u64, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
+        L.sfhe_matmul_slots.argtypes = [vp, vp, vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.sfhe_export_stored.argtypes = [vp, vp, i64, ctypes.POINTER(u64), ctypes.c_size_t, vp]
+        L.sfhe_rotate.argtypes = [vp, i32, vp, vp, i32, i32, vp]
         _lib = L
     return _lib
 
@@ -329,6 +336,41 @@ class Context:
         _check(lib().sfhe_matmul(self._h, A.handle, B.handle, SCHED[sched], _stream_handle(stream),
                                  ctypes.byref(h)))
         return Matrix(self, h)
+
+    # ---- several values per ciphertext (chunks) --------------------------
+    def encrypt_slots(self, vals, enc, slots, seed, operand, stream=None):
+        """The stored values of `enc` in chunks of `slots` values per ciphertext."""
+        v = np.ascontiguousarray(vals, dtype=np.float64)
+        rows, cols = v.shape
+        h = ctypes.c_void_p()
+        _check(lib().sfhe_encrypt_matrix_slots(self._h, v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), rows,
+                                               cols, cols, ENC[enc], int(slots), ctypes.c_uint64(seed),
+                                               int(operand), _stream_handle(stream), ctypes.byref(h)))
+        return Matrix(self, h)
+
+    def matmul_slots(self, A, B, sched, stream=None):
+        """Algorithm 1 with rotations and the slot-zero mask."""
+        h = ctypes.c_void_p()
+        _check(lib().sfhe_matmul_slots(self._h, A.handle, B.handle, SCHED[sched], _stream_handle(stream),
+                                       ctypes.byref(h)))
+        return Matrix(self, h)
+
+    def export_stored(self, M, n, stream=None):
+        info = M.info()
+        out = np.zeros((2, info.level + 1, self.n), dtype=np.uint64)
+        _check(lib().sfhe_export_stored(self._h, M.handle, int(n), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                        out.size, _stream_handle(stream)))
+        return out
+
+    def rotate(self, level, ct, r, stream=None):
+        """Rotation by r slots of a device tensor [batch, 2, level+1, N] (NTT domain)."""
+        nl = level + 1
+        assert ct.is_contiguous()
+        batch = ct.numel() // (2 * nl * self.n)
+        out = self._torch.empty(batch * 2 * nl * self.n, dtype=self._torch.int64, device="cuda")
+        _check(lib().sfhe_rotate(self._h, level, ctypes.c_void_p(ct.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                 batch, int(r), _stream_handle(stream)))
+        return out.view(batch, 2, nl, self.n)
 
     # ---- plaintext weights times encrypted values -----------------------
     def encode_weights(self, vals, enc, log2_scale_w=40):

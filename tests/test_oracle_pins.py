@@ -280,8 +280,8 @@ def test_modup_is_one_small_integer(params):
 
 @pytest.mark.parametrize("params", [TINY_HYBRID, TINY_SINGLE])
 def test_moddown_divides_by_P(params):
-    """out = (X - F)/P exactly with F = X mod P lifted to [0, alpha*P):
-    |out - X/P| <= alpha for every coefficient (big integers)."""
+    """out = (X - F)/P exactly with F = X mod P lifted to (-alpha*P/2,
+    alpha*P/2): the centered conversion (big integers)."""
     o = make(params)
     rng = np.random.default_rng(4)
     lev = o.L - 1
@@ -293,9 +293,9 @@ def test_moddown_divides_by_P(params):
     for t in range(o.n):
         X = brute.crt([int(acc[e, t]) for e in range(len(basis))], basis)
         Y = brute.crt([int(out[i, t]) for i in range(lev + 1)], o.q[:lev + 1])
-        # Y = (X - F) / P mod Q with 0 <= F < alpha*P, F = X mod P
-        F = (X - Y * P) % (P * Q)
-        assert F < o.alpha * P
+        # Y = (X - F) / P mod Q with |F| < alpha*P/2, F = X mod P
+        F = brute.centered((X - Y * P) % (P * Q), P * Q)
+        assert 2 * abs(F) < o.alpha * P
         assert F % P == X % P
 
 
@@ -675,6 +675,21 @@ def test_rotation_moves_slots(r):
         src = (j + r) % h
         want = z[src] if src < len(z) else 0.0
         assert abs(o.decrypt_slot(o.L - 1, rot, 2.0 ** o.log2_scale, j) - want) < 1e-6, (r, j)
+
+
+def test_rotation_has_no_low_frequency_bias():
+    """N = 2^14: after a rotation slot 0 is within 1e-7 of its value.  An
+    uncentered ModDown leaves u s in the result (u the conversion overflow,
+    mean (alpha - 1)/2 = 1 here), a random walk over the coefficients whose
+    slot-0 component is about 2 N/pi sqrt(N/3) ~ 7.7e5, i.e. 7e-7 at Delta =
+    2^40; the centered conversion has u of mean zero."""
+    o = make(W.PARAMS["realistic_n16384"], seed=3)
+    z = np.array([0.5, -0.25, 0.75, 0.1])
+    ct = o.encrypt_slots(z, 3, 0, 0)
+    rot = o.rotate(o.L - 1, ct, 1)
+    S = 2.0 ** o.log2_scale
+    for j in range(3):
+        assert abs(o.decrypt_slot(o.L - 1, rot, S, j) - z[j + 1]) < 1e-7, j
 
 
 @pytest.mark.parametrize("chunk", [1, 2, 4])
