@@ -211,6 +211,32 @@ def ctpt_leg(torch, sfhe, W, count=32):
             "host_wall_s": wall, "per_product_launch_sample": sample}
 
 
+def slots_leg(ctx, torch, A, Bm, sa, sb, chunk):
+    """Algorithm 1 with chunks of `chunk` values per ciphertext (rotations into
+    slot 0, the slot-0 mask, rotation to the output slot), LAZY, on the
+    headline operands: one untimed call (it builds the rotation keys), then
+    one timed call."""
+    EA = ctx.encrypt_slots(A, "csr", chunk, sa, 0)
+    EB = ctx.encrypt_slots(Bm, "dense", chunk, sb, 1)
+    torch.cuda.synchronize()
+    ctx.matmul_slots(EA, EB, "lazy").close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C = ctx.matmul_slots(EA, EB, "lazy")
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    st = ctx.last_stats()
+    err = float(np.max(np.abs(ctx.decrypt(C) - A @ Bm)))
+    out = {"ms": st.ms, "wall_ms": wall, "products": int(st.products), "ct_mults_per_s": st.products / (st.ms / 1e3),
+           "keyswitches_and_rotations": int(st.keyswitches), "chunk": chunk,
+           "ciphertexts_A": int(EA.info().n_ciphertexts), "ciphertexts_B": int(EB.info().n_ciphertexts),
+           "ciphertexts_C": int(C.info().n_ciphertexts), "max_abs_err_vs_fp64": err}
+    for M in (C, EA, EB):
+        M.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
     """The request loop over plaintext-weight products: encrypted MLP-layer
     requests (weights 128x784, 256x256 or 128x512, i.e. layers 784->128,
@@ -334,7 +360,7 @@ def main():
     ap.add_argument("--sparsity", type=float, default=0.5)
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--only", default="", help="comma list of extra legs to run (default all): "
-                    "s90,dense,ell,naive,per_product,both,serve,ctpt,cpu")
+                    "s90,dense,ell,naive,per_product,both,slots,serve,ctpt,cpu")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -454,6 +480,12 @@ def main():
     EA.close()
     EB.close()
     torch.cuda.empty_cache()
+    if run("slots"):
+        log("chunks of 8 values per ciphertext: Algorithm 1 with rotations and the slot-0 mask")
+        legs["slots8_lazy_csr_50"] = slots_leg(ctx, torch, A, Bm, sa, sb, 8)
+        log("slots8: %.1f ms, %d products, %d key switches and rotations, err %.2e" %
+            (legs["slots8_lazy_csr_50"]["ms"], legs["slots8_lazy_csr_50"]["products"],
+             legs["slots8_lazy_csr_50"]["keyswitches_and_rotations"], legs["slots8_lazy_csr_50"]["max_abs_err_vs_fp64"]))
     if run("serve"):
         log("serving: Poisson arrivals of encrypted MLP-layer requests")
         legs["serving"] = serving_leg(torch, sfhe, W)
