@@ -338,6 +338,23 @@ const char* sfhe_last_error(void);
  * primitive inputs and outputs) uses that order; coefficient-domain rows are
  * always in natural order.  Buffers must not overlap unless stated. */
 
+/* NTT designs (the transform radix and tile of every launch of
+ * sfhe_ntt and of the library's unfused transforms: encryption, decryption,
+ * the generic key switch and rescale, rotations): 0 = the register transform
+ * (32 residues per thread, half-row LDS exchanges; N >= 2^14), 1, 2, 3 = the
+ * LDS transform with radix-16, radix-8 or radix-4 passes (one thread per 16,
+ * 8 or 4 residues; N <= 2^14).  All give the same bits in the storage order
+ * above.  sfhe_ctx_create times every design that applies to the ring (a
+ * scratch batch of about 2048 rows) and keeps the fastest per
+ * direction; N = 2^15 has the register design only.  The fused N = 2^14
+ * kernels (key switch, rescale) always use the register design. */
+/* The design in use for direction `inverse` and, in us_per_row[0..cap), the
+ * measured microseconds per row of each design (-1: does not apply). */
+int sfhe_ntt_tuning(const sfhe_ctx* ctx, int32_t inverse, int32_t* variant, double* us_per_row, int32_t cap);
+/* Use design `variant` for direction `inverse` (SFHE_E_UNSUPPORTED if it does
+ * not apply to the ring); -1 returns to the measured choice. */
+int sfhe_set_ntt_variant(sfhe_ctx* ctx, int32_t inverse, int32_t variant);
+
 /* In-place negacyclic NTT (inverse = 0) or inverse NTT (inverse = 1) of
  * `batch` groups of n_limbs rows laid out [batch][n_limbs][N]; row l of a
  * group is taken modulo basis prime first_prime + l. */

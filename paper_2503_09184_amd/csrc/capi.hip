@@ -263,6 +263,59 @@ static int build_tables(sfhe_ctx* c) {
   return SFHE_OK;
 }
 
+// Which designs can transform this ring (each gives the same bits in the
+// library's storage order): the register design at N >= 2^14, the LDS
+// designs at N <= 2^14 (N = 2^15 runs halves of the register design only).
+static bool ntt_variant_applies(const sfhe_ctx* c, int v) {
+  if (v == kNttRegister) return c->logN >= 14;
+  return v >= kNttRadix16 && v <= kNttRadix4 && c->logN <= 14;
+}
+
+// Time every applicable design on a scratch batch of about 2048 rows (groups
+// of one row per basis prime: enough blocks to fill the chip; 1 warm-up and
+// 3 timed launches each) and keep the fastest per direction.
+static int tune_ntt(sfhe_ctx* c) {
+  for (int d = 0; d < 2; ++d) {
+    c->ntt_var[d] = c->ntt_tuned[d] = c->logN >= 14 ? kNttRegister : kNttRadix16;
+    for (int v = 0; v < 4; ++v) c->ntt_us[d][v] = -1.0;
+  }
+  if (c->logN > 14) return SFHE_OK;
+  const int N = c->N, nb = c->nb, groups = (2048 + nb - 1) / nb, reps = 3;
+  DevBuf<u64> buf;
+  if (!buf.alloc(&c->alloc, (size_t)groups * nb * N)) { set_error("NTT tuning: device allocation failed"); return SFHE_E_NOMEM; }
+  SFHE_HIP(hipMemset(buf.ptr, 0, (size_t)groups * nb * N * sizeof(u64)));
+  int pos[2 * kMaxBasis], pr[2 * kMaxBasis];
+  for (int r = 0; r < nb; ++r) { pos[r] = r; pr[r] = r; }
+  hipEvent_t e0, e1;
+  SFHE_HIP(hipEventCreate(&e0));
+  SFHE_HIP(hipEventCreate(&e1));
+  int rc = SFHE_OK;
+  for (int d = 0; d < 2 && !rc; ++d) {
+    double best = 1e30;
+    for (int v = 0; v < 4 && !rc; ++v) {
+      if (!ntt_variant_applies(c, v)) continue;
+      c->ntt_var[d] = v;
+      rc = launch_ntt(c, buf.ptr, groups, (int64_t)nb * N, nb, pos, pr, d == 1, 0);
+      if (!rc && hipEventRecord(e0, 0) != hipSuccess) rc = SFHE_E_DEVICE;
+      for (int x = 0; x < reps && !rc; ++x) rc = launch_ntt(c, buf.ptr, groups, (int64_t)nb * N, nb, pos, pr, d == 1, 0);
+      float ms = 0.f;
+      if (!rc && (hipEventRecord(e1, 0) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess)) {
+        rc = SFHE_E_DEVICE;
+        set_error("NTT tuning: event timing failed");
+      }
+      if (rc) break;
+      const double us = (double)ms * 1e3 / reps / (groups * nb);
+      c->ntt_us[d][v] = us;
+      if (us < best) { best = us; c->ntt_tuned[d] = v; }
+    }
+    c->ntt_var[d] = c->ntt_tuned[d];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
 static int gen_primes(sfhe_ctx* c, const std::vector<uint32_t>& bits) {
   const u64 two_n = 2 * (u64)c->N;
   for (size_t r = 0; r < bits.size(); ++r) {
@@ -514,9 +567,32 @@ int sfhe_ctx_create(const sfhe_params* p, const sfhe_device_hooks* hooks, sfhe_c
     set_error("hipEventCreate failed");
     return SFHE_E_DEVICE;
   }
+  rc = tune_ntt(c);
+  if (rc) {
+    delete c;
+    return rc;
+  }
   *out = c;
   return SFHE_OK;
   GUARD_END
+}
+
+int sfhe_ntt_tuning(const sfhe_ctx* c, int32_t inverse, int32_t* variant, double* us_per_row, int32_t cap) {
+  if (!c || !variant) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  const int d = inverse ? 1 : 0;
+  *variant = c->ntt_var[d];
+  if (us_per_row)
+    for (int v = 0; v < 4 && v < cap; ++v) us_per_row[v] = c->ntt_us[d][v];
+  return SFHE_OK;
+}
+
+int sfhe_set_ntt_variant(sfhe_ctx* c, int32_t inverse, int32_t variant) {
+  if (!c) { set_error("NULL context"); return SFHE_E_INVALID_ARG; }
+  const int d = inverse ? 1 : 0;
+  if (variant == -1) { c->ntt_var[d] = c->ntt_tuned[d]; return SFHE_OK; }
+  if (!ntt_variant_applies(c, variant)) { set_error("this NTT design does not apply to the ring"); return SFHE_E_UNSUPPORTED; }
+  c->ntt_var[d] = variant;
+  return SFHE_OK;
 }
 
 int sfhe_set_profiling(sfhe_ctx* c, int32_t on) {

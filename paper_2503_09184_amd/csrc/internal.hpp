@@ -14,6 +14,10 @@ namespace sfhe {
 
 constexpr int kMaxDigit = 8;   // primes per key-switching digit (alpha)
 
+// NTT designs: the register transform of the 2^14 kernels (N >= 2^14), and
+// the LDS transform with radix-16, radix-8 or radix-4 passes (N <= 2^14)
+enum { kNttRegister = 0, kNttRadix16 = 1, kNttRadix8 = 2, kNttRadix4 = 3 };
+
 // ---- constants of the base conversions, one block per (level, digit) ----
 // ModUp of digit j at level lev: y_i = [x_i (D/q_i)^-1]_{q_i} for the digit's
 // primes, then target e of the extended basis (data 0..lev, then special)
@@ -100,6 +104,12 @@ struct sfhe_ctx {
   sfhe::DevBuf<sfhe::ModDownConst> d_moddown;  // [L]
   sfhe::DevBuf<sfhe::RescaleConst> d_rescale;  // [L]
   sfhe::u64 cdt[sfhe::kCdtLen];
+  // NTT design per direction (0 forward, 1 inverse): one of sfhe::kNtt*,
+  // chosen by measurement when the context is made (tuned) and in use (var);
+  // ntt_us: measured microseconds per row of each design, -1 where it does
+  // not apply to the ring
+  int ntt_var[2] = {0, 0}, ntt_tuned[2] = {0, 0};
+  double ntt_us[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
   // keys
   bool has_keys = false;
   sfhe::DevBuf<sfhe::u64> d_s;           // secret, NTT domain [nb][N]

@@ -6,15 +6,27 @@
 
 namespace sfhe {
 
-template <bool INV, typename Ar>
+// storage position x of an N = 2^14 row -> the NTT index it holds (the
+// register-major order of the 2^14 transform kernels)
+__device__ __forceinline__ int ord14(int x) {
+  const int r = x >> 9, t = x & 511;
+  return ((r >> 4) << 13) | ((t & 63) << 4) | (((t >> 6) & 1) << 10) | (((t >> 8) & 1) << 11) |
+         (((t >> 7) & 1) << 12) | (r & 15);
+}
+
+// The LDS transform with passes of at most PMAX stages (radix 2^PMAX); at
+// N = 2^14 its NTT-domain side is read and written in the 2^14 kernels'
+// storage order, so that either design can serve a ring.
+template <bool INV, int PMAX, typename Ar>
 __device__ __forceinline__ void ntt_row(u64* p, const PrimeDev& P, int N, int logN, void* lds) {
   typedef typename Ar::Val Val;
   Val* sh = reinterpret_cast<Val*>(lds);
   const Ar ar(P, INV);
+  const bool perm = logN == 14;
   if (!INV) {
     int s0 = 0;
     while (s0 < logN) {
-      const int np = min(4, logN - s0);
+      const int np = min(PMAX, logN - s0);
       const u64* src = s0 == 0 ? p : nullptr;
       if (np == 4) fwd_pass<4>(ar, sh, src, N, logN, s0);
       else if (np == 3) fwd_pass<3>(ar, sh, src, N, logN, s0);
@@ -23,13 +35,13 @@ __device__ __forceinline__ void ntt_row(u64* p, const PrimeDev& P, int N, int lo
       __syncthreads();
       s0 += np;
     }
-    for (int x = threadIdx.x; x < N; x += blockDim.x) p[x] = ar.out_fwd(sh[lpos(x)]);
+    for (int x = threadIdx.x; x < N; x += blockDim.x) p[x] = ar.out_fwd(sh[lpos(perm ? ord14(x) : x)]);
   } else {
-    for (int x = threadIdx.x; x < N; x += blockDim.x) sh[lpos(x)] = ar.in(p[x]);
+    for (int x = threadIdx.x; x < N; x += blockDim.x) sh[lpos(perm ? ord14(x) : x)] = ar.in(p[x]);
     __syncthreads();
     int lt0 = 0;
     while (lt0 < logN) {
-      const int np = min(4, logN - lt0);
+      const int np = min(PMAX, logN - lt0);
       u64* dst = lt0 + np == logN ? p : nullptr;
       if (np == 4) inv_pass<4>(ar, sh, dst, P, N, logN, lt0);
       else if (np == 3) inv_pass<3>(ar, sh, dst, P, N, logN, lt0);
@@ -41,7 +53,7 @@ __device__ __forceinline__ void ntt_row(u64* p, const PrimeDev& P, int N, int lo
   }
 }
 
-template <bool INV>
+template <bool INV, int PMAX>
 __global__ void __launch_bounds__(1024) ntt_kernel(NttRows R, DevParams dp) {
   extern __shared__ u64 lds[];
   const int N = dp.N, logN = dp.logN;
@@ -50,9 +62,9 @@ __global__ void __launch_bounds__(1024) ntt_kernel(NttRows R, DevParams dp) {
   u64* p = R.base + g * R.bstride + (int64_t)R.pos[r] * N;
   const PrimeDev& P = dp.pr[R.prime[r]];
   if (P.q < (1ull << 42))
-    ntt_row<INV, NttFp>(p, P, N, logN, lds);
+    ntt_row<INV, PMAX, NttFp>(p, P, N, logN, lds);
   else
-    ntt_row<INV, NttInt>(p, P, N, logN, lds);
+    ntt_row<INV, PMAX, NttInt>(p, P, N, logN, lds);
 }
 
 
@@ -188,7 +200,8 @@ int launch_ntt(const sfhe_ctx* c, u64* base, int64_t batch, int64_t bstride, int
     SFHE_HIP(hipGetLastError());
     return SFHE_OK;
   }
-  if (c->logN == n14::kLogN) {
+  const int var = c->ntt_var[inverse ? 1 : 0];
+  if (c->logN == n14::kLogN && var == kNttRegister) {
     static bool attr14 = false;
     if (!attr14) {
       SFHE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&ntt14_kernel<false>),
@@ -205,19 +218,23 @@ int launch_ntt(const sfhe_ctx* c, u64* base, int64_t batch, int64_t bstride, int
     SFHE_HIP(hipGetLastError());
     return SFHE_OK;
   }
-  const int threads = N / 16 < 1024 ? N / 16 : 1024;
+  // the LDS designs: radix 16, 8 or 4 passes, one thread per 2^PMAX residues
+  const int pmax = var == kNttRadix8 ? 3 : var == kNttRadix4 ? 2 : 4;
+  const int threads = std::min(N >> pmax, 1024);
   const size_t lds = (size_t)(N + (N >> kPadShift)) * sizeof(u64);
-  static bool attr_done[2] = {false, false};
-  if (!attr_done[inverse ? 1 : 0]) {
-    const void* fn = inverse ? reinterpret_cast<const void*>(&ntt_kernel<true>)
-                             : reinterpret_cast<const void*>(&ntt_kernel<false>);
-    SFHE_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    attr_done[inverse ? 1 : 0] = true;
+  static bool attr_done = false;
+  if (!attr_done) {
+    const void* fns[6] = {reinterpret_cast<const void*>(&ntt_kernel<false, 4>), reinterpret_cast<const void*>(&ntt_kernel<true, 4>),
+                          reinterpret_cast<const void*>(&ntt_kernel<false, 3>), reinterpret_cast<const void*>(&ntt_kernel<true, 3>),
+                          reinterpret_cast<const void*>(&ntt_kernel<false, 2>), reinterpret_cast<const void*>(&ntt_kernel<true, 2>)};
+    for (const void* fn : fns) SFHE_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr_done = true;
   }
-  if (inverse)
-    hipLaunchKernelGGL(ntt_kernel<true>, dim3((unsigned)blocks), dim3(threads), lds, s, R, c->dp);
-  else
-    hipLaunchKernelGGL(ntt_kernel<false>, dim3((unsigned)blocks), dim3(threads), lds, s, R, c->dp);
+#define SFHE_NTT_LAUNCH(I, PM) hipLaunchKernelGGL((ntt_kernel<I, PM>), dim3((unsigned)blocks), dim3(threads), lds, s, R, c->dp)
+  if (pmax == 4) { if (inverse) SFHE_NTT_LAUNCH(true, 4); else SFHE_NTT_LAUNCH(false, 4); }
+  else if (pmax == 3) { if (inverse) SFHE_NTT_LAUNCH(true, 3); else SFHE_NTT_LAUNCH(false, 3); }
+  else { if (inverse) SFHE_NTT_LAUNCH(true, 2); else SFHE_NTT_LAUNCH(false, 2); }
+#undef SFHE_NTT_LAUNCH
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;
 }

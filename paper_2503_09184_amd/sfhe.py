@@ -32,7 +32,7 @@ EXPORTED = [
     "sfhe_server_create", "sfhe_server_submit", "sfhe_server_step", "sfhe_server_poll", "sfhe_server_status",
     "sfhe_server_destroy", "sfhe_plain_graph_create", "sfhe_plain_graph_launch", "sfhe_plain_graph_result",
     "sfhe_plain_graph_destroy", "sfhe_encrypt_matrix_slots", "sfhe_matmul_slots", "sfhe_export_stored",
-    "sfhe_rotate",
+    "sfhe_rotate", "sfhe_ntt_tuning", "sfhe_set_ntt_variant",
 ]
 
 PLAIN_LAUNCH = {"fused": 0, "per_product": 1}
@@ -131,6 +131,8 @@ def lib():
         L.sfhe_matmul_slots.argtypes = [vp, vp, vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
         L.sfhe_export_stored.argtypes = [vp, vp, i64, ctypes.POINTER(u64), ctypes.c_size_t, vp]
         L.sfhe_rotate.argtypes = [vp, i32, vp, vp, i32, i32, vp]
+        L.sfhe_ntt_tuning.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), i32]
+        L.sfhe_set_ntt_variant.argtypes = [vp, i32, i32]
         _lib = L
     return _lib
 
@@ -419,6 +421,21 @@ class Context:
                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), out.size,
                                     _stream_handle(stream)))
         return out
+
+    # ---- NTT designs ---------------------------------------------------------
+    NTT_DESIGNS = ("register", "radix16", "radix8", "radix4")
+
+    def ntt_tuning(self, inverse=False):
+        """(design in use, {design: measured us per row}) for one direction."""
+        v = ctypes.c_int32()
+        us = (ctypes.c_double * 4)()
+        _check(lib().sfhe_ntt_tuning(self._h, 1 if inverse else 0, ctypes.byref(v), us, 4))
+        return self.NTT_DESIGNS[v.value], {n: us[i] for i, n in enumerate(self.NTT_DESIGNS) if us[i] >= 0}
+
+    def set_ntt_design(self, inverse, design):
+        """Force a design by name, or None for the measured choice."""
+        v = -1 if design is None else self.NTT_DESIGNS.index(design)
+        _check(lib().sfhe_set_ntt_variant(self._h, 1 if inverse else 0, v))
 
     # ---- primitives on device buffers --------------------------------------
     def to_device(self, arr):
