@@ -540,6 +540,8 @@ def main():
         "legs": legs,
         "speedups": speedups,
         "roofline": roofline,
+        "ntt_designs": {d: {"used": ctx.ntt_tuning(d == "inverse")[0], "us_per_row": ctx.ntt_tuning(d == "inverse")[1]}
+                        for d in ("forward", "inverse")},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
