@@ -130,7 +130,7 @@ struct sfhe_ctx {
   // first use; 5^j mod 2N for j < 64; the slot-zero mask, NTT domain [L][N]
   sfhe::u64 key_seed = 0;
   std::map<sfhe::u64, sfhe::DevBuf<int>> auto_perm;
-  std::map<sfhe::u64, sfhe::DevBuf<sfhe::u64>> rot_keys;
+  std::map<sfhe::u64, sfhe::DevBuf<sfhe::u64>> rot_keys, rot_keys_s;   // keys and their Shoup companions
   sfhe::DevBuf<sfhe::u64> d_gal, d_mask0;
 };
 
@@ -296,6 +296,12 @@ int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLay
 int rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s,
                 u64* scratch = nullptr);
 bool keyswitch_rescale_n14_supported(const sfhe_ctx* c);
+// N = 2^14 only: (d0, d1) + KeySwitch(d2) with the given key (NTT domain
+// [dnum][2][nb][N] and its Shoup companions) for n inputs D[b] (stride dw
+// words; rows d0, d1, d2 of lev + 1 primes, NTT domain), written limb-major
+// to out (lev + 1 primes per poly)
+int keyswitch_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, const u64* key,
+                  const u64* key_s, hipStream_t s);
 // chunked out[oidx[o]] += sum of limb-major t[p] for p in seg[o] .. seg[o+1]-1 (rows [2][nl][N])
 int launch_segment_sum(const sfhe_ctx* c, int nl, const u64* t, u64* out, int64_t n_ct, const int* d_seg,
                        const int64_t* d_oidx, int64_t nout, hipStream_t s);

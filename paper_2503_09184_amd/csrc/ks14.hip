@@ -357,12 +357,14 @@ __global__ void __launch_bounds__(n14::kThreads, 4) ks14_k3a_kernel(Ks14Args a, 
 }
 
 // ---------------------------------------------------------------- Lift
-// grid (N / kEwSpan, 2 n lev): block row (b * 2 + p) * lev + i
-template <int ALPHA>
+// grid (N / kEwSpan, 2 n rows), rows = lev with the rescale (RS), else
+// lev + 1: block row (b * 2 + p) * rows + i.  Without the rescale w_i is
+// z_i P^-1 alone.
+template <int ALPHA, bool RS>
 __global__ void __launch_bounds__(kEwThreads) ks14_lift_kernel(Ks14Args a, DevParams dp) {
   const int x0 = blockIdx.x * kEwSpan + threadIdx.x;
-  const int lev = a.lev;
-  const int bp = blockIdx.y / lev, i = blockIdx.y % lev;   // bp = b * 2 + p
+  const int lev = a.lev, rows = RS ? lev : lev + 1;
+  const int bp = blockIdx.y / rows, i = blockIdx.y % rows;   // bp = b * 2 + p
   const u64 ql = dp.pr[lev].q;
   const PrimeDev& P = dp.pr[i];
   const u64 q = P.q;
@@ -386,18 +388,26 @@ __global__ void __launch_bounds__(kEwThreads) ks14_lift_kernel(Ks14Args a, DevPa
       z = add_mod(z, mul_shoup(y, cv[k], cs[k], q), q);
       above += y > ph[k];
     }
+    const u64 zp = sub_mod(mul_shoup(z, Pi, Pis, q), above, q);
+    if (!RS) {
+      o[m * kEwThreads] = zp;
+      continue;
+    }
     // centered lift of the last prime, reduced mod q_i
     const u64 c = rb[m * kEwThreads];
     const bool neg = c > (ql - 1) / 2;
     const u64 mag = neg ? ql - c : c;
     u64 r = mag < q ? mag : reduce_wide(U128{mag, 0}, q, P.mu_hi, P.mu_lo);
     r = (neg && r) ? q - r : r;
-    o[m * kEwThreads] = add_mod(sub_mod(mul_shoup(z, Pi, Pis, q), above, q), r, q);
+    o[m * kEwThreads] = add_mod(zp, r, q);
   }
 }
 
 // ---------------------------------------------------------------- K3b
-template <typename Ar>
+// RS: C_i = (acc_i P^-1 + d_i - NTT(w_i)) q_lev^-1 for i < lev; else the
+// key-switched sum itself, acc_i P^-1 + d_i - NTT(w_i) for i <= lev (limb-major
+// output rows only)
+template <typename Ar, bool RS>
 __device__ __forceinline__ void k3b_body(const Ks14Args& a, const DevParams& dp, const OutLayout& ol, int b, int p, int i,
                                          void* lds) {
   typedef typename Ar::Val Val;
@@ -407,12 +417,23 @@ __device__ __forceinline__ void k3b_body(const Ks14Args& a, const DevParams& dp,
   const Ar ar(P, false);
   const u64 Pi = a.md->Pinv[i], Pis = a.md->Pinv_s[i];
   Val v[32];
-  load_a(ar, v, a.w + (((int64_t)b * 2 + p) * lev + i) * kN, t);
+  const int rows = RS ? lev : lev + 1;
+  load_a(ar, v, a.w + (((int64_t)b * 2 + p) * rows + i) * kN, t);
   n14::forward(ar, v, reinterpret_cast<Val*>(lds), t);
   const u64* acc = a.accQ + (((int64_t)b * 2 + p) * a.nl + i) * kN;
   const u64* d = a.D + (int64_t)b * a.dw + (int64_t)(p * a.nl + i) * kN;
   const u64 qi = a.rs->qinv[i], qis = a.rs->qinv_s[i];
   const int tt = after(t, v[15], v[31]);
+  if (!RS) {
+    u64* dst = ol.base + (int64_t)b * ol.stride + ((int64_t)p * rows + i) * kN;
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      const int x = pos_c(tt, r);
+      dst[x] = sub_mod(add_mod(mul_shoup(acc[x], Pi, Pis, q), d[x], q), ar.fwd_res(v[r]), q);
+      group_fence<4>(r);
+    }
+    return;
+  }
   // the two destination layouts in loops of their own (a select of the
   // address inside one loop spills registers)
   if (ol.chunked) {
@@ -435,16 +456,17 @@ __device__ __forceinline__ void k3b_body(const Ks14Args& a, const DevParams& dp,
   }
 }
 
+template <bool RS>
 __global__ void __launch_bounds__(n14::kThreads, 4) ks14_k3b_kernel(Ks14Args a, OutLayout ol, DevParams dp) {
   extern __shared__ u64 lds[];
-  const int lev = a.lev;
-  const int b = blockIdx.x / (2 * lev);
-  const int rem = blockIdx.x % (2 * lev);
-  const int p = rem / lev, i = rem % lev;
+  const int rows = RS ? a.lev : a.lev + 1;
+  const int b = blockIdx.x / (2 * rows);
+  const int rem = blockIdx.x % (2 * rows);
+  const int p = rem / rows, i = rem % rows;
   if (dp.pr[i].q < (1ull << 42))
-    k3b_body<NttFp>(a, dp, ol, b, p, i, lds);
+    k3b_body<NttFp, RS>(a, dp, ol, b, p, i, lds);
   else
-    k3b_body<NttInt>(a, dp, ol, b, p, i, lds);
+    k3b_body<NttInt, RS>(a, dp, ol, b, p, i, lds);
 }
 
 template <int NT>
@@ -470,13 +492,14 @@ int launch_k2(const sfhe_ctx* c, const Ks14Args& a, int64_t n, size_t lds, hipSt
 }
 
 template <int ALPHA>
-int launch_ks14(sfhe_ctx* c, const Ks14Args& a, int ndig, OutLayout out, int64_t n, hipStream_t s) {
+int launch_ks14(sfhe_ctx* c, const Ks14Args& a, int ndig, OutLayout out, int64_t n, bool rescale, hipStream_t s) {
   const size_t lds = (size_t)n14::kLdsWords * sizeof(u64);
   static bool attr = false;
   if (!attr) {
-    const void* fns[3] = {reinterpret_cast<const void*>(&ks14_k1_kernel),
+    const void* fns[4] = {reinterpret_cast<const void*>(&ks14_k1_kernel),
                           reinterpret_cast<const void*>(&ks14_k3a_kernel<ALPHA>),
-                          reinterpret_cast<const void*>(&ks14_k3b_kernel)};
+                          reinterpret_cast<const void*>(&ks14_k3b_kernel<true>),
+                          reinterpret_cast<const void*>(&ks14_k3b_kernel<false>)};
     for (const void* f : fns) SFHE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
@@ -494,12 +517,20 @@ int launch_ks14(sfhe_ctx* c, const Ks14Args& a, int ndig, OutLayout out, int64_t
     default: rc = launch_k2<4>(c, a, n, lds, s); break;
   }
   if (rc) return rc;
+  if (!rescale) {   // the key-switched sum itself: no last-prime transform, no lift
+    hipLaunchKernelGGL((ks14_lift_kernel<ALPHA, false>), dim3(kN / kEwSpan, (unsigned)(n * 2 * nl)), dim3(kEwThreads), 0, s,
+                       a, c->dp);
+    SFHE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(ks14_k3b_kernel<false>, dim3((unsigned)(n * 2 * nl)), blk, lds, s, a, out, c->dp);
+    SFHE_HIP(hipGetLastError());
+    return SFHE_OK;
+  }
   hipLaunchKernelGGL(ks14_k3a_kernel<ALPHA>, dim3((unsigned)(n * 2)), blk, lds, s, a, c->dp);
   SFHE_HIP(hipGetLastError());
-  hipLaunchKernelGGL(ks14_lift_kernel<ALPHA>, dim3(kN / kEwSpan, (unsigned)(n * 2 * lev)), dim3(kEwThreads), 0, s, a,
+  hipLaunchKernelGGL((ks14_lift_kernel<ALPHA, true>), dim3(kN / kEwSpan, (unsigned)(n * 2 * lev)), dim3(kEwThreads), 0, s, a,
                      c->dp);
   SFHE_HIP(hipGetLastError());
-  hipLaunchKernelGGL(ks14_k3b_kernel, dim3((unsigned)(n * 2 * lev)), blk, lds, s, a, out, c->dp);
+  hipLaunchKernelGGL(ks14_k3b_kernel<true>, dim3((unsigned)(n * 2 * lev)), blk, lds, s, a, out, c->dp);
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;
 }
@@ -628,14 +659,16 @@ int rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, i
   return SFHE_OK;
 }
 
-int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s) {
+static int ks14_run(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, const u64* key,
+                    const u64* key_s, bool rescale, hipStream_t s) {
   if (n <= 0) return SFHE_OK;
   if (!keyswitch_rescale_n14_supported(c)) {
     set_error("fused key switch: N = 2^14, 1 <= alpha <= 4 and dnum <= 4 only");
     return SFHE_E_INVALID_ARG;
   }
-  if (lev < 1) { set_error("rescale: level 0 has no prime to drop"); return SFHE_E_LEVEL; }
-  if (!c->d_rlk_s.ptr) { set_error("keygen first"); return SFHE_E_STATE; }
+  if (rescale && lev < 1) { set_error("rescale: level 0 has no prime to drop"); return SFHE_E_LEVEL; }
+  if (!rescale && out.chunked) { set_error("key switch: limb-major output only"); return SFHE_E_INVALID_ARG; }
+  if (!key || !key_s) { set_error("keygen first"); return SFHE_E_STATE; }
   const int nl = lev + 1, ne = nl + c->alpha;
   int next = 0, ndig = 0;
   for (int j = 0; j < c->dnum; ++j) {
@@ -645,7 +678,7 @@ int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLay
     ++ndig;
   }
   // grid limits of the element-wise kernels (rows in y)
-  if (n * ne > 0x7FFFFFFF || n * std::max(std::max(next, 2 * lev), nl) > 65535) {
+  if (n * ne > 0x7FFFFFFF || n * std::max(std::max(next, 2 * nl), nl) > 65535) {
     set_error("key switch: slice too large");
     return SFHE_E_INVALID_ARG;
   }
@@ -653,7 +686,7 @@ int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLay
   if (!y.alloc(&c->alloc, (size_t)n * nl * kN) || !ext.alloc(&c->alloc, (size_t)n * next * kN) ||
       !accQ.alloc(&c->alloc, (size_t)n * 2 * nl * kN) || !part.alloc(&c->alloc, (size_t)n * 2 * c->alpha * kN) ||
       !yP.alloc(&c->alloc, (size_t)n * 2 * c->alpha * kN) || !r.alloc(&c->alloc, (size_t)n * 2 * kN) ||
-      !w.alloc(&c->alloc, (size_t)n * 2 * lev * kN)) {
+      !w.alloc(&c->alloc, (size_t)n * 2 * (rescale ? lev : nl) * kN)) {
     set_error("key switch: device allocation failed");
     return SFHE_E_NOMEM;
   }
@@ -668,8 +701,8 @@ int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLay
   a.yP = yP.ptr;
   a.r = r.ptr;
   a.w = w.ptr;
-  a.rlk = c->d_rlk.ptr;
-  a.rlk_s = c->d_rlk_s.ptr;
+  a.rlk = key;
+  a.rlk_s = key_s;
   a.mu = c->d_modup.ptr + (size_t)lev * c->dnum;
   a.md = c->d_moddown.ptr + lev;
   a.rs = c->d_rescale.ptr + lev;
@@ -677,11 +710,20 @@ int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLay
   a.nl = nl;
   a.n = (int)n;
   switch (c->alpha) {
-    case 1: return launch_ks14<1>(c, a, ndig, out, n, s);
-    case 2: return launch_ks14<2>(c, a, ndig, out, n, s);
-    case 3: return launch_ks14<3>(c, a, ndig, out, n, s);
-    default: return launch_ks14<4>(c, a, ndig, out, n, s);
+    case 1: return launch_ks14<1>(c, a, ndig, out, n, rescale, s);
+    case 2: return launch_ks14<2>(c, a, ndig, out, n, rescale, s);
+    case 3: return launch_ks14<3>(c, a, ndig, out, n, rescale, s);
+    default: return launch_ks14<4>(c, a, ndig, out, n, rescale, s);
   }
+}
+
+int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s) {
+  return ks14_run(c, lev, D, dw, out, n, c->d_rlk.ptr, c->d_rlk_s.ptr, true, s);
+}
+
+int keyswitch_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, const u64* key,
+                  const u64* key_s, hipStream_t s) {
+  return ks14_run(c, lev, D, dw, out, n, key, key_s, false, s);
 }
 
 }  // namespace sfhe

@@ -139,6 +139,24 @@ __global__ void automorphism_kernel(const u64* in, int64_t istride, int nl, cons
   t1[row * N + t] = ci[(int64_t)(nl + i) * N + src];
 }
 
+// D[x] = (c0(X^g), 0, c1(X^g)), rows of nl primes, stride 3 nl N: the input
+// of the fused key switch (NTT domain)
+__global__ void automorphism_d_kernel(const u64* in, int64_t istride, int nl, const int* perm, u64* D, int64_t n,
+                                      int N) {
+  const int64_t row = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;   // (x, prime)
+  if (row >= n * nl) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const int64_t x = row / nl;
+  const int i = (int)(row % nl);
+  const int src = perm[t];
+  const u64* ci = in + x * istride;
+  u64* d = D + x * (int64_t)3 * nl * N;
+  d[(int64_t)i * N + t] = ci[(int64_t)i * N + src];
+  d[(int64_t)(nl + i) * N + t] = 0;
+  d[(int64_t)(2 * nl + i) * N + t] = ci[(int64_t)(nl + i) * N + src];
+}
+
 // x[b][p][i] *= mask[i] (NTT domain, pointwise) for n ciphertexts of nl primes
 __global__ void mask_kernel(u64* x, int64_t stride, int nl, const u64* mask, int64_t n, DevParams dp) {
   const int N = dp.N;
@@ -227,8 +245,23 @@ const u64* rotation_key(sfhe_ctx* c, u64 g) {
     set_error("rotation key: kernel failed");
     return nullptr;
   }
+  // Shoup companions floor(k 2^64 / q) of every key word, for the fused key
+  // switch (computed once, on the host)
+  const size_t nk = (size_t)dnum * 2 * nb * N;
+  std::vector<u64> h(nk);
+  DevBuf<u64> ks;
+  if (!ks.alloc(&c->alloc, nk) || hipMemcpy(h.data(), key.ptr, nk * sizeof(u64), hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("rotation key: allocation or copy failed");
+    return nullptr;
+  }
+  for (size_t w = 0; w < nk; ++w) h[w] = hostmath::shoup(h[w], c->primes[(w / N) % nb]);
+  if (hipMemcpy(ks.ptr, h.data(), nk * sizeof(u64), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("rotation key: copy failed");
+    return nullptr;
+  }
   const u64* p = key.ptr;
   c->rot_keys.emplace(g, std::move(key));
+  c->rot_keys_s.emplace(g, std::move(ks));
   return p;
 }
 
@@ -254,6 +287,25 @@ int rotate_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, int64_t r
   const int* perm = automorphism_table(c, g);
   const u64* key = perm ? rotation_key(c, g) : nullptr;
   if (!key) return SFHE_E_NOMEM;
+  if (keyswitch_rescale_n14_supported(c)) {
+    // N = 2^14: the fused key switch, in slices within its grid limits
+    const u64* key_s = c->rot_keys_s.at(g).ptr;
+    const int64_t slice = std::min<int64_t>(n, 1024);
+    DevBuf<u64> D;
+    if (!D.alloc(&c->alloc, (size_t)slice * 3 * nl * N)) { set_error("rotate: device allocation failed"); return SFHE_E_NOMEM; }
+    for (int64_t x0 = 0; x0 < n; x0 += slice) {
+      const int64_t m = std::min(slice, n - x0);
+      unsigned gy, gz;
+      grid_rows(m * nl, gy, gz);
+      hipLaunchKernelGGL(automorphism_d_kernel, dim3((N + 255) / 256, gy, gz), dim3(256), 0, s, in + x0 * istride, istride,
+                         nl, perm, D.ptr, m, N);
+      SFHE_HIP(hipGetLastError());
+      const int rc = keyswitch_n14(c, lev, D.ptr, (int64_t)3 * nl * N, OutLayout{out + x0 * ostride, ostride, false, 0, 0},
+                                   m, key, key_s, s);
+      if (rc) return rc;
+    }
+    return SFHE_OK;
+  }
   DevBuf<u64> t1;
   if (!t1.alloc(&c->alloc, (size_t)n * nl * N)) { set_error("rotate: device allocation failed"); return SFHE_E_NOMEM; }
   unsigned gy, gz;

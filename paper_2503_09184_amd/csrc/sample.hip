@@ -141,6 +141,7 @@ int keygen_device(sfhe_ctx* c, u64 seed, hipStream_t s) {
   const int N = c->N, nb = c->nb, dnum = c->dnum;
   c->key_seed = seed;
   c->rot_keys.clear();
+  c->rot_keys_s.clear();
   if (!c->d_s.alloc(&c->alloc, (size_t)nb * N) || !c->d_rlk.alloc(&c->alloc, (size_t)dnum * 2 * nb * N)) {
     set_error("keygen: device allocation failed");
     return SFHE_E_NOMEM;
