@@ -32,6 +32,10 @@
 // whose sums over primes would not fit beside a row in registers, are
 // element-wise kernels of their own.
 //
+// Without the rescale (a rotation's key switch: D = (c0, 0, c1) after the
+// automorphism) K3a is skipped, the lift gives w_i = z_i P^-1 for every
+// i <= lev and K3b writes acc_i P^-1 + d_i - NTT(w_i) itself.
+//
 // Each transform block has 512 threads and 66.5 KiB of LDS, two blocks per
 // CU.  NTT-domain rows are in the register-major order pos_c of ntt14.hpp,
 // the private coefficient rows (y, ext, yP, r, w) in pos_a, so every access
