@@ -1825,12 +1825,19 @@ static int unpack_values(sfhe_ctx* c, const sfhe_mat* src, const std::vector<int
       std::vector<int64_t> es(vs.begin() + x0, vs.begin() + x0 + n), ed(es);
       for (auto& e : es) e /= cs;
       if (!upload(c, d_src, es, s) || !upload(c, d_dst, ed, s)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
-      int rc = launch_from_chunked(c, src->data.ptr, src->n_ct, nl, n, d_src.ptr, 0, a.ptr, w, s);
+      int rc = SFHE_OK;
       const u64* res = a.ptr;
-      if (!rc && o) {
-        rc = rotate_batch(c, lev, a.ptr, w, o, b.ptr, w, n, s);
+      if (o && keyswitch_rescale_n14_supported(c)) {   // the rotation reads the chunks in place
+        rc = rotate_chunked(c, lev, src->data.ptr, src->n_ct, d_src.ptr, o, b.ptr, w, n, s);
         res = b.ptr;
         rotations += n;
+      } else {
+        rc = launch_from_chunked(c, src->data.ptr, src->n_ct, nl, n, d_src.ptr, 0, a.ptr, w, s);
+        if (!rc && o) {
+          rc = rotate_batch(c, lev, a.ptr, w, o, b.ptr, w, n, s);
+          res = b.ptr;
+          rotations += n;
+        }
       }
       if (!rc) rc = launch_to_chunked(c, res, w, nl, n, dst->data.ptr, dst->n_ct, d_dst.ptr, 0, s);
       if (rc) return rc;
@@ -1857,7 +1864,8 @@ static int finish_products(sfhe_ctx* c, int lev, u64* x, int64_t n, int roff, co
     set_error("device allocation failed");
     rc = SFHE_E_NOMEM;
   }
-  if (!rc) rc = rescale_batch(c, lev, x, wx, OutLayout{y.ptr, wy, false, 0, 0}, n, s);
+  const OutLayout oy{y.ptr, wy, false, 0, 0};
+  if (!rc) rc = c->logN == 14 ? rescale_n14(c, lev, x, wx, oy, n, s) : rescale_batch(c, lev, x, wx, oy, n, s);
   const u64* res = y.ptr;
   if (!rc && roff) {
     rc = rotate_batch(c, lev - 1, y.ptr, wy, -(int64_t)roff, z.ptr, wy, n, s);

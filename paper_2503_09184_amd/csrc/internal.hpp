@@ -324,6 +324,10 @@ int prepare_rotations(sfhe_ctx* c, const std::vector<int64_t>& offsets);
 // slots into out (stride ostride); in and out must not overlap
 int rotate_batch(sfhe_ctx* c, int lev, const u64* in, int64_t istride, int64_t r, u64* out, int64_t ostride,
                  int64_t n, hipStream_t s);
+// N = 2^14: the same for n <= 1024 ciphertexts d_elem[x] of a chunked matrix
+// (top level, n_ct ciphertexts), read in place
+int rotate_chunked(sfhe_ctx* c, int lev, const u64* src, int64_t n_ct, const int64_t* d_elem, int64_t r, u64* out,
+                   int64_t ostride, int64_t n, hipStream_t s);
 // encrypt chunks x0 .. x0 + count - 1 of nvals stored values (slots per
 // chunk) into tmp[count][2][L][N], NTT domain
 int encrypt_slots(sfhe_ctx* c, u64* tmp, int64_t count, int64_t x0, const double* d_vals, int64_t nvals, int slots,

@@ -157,6 +157,23 @@ __global__ void automorphism_d_kernel(const u64* in, int64_t istride, int nl, co
   d[(int64_t)(2 * nl + i) * N + t] = ci[(int64_t)(nl + i) * N + src];
 }
 
+// the same, reading ciphertext elem[x] of a chunked matrix (n_ct ciphertexts)
+__global__ void automorphism_dc_kernel(const u64* src, int64_t n_ct, const int64_t* elem, int nl, const int* perm,
+                                       u64* D, int64_t n, int N) {
+  const int64_t row = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;   // (x, prime)
+  if (row >= n * nl) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const int64_t x = row / nl;
+  const int i = (int)(row % nl);
+  const int sp = perm[t];
+  const int64_t e = elem[x];
+  u64* d = D + x * (int64_t)3 * nl * N;
+  d[(int64_t)i * N + t] = src[chunk_index(e, 0, i, sp, n_ct, N >> 6)];
+  d[(int64_t)(nl + i) * N + t] = 0;
+  d[(int64_t)(2 * nl + i) * N + t] = src[chunk_index(e, 1, i, sp, n_ct, N >> 6)];
+}
+
 // x[b][p][i] *= mask[i] (NTT domain, pointwise) for n ciphertexts of nl primes
 __global__ void mask_kernel(u64* x, int64_t stride, int nl, const u64* mask, int64_t n, DevParams dp) {
   const int N = dp.N;
@@ -323,6 +340,27 @@ int slot_table(sfhe_ctx* c) {
   if (!c->d_gal.alloc(&c->alloc, gal.size())) { set_error("slot table: device allocation failed"); return SFHE_E_NOMEM; }
   SFHE_HIP(hipMemcpy(c->d_gal.ptr, gal.data(), gal.size() * sizeof(u64), hipMemcpyHostToDevice));
   return SFHE_OK;
+}
+
+int rotate_chunked(sfhe_ctx* c, int lev, const u64* src, int64_t n_ct, const int64_t* d_elem, int64_t r, u64* out,
+                   int64_t ostride, int64_t n, hipStream_t s) {
+  if (n <= 0) return SFHE_OK;
+  if (!keyswitch_rescale_n14_supported(c)) { set_error("rotate_chunked: N = 2^14 only"); return SFHE_E_INVALID_ARG; }
+  const int N = c->N, nl = lev + 1;
+  const u64 g = galois_element(c, r);
+  const int* perm = automorphism_table(c, g);
+  const u64* key = perm ? rotation_key(c, g) : nullptr;
+  if (!key) return SFHE_E_NOMEM;
+  const u64* key_s = c->rot_keys_s.at(g).ptr;
+  if (n > 1024) { set_error("rotate_chunked: at most 1024 ciphertexts per call"); return SFHE_E_INVALID_ARG; }
+  DevBuf<u64> D;
+  if (!D.alloc(&c->alloc, (size_t)n * 3 * nl * N)) { set_error("rotate: device allocation failed"); return SFHE_E_NOMEM; }
+  unsigned gy, gz;
+  grid_rows(n * nl, gy, gz);
+  hipLaunchKernelGGL(automorphism_dc_kernel, dim3((N + 255) / 256, gy, gz), dim3(256), 0, s, src, n_ct, d_elem, nl, perm,
+                     D.ptr, n, N);
+  SFHE_HIP(hipGetLastError());
+  return keyswitch_n14(c, lev, D.ptr, (int64_t)3 * nl * N, OutLayout{out, ostride, false, 0, 0}, n, key, key_s, s);
 }
 
 int encrypt_slots(sfhe_ctx* c, u64* tmp, int64_t count, int64_t x0, const double* d_vals, int64_t nvals, int slots,

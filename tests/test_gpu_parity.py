@@ -336,6 +336,26 @@ def test_sweep_n8192_sampled_outputs_and_cross_encoding(torch_cuda, sparsity):
         assert np.array_equal(o, cts[n]), sample[n]
 
 
+@pytest.mark.parametrize("sparsity,sched", [(0.25, "lazy"), (0.75, "lazy"), (0.5, "per_product")])
+def test_sweep_n8192_all_outputs(torch_cuda, sparsity, sched):
+    """N = 2^13, 64 x 64 x 64 (CSR): every output bit-exact against the oracle
+    (LAZY: all 4096; PER_PRODUCT, whose oracle relinearises every product:
+    the 1024 outputs of rows 0-15), and decrypted within 1e-6 of the fp64
+    product."""
+    P = W.PARAMS["sweep_n8192"]
+    ctx, orc = pair(P, W.key_seed(2))
+    A, B = W.operands(64, 64, 64, sparsity, W.workload_seed(2))
+    sa, sb = W.enc_seed(2, 0), W.enc_seed(2, 1)
+    note("sweep all outputs %.2f %s" % (sparsity, sched))
+    C = ctx.matmul(ctx.encrypt(A, "csr", sa, 0), ctx.encrypt(B, "dense", sb, 1), sched)
+    assert np.max(np.abs(ctx.decrypt(C) - A @ B)) < 1e-6
+    rows = 64 if sched == "lazy" else 16
+    outs = [(i, j) for i in range(rows) for j in range(64)]
+    cts, _, _ = orc.matmul(A, B, "csr", sched, sa, sb, outputs=outs, threads=_threads(), decrypt=False)
+    for n, (i, j) in enumerate(outs):
+        assert np.array_equal(ctx.export_ct(C, i, j), cts[n]), (i, j)
+
+
 # ---------------------------------------------------------------- full size
 def _threads():
     import os
