@@ -136,3 +136,29 @@ def test_matmul_slots_errors(torch_cuda):
     with pytest.raises(sfhe.SfheError) as e:
         small.matmul_slots(small.encrypt_slots(A, "csr", 2, 1, 0), small.encrypt_slots(B, "dense", 2, 2, 1), "lazy")
     assert e.value.code == -4
+
+
+def test_matmul_slots_benchmarked_size(torch_cuda):
+    """The benchmarked product with 8 values per ciphertext (128 x 128 x 128,
+    N = 2^14, CSR at 50%, LAZY, the same calls as the bench leg): every one
+    of the 16384 outputs decrypts within 1e-6 of the fp64 product, the counts
+    of products, rotations and result ciphertexts are the method's, and the
+    result ciphertexts of a repeated call are identical."""
+    ctx, _ = pair(W.PARAMS["realistic_n16384"], W.key_seed(3))
+    A, B = W.operands(128, 128, 128, 0.5, W.workload_seed(3))
+    sa, sb = W.enc_seed(3, 0), W.enc_seed(3, 1)
+    note("matmul slots 128^3 c=8")
+    EA = ctx.encrypt_slots(A, "csr", 8, sa, 0)
+    EB = ctx.encrypt_slots(B, "dense", 8, sb, 1)
+    C = ctx.matmul_slots(EA, EB, "lazy")
+    st = ctx.last_stats()
+    nnz = int(np.count_nonzero(A))
+    assert st.products == nnz * 128
+    # rotations: stored values off slot 0 (A's nonzeros, all of B), then one per output off slot 0
+    rot = (nnz - (nnz + 7) // 8) + (128 * 128 - 128 * 128 // 8) + (128 * 128 - 128 * 128 // 8)
+    assert st.keyswitches == 128 * 128 + rot
+    assert C.info().n_ciphertexts == 2048
+    assert np.max(np.abs(ctx.decrypt(C) - A @ B)) < 1e-6
+    C2 = ctx.matmul_slots(EA, EB, "lazy")
+    for x in (0, 777, 2047):
+        assert np.array_equal(ctx.export_stored(C, x), ctx.export_stored(C2, x))
