@@ -24,6 +24,11 @@
  *
  * The library plays both parties for benchmarking: the secret key lives in
  * the context and never leaves it.
+ *
+ * Concurrency: a context and the handles made from it are used by one host
+ * thread at a time (the context holds the last call's statistics, event
+ * pool and key caches).  Work of one context may be enqueued on several
+ * streams; results are not ordered across streams by the library.
  */
 #ifndef SFHE_H
 #define SFHE_H
@@ -209,7 +214,10 @@ int sfhe_encrypt_matrix_slots(sfhe_ctx* ctx, const double* vals, int32_t rows, i
  * ciphertext, level L - 3, scale scale_A scale_B 2^log2_scale / (q_{L-1}
  * q_{L-2}); chunks no product reaches stay trivial zeros.  Rotation keys
  * (for offsets -(c-1) .. c-1) are generated on first use and kept by the
- * context.  sfhe_last_stats: products, relinearisations plus rotations (as
+ * context; generating them synchronises the device.  The call holds
+ * temporary device memory for A's visited values and all of B as
+ * one-value ciphertexts (top level) besides the lazy sums of the product.
+ * sfhe_last_stats: products, relinearisations plus rotations (as
  * keyswitches), result ciphertexts and the device time of the whole call. */
 int sfhe_matmul_slots(sfhe_ctx* ctx, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched,
                       void* stream, sfhe_mat** C);
