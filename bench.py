@@ -211,18 +211,18 @@ def ctpt_leg(torch, sfhe, W, count=32):
             "host_wall_s": wall, "per_product_launch_sample": sample}
 
 
-def slots_leg(ctx, torch, A, Bm, sa, sb, chunk):
+def slots_leg(ctx, torch, A, Bm, sa, sb, chunk, sched="lazy"):
     """Algorithm 1 with chunks of `chunk` values per ciphertext (rotations into
-    slot 0, the slot-0 mask, rotation to the output slot), LAZY, on the
-    headline operands: one untimed call (it builds the rotation keys), then
-    one timed call."""
+    slot 0, the slot-0 mask, rotation to the output slot) on the given
+    operands: one untimed call (it builds the rotation keys), then one timed
+    call."""
     EA = ctx.encrypt_slots(A, "csr", chunk, sa, 0)
     EB = ctx.encrypt_slots(Bm, "dense", chunk, sb, 1)
     torch.cuda.synchronize()
-    ctx.matmul_slots(EA, EB, "lazy").close()
+    ctx.matmul_slots(EA, EB, sched).close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    C = ctx.matmul_slots(EA, EB, "lazy")
+    C = ctx.matmul_slots(EA, EB, sched)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
     st = ctx.last_stats()
@@ -486,6 +486,12 @@ def main():
         log("slots8: %.1f ms, %d products, %d key switches and rotations, err %.2e" %
             (legs["slots8_lazy_csr_50"]["ms"], legs["slots8_lazy_csr_50"]["products"],
              legs["slots8_lazy_csr_50"]["keyswitches_and_rotations"], legs["slots8_lazy_csr_50"]["max_abs_err_vs_fp64"]))
+        # both schedules on a 32-row slice of the same operands (Algorithm 1's
+        # own order rotates every product to its output slot: 8x the rotations)
+        for sched in ("lazy", "per_product"):
+            name = "slots8_%s_csr_50_32x128x128" % sched
+            legs[name] = slots_leg(ctx, torch, A[:32], Bm, sa, sb, 8, sched)
+            log("%s: %.1f ms, %d products" % (name, legs[name]["ms"], legs[name]["products"]))
     if run("serve"):
         log("serving: Poisson arrivals of encrypted MLP-layer requests")
         legs["serving"] = serving_leg(torch, sfhe, W)
@@ -514,6 +520,9 @@ def main():
         speedups["sparse90_over_dense"] = legs["lazy_dense_90_operands"]["ms"] / legs["lazy_csr_90"]["ms"]
     if "per_product_csr_50" in legs:
         speedups["lazy_over_per_product_50"] = legs["per_product_csr_50"]["ms"] / ms
+    if "slots8_per_product_csr_50_32x128x128" in legs:
+        speedups["slots8_lazy_over_per_product_32x128x128"] = (legs["slots8_per_product_csr_50_32x128x128"]["ms"] /
+                                                               legs["slots8_lazy_csr_50_32x128x128"]["ms"])
     if "lazy_csr_both_50" in legs and "lazy_dense_same_operands" in legs:
         # the dense schedule's time does not depend on the values
         speedups["both_sparse50_over_dense"] = legs["lazy_dense_same_operands"]["ms"] / legs["lazy_csr_both_50"]["ms"]
