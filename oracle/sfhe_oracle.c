@@ -29,9 +29,10 @@
  *   R3  randomness from SplitMix64 used as a counter-based generator, one
  *       stream per (seed, tag, fields); see key_of() and word().
  *   R4  hybrid key switching with contiguous digits of alpha data primes,
- *       uncentered fast base conversion in ModUp, centered in ModDown (the
- *       special part's residues taken in (-p_k/2, p_k/2)), so that the
- *       division by P carries no bias.
+ *       centered fast base conversions in ModUp and ModDown (the converted
+ *       residues taken in (-q/2, q/2)): ModDown's division by P then carries
+ *       no bias, and ModUp commutes with X -> X^g (it maps -x to -x), so a
+ *       digit raised once serves every rotation of a ciphertext.
  *   R5  rescale by the last prime with the centered lift (exact rounding).
  *   R6  outputs with no product are trivial zero ciphertexts.
  *   R7  NTT-domain index k holds a(psi^(2*brv(k)+1)), psi the smallest
@@ -434,8 +435,9 @@ static int ext_basis(const orc_ctx* c, int lev, int* eb) {
 }
 
 /* ModUp of digit j: the residues, over the extended basis, of the integer
- * x = sum_{i in D_j} [d2_i * (D_j/q_i)^-1]_{q_i} * (D_j/q_i)  (uncentered fast
- * base conversion), which is congruent to d2 modulo every prime of the digit.
+ * x = sum_{i in D_j} [d2_i * (D_j/q_i)^-1]_{q_i} * (D_j/q_i) with each
+ * [.]_{q_i} taken in (-q_i/2, q_i/2) (centered fast base conversion, R4),
+ * which is congruent to d2 modulo every prime of the digit.
  * in: d2[lev+1][N] coefficient domain; out: x[lev+1+alpha][N] coefficient domain. */
 void orc_modup(const orc_ctx* c, int lev, int j, const u64* d2, u64* x) {
   int N = c->N, nl = lev + 1, eb[ORC_MAXB];
@@ -455,9 +457,13 @@ void orc_modup(const orc_ctx* c, int lev, int j, const u64* d2, u64* x) {
     if (r >= lo && r < hi) { memcpy(xo, d2 + (size_t)r * N, sizeof(u64) * N); continue; }
     memset(xo, 0, sizeof(u64) * N);
     for (int i = lo; i < hi; i++) {
-      u64 Dq = 1;                                         /* [D_j/q_i]_t */
+      u64 qi = c->q[i], Dq = 1;                           /* [D_j/q_i]_t */
       for (int i2 = lo; i2 < hi; i2++) if (i2 != i) Dq = mulm(Dq, c->q[i2] % qt, qt);
-      for (int t = 0; t < N; t++) xo[t] = addm(xo[t], mulm(y[(size_t)i * N + t] % qt, Dq, qt), qt);
+      for (int t = 0; t < N; t++) {
+        u64 yv = y[(size_t)i * N + t];
+        i64 yc = yv > (qi - 1) / 2 ? -(i64)(qi - yv) : (i64)yv;   /* centered representative */
+        xo[t] = addm(xo[t], mulm(redi(yc, qt), Dq, qt), qt);
+      }
     }
   }
   free(y);

@@ -219,6 +219,13 @@ static int build_tables(sfhe_ctx* c) {
           m.conv_s[i - m.lo][e] = shoup(v, qe);
         }
       }
+      for (int e = 0; e < m.ne; ++e) {
+        const u64 qe = c->primes[m.basis[e]];
+        u64 v = 1;  // D mod q_e
+        for (int i2 = m.lo; i2 < m.hi; ++i2) v = mulmod(v, c->primes[i2] % qe, qe);
+        m.dmod[e] = v;
+        m.dmod_s[e] = shoup(v, qe);
+      }
     }
     ModDownConst& d = md[lev];
     for (int k = 0; k < al; ++k) {

@@ -20,8 +20,9 @@ enum { kNttRegister = 0, kNttRadix16 = 1, kNttRadix8 = 2, kNttRadix4 = 3 };
 
 // ---- constants of the base conversions, one block per (level, digit) ----
 // ModUp of digit j at level lev: y_i = [x_i (D/q_i)^-1]_{q_i} for the digit's
-// primes, then target e of the extended basis (data 0..lev, then special)
-// gets sum_i y_i [D/q_i]_{e}.
+// primes, taken in (-q_i/2, q_i/2), then target e of the extended basis (data
+// 0..lev, then special) gets sum_i y_i [D/q_i]_{e}: the uncentered sum minus
+// c [D]_e, c the count of y_i above (q_i - 1) / 2.
 struct ModUpConst {
   int lo, hi;                          // digit primes lo..hi-1 (clipped to the level)
   int ne;                              // extended basis size = lev + 1 + alpha
@@ -29,6 +30,7 @@ struct ModUpConst {
   u64 inv[kMaxDigit], inv_s[kMaxDigit];
   u64 inv_n[kMaxDigit], inv_n_s[kMaxDigit];   // inv * N^-1 mod q_i (applied with an inverse NTT)
   u64 conv[kMaxDigit][kMaxBasis], conv_s[kMaxDigit][kMaxBasis];
+  u64 dmod[kMaxBasis], dmod_s[kMaxBasis];     // [D]_e and its Shoup companion
 };
 // ModDown at level lev: y_k = [acc_{p_k} (P/p_k)^-1]_{p_k} taken in
 // (-p_k/2, p_k/2) (the centered conversion: y_k above (p_k - 1)/2 stands for

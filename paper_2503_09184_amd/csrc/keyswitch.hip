@@ -3,10 +3,10 @@
 //
 // Key switching of a degree-2 part d2 at level lev (Q = q_0..q_lev, special
 // primes P = p_0..p_{alpha-1}, digits of alpha consecutive data primes):
-//   ModUp     per digit j, the uncentered fast base conversion of [d2]_{D_j}
+//   ModUp     per digit j, the centered fast base conversion of [d2]_{D_j}
 //             to every other prime of Q and P, then the NTT of those rows;
 //   inner     acc_p = sum_j x_j * rlk_j.p over Q u P (NTT domain);
-//   ModDown   the special rows of acc back to coefficients, their uncentered
+//   ModDown   the special rows of acc back to coefficients, their centered
 //             fast base conversion to Q, NTT, and (acc_i - z_i) P^-1.
 // Rescale drops q_lev with exact rounding: r = centered lift of the last row,
 // c_i' = (c_i - r) q_lev^-1.  Base conversions run in the coefficient domain,
@@ -32,11 +32,13 @@ __global__ void modup_kernel(const u64* d2c, int nl, const ModUpConst* __restric
   if (t >= N) return;
   const int lo = mc->lo, hi = mc->hi, ne = mc->ne;
   u64 y[kMaxDigit];
+  u64 neg = 0;   // centered conversion: residues above (q_i - 1) / 2 stand for y_i - q_i
 #pragma unroll
   for (int i = 0; i < kMaxDigit; ++i) {
     if (lo + i < hi) {
       const u64 qi = dp.pr[lo + i].q;
       y[i] = mul_shoup(d2c[(b * nl + lo + i) * N + t], mc->inv[i], mc->inv_s[i], qi);
+      neg += y[i] > (qi - 1) / 2;
     } else {
       y[i] = 0;
     }
@@ -50,7 +52,7 @@ __global__ void modup_kernel(const u64* d2c, int nl, const ModUpConst* __restric
     for (int i = 0; i < kMaxDigit; ++i) {
       if (lo + i < hi) acc = add_mod(acc, mul_shoup(y[i], mc->conv[i][e], mc->conv_s[i][e], qe), qe);
     }
-    xbuf[(b * ne + e) * N + t] = acc;
+    xbuf[(b * ne + e) * N + t] = sub_mod(acc, mul_shoup(neg, mc->dmod[e], mc->dmod_s[e], qe), qe);
   }
 }
 

@@ -9,8 +9,9 @@
 //
 //  K1 (b, i)    y_i = [iNTT(d2_i) (D_j/q_i)^-1]_{q_i}: ModUp's pre-scale,
 //               with N^-1 folded into the constant.
-//  BConv (b, j, e, x)  ext_{j,e} = sum_{i in D_j} y_i [D_j/q_i]_e for every
-//               digit j and every prime e outside it (element-wise).
+//  BConv (b, j, e, x)  ext_{j,e} = sum_{i in D_j} y_i [D_j/q_i]_e (y_i
+//               centered) for every digit j and every prime e outside it
+//               (element-wise).
 //  K2 (b, e)    x_j = NTT(ext_{j,e}) for the digits j not holding e, and the
 //               key products acc_p = sum_j x_j rlk_j,p[e] (+ d2_e rlk_own,p[e]
 //               when e is a data prime of digit own).  Data prime: acc_p is
@@ -24,8 +25,8 @@
 //  K3b (b, p, i), i < lev:  C_i = (acc_i P^-1 + d_i - NTT(w_i)) q_lev^-1.
 //
 // Every identity is exact modular arithmetic, so the result is the same, bit
-// for bit, as key switching with uncentered fast base conversions followed
-// by an exactly rounded rescale.  Per output this takes 4 L + 4 + (the base
+// for bit, as key switching with centered fast base conversions followed by
+// an exactly rounded rescale.  Per output this takes 4 L + 4 + (the base
 // conversions') transforms -- 32 at L = 5, alpha = 3, dnum = 2 -- instead of
 // the 42 of the separate steps.  The transform kernels only load, transform
 // and store with light arithmetic on either side; the two base conversions,
@@ -145,14 +146,20 @@ __global__ void __launch_bounds__(kEwThreads) ks14_bconv_kernel(Ks14Args a, DevP
   const int e = rem < mc.lo ? rem : rem + (mc.hi - mc.lo);
   const u64 q = dp.pr[mc.basis[e]].q;
   const u64* yb = a.y + (int64_t)b * a.nl * kN + x0;
-  u64 s[kEwPer];
+  u64 s[kEwPer], neg[kEwPer];   // centered conversion: residues above (q_i - 1) / 2 stand for y_i - q_i
 #pragma unroll
-  for (int m = 0; m < kEwPer; ++m) s[m] = 0;
+  for (int m = 0; m < kEwPer; ++m) s[m] = neg[m] = 0;
   for (int i = mc.lo; i < mc.hi; ++i) {
-    const u64 c = mc.conv[i - mc.lo][e], cs = mc.conv_s[i - mc.lo][e];
+    const u64 c = mc.conv[i - mc.lo][e], cs = mc.conv_s[i - mc.lo][e], h = (dp.pr[i].q - 1) / 2;
 #pragma unroll
-    for (int m = 0; m < kEwPer; ++m) s[m] = add_mod(s[m], mul_shoup(yb[(int64_t)i * kN + m * kEwThreads], c, cs, q), q);
+    for (int m = 0; m < kEwPer; ++m) {
+      const u64 y = yb[(int64_t)i * kN + m * kEwThreads];
+      s[m] = add_mod(s[m], mul_shoup(y, c, cs, q), q);
+      neg[m] += y > h;
+    }
   }
+#pragma unroll
+  for (int m = 0; m < kEwPer; ++m) s[m] = sub_mod(s[m], mul_shoup(neg[m], mc.dmod[e], mc.dmod_s[e], q), q);
   u64* o = a.ext + ((int64_t)b * a.next + slot) * kN + x0;
 #pragma unroll
   for (int m = 0; m < kEwPer; ++m) o[m * kEwThreads] = s[m];

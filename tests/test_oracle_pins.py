@@ -260,7 +260,8 @@ def test_tensor_invariant():
 @pytest.mark.parametrize("params", [TINY_HYBRID, TINY_SINGLE])
 def test_modup_is_one_small_integer(params):
     """The ModUp residues over the extended basis are those of one integer
-    x with x = d2 mod every prime of the digit and 0 <= x < |D| * D."""
+    x with x = d2 mod every prime of the digit and |x| < |D| * D / 2 (the
+    centered conversion), and ModUp maps -d2 to -x."""
     o = make(params)
     rng = np.random.default_rng(2)
     lev = o.L - 1
@@ -271,11 +272,16 @@ def test_modup_is_one_small_integer(params):
         digit = o.q[lo:hi]
         D = brute.prod(digit)
         x = o.modup(lev, j, d2)
+        PB = brute.prod(basis)
         for t in range(o.n):
-            X = brute.crt([int(x[e, t]) for e in range(len(basis))], basis)
-            assert X < len(digit) * D
+            X = brute.centered(brute.crt([int(x[e, t]) for e in range(len(basis))], basis), PB)
+            assert 2 * abs(X) < len(digit) * D
             for i in range(lo, hi):
                 assert X % o.q[i] == int(d2[i, t])
+        neg = np.stack([(np.uint64(q) - d2[r]) % np.uint64(q) for r, q in enumerate(o.q)])
+        xn = o.modup(lev, j, neg)
+        for e, q in enumerate(basis):
+            assert np.array_equal(xn[e], (np.uint64(q) - x[e]) % np.uint64(q)), (j, e)
 
 
 @pytest.mark.parametrize("params", [TINY_HYBRID, TINY_SINGLE])
