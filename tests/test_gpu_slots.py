@@ -162,3 +162,24 @@ def test_matmul_slots_benchmarked_size(torch_cuda):
     C2 = ctx.matmul_slots(EA, EB, "lazy")
     for x in (0, 777, 2047):
         assert np.array_equal(ctx.export_stored(C, x), ctx.export_stored(C2, x))
+
+
+@pytest.mark.parametrize("sched", ["lazy", "per_product"])
+def test_matmul_slots_degenerate(torch_cuda, sched):
+    """An all-zero A in CSR (no stored value, no product: the result chunks
+    stay trivial zeros) and a 1 x 1 x 1 product with 4 slots per ciphertext
+    (one value in a chunk of four), against the oracle."""
+    ctx, orc = pair(HYB_SMALL, 21)
+    A = np.zeros((3, 4))
+    _, B = W.operands(3, 4, 2, 0.5, 65)
+    note("matmul slots all-zero A %s" % sched)
+    EA = ctx.encrypt_slots(A, "csr", 4, 1, 0)
+    assert EA.info().n_ciphertexts == 0
+    C = ctx.matmul_slots(EA, ctx.encrypt_slots(B, "dense", 4, 2, 1), sched)
+    assert ctx.last_stats().products == 0
+    for x in range(C.info().n_ciphertexts):
+        assert not np.any(ctx.export_stored(C, x))
+    assert np.all(ctx.decrypt(C) == 0.0)
+    note("matmul slots 1x1x1 %s" % sched)
+    A1, B1 = np.array([[0.625]]), np.array([[-0.5]])
+    _check_product(ctx, orc, A1, B1, "csr", sched, 4, 81, 82)
