@@ -369,8 +369,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the product shards by output rows; see the design notes)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the product would shard by output rows, each GPU running this path on its rows)", file=sys.stderr)
         sys.exit(2)
 
     import torch

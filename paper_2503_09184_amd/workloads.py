@@ -5,7 +5,7 @@ Both the GPU library's tests/benchmark and the CPU oracle receive the plain
 fp64 matrices it returns.
 
 Operands follow the profiling procedure of Sec. 4.1 (random square matrices
-with a set fraction of zeros), with the distributions fixed for this build:
+with a set fraction of zeros), with these distributions:
 values i.i.d. uniform on [-1, 1], zeros placed by an i.i.d. Bernoulli mask on
 A only (B dense), so a row's nonzero count is Binomial(K, 1 - s).  Masks are
 nested: element (i, k) is zero iff its mask draw u_ik < s, so for one seed the
