@@ -4,11 +4,15 @@
  *
  * Method: Ferguson et al., "Exploiting Unstructured Sparsity in Fully
  * Homomorphic Encrypted DNNs" (EuroMLSys '25).  The operands are matrices of
- * CKKS ciphertexts, one value per ciphertext (chunk size c = 1, Sec. 3.2);
- * C = A*B is formed by ciphertext products, relinearisation, rescaling and
- * accumulation (Algorithm 1), and the zeros of A are skipped through the
- * plaintext structure of one of the sparse schemes of Sec. 3.3.2 (naive
- * sparse mask, CSR, ELLPACK), or not at all (naive dense, Sec. 3.3.1).
+ * CKKS ciphertexts, one value per ciphertext (chunk size c = 1, Sec. 3.2;
+ * sfhe_matmul) or c values per ciphertext (sfhe_matmul_slots, with the
+ * rotations and slot-zero mask of Algorithm 1); C = A*B is formed by
+ * ciphertext products, relinearisation, rescaling and accumulation
+ * (Algorithm 1), and the zeros of A are skipped through the plaintext
+ * structure of one of the sparse schemes of Sec. 3.3.2 (naive sparse mask,
+ * CSR, ELLPACK), or not at all (naive dense, Sec. 3.3.1).  Plaintext weights
+ * times encrypted values (sfhe_matmul_plain*) and a request loop over them
+ * (sfhe_server_*) are the server-side variant of Sec. 3.3.2.
  *
  * Every function returns an int status: SFHE_OK (0) or a negative SFHE_E_*
  * code; sfhe_last_error() then holds a message (thread-local).  No exception
