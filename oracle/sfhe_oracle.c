@@ -10,6 +10,9 @@
  *     zero mask, CSR, ELLPACK), which skip the products whose A element is 0;
  *   - the thread assignment of Sec. 3.4 (result value -> thread by its index
  *     modulo the pool size);
+ *   - chunks of several values per ciphertext (Sec. 3.2) with Algorithm 1's
+ *     rotations and slot-zero mask, and plaintext weights times encrypted
+ *     values (Sec. 3.3.2);
  * over an RNS CKKS scheme (Sec. 3.1) with secret-key encryption, hybrid key
  * switching and exact rescaling.
  *
@@ -42,6 +45,9 @@
  *   R9  both operands sparse (the naive scheme's two masks, Sec. 3.3.2, and
  *       CSR/ELLPACK on the right operand): output (i, j) visits the k of row
  *       i whose B_kj the right operand's encoding stores; see out_ks().
+ *   R10 several values per ciphertext: slot j at zeta^(5^j), rotations by
+ *       X -> X^g with g = 5^r mod 2N and rotation keys; see the section on
+ *       chunks below.
  */
 #include <math.h>
 #include <pthread.h>
