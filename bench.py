@@ -37,6 +37,22 @@ VALU_PEAK = 256 * 4 * 16 * 2.4e9
 # a*b - rint(a*b/q)*q (mul, fma, mul, rndne, fma, add) for a0 b0, a1 b1 and
 # the Karatsuba (a0+a1)(b0+b1), plus three accumulating adds.
 FP_OPS_PER_PRODUCT = 21
+# ... in the carry-save arithmetic of the primes 2^60 - c (c < 2^20): 16
+# v_mad_u64_u32 (four 30-bit partial products for each of a0 b0, a0 b1,
+# a1 b0, a1 b1), the fold every four entries not counted
+INT60_OPS_PER_PRODUCT = 16
+# Fused key switch + rescale of one output at N = 2^14 with five data and
+# three special primes (dnum = 2): 32 transforms of 2^13 * 14 = 114,688
+# butterflies each, 16 of them over the 60-bit primes (integer Harvey
+# butterflies with Shoup twiddles: about 28 VALU instructions each) and 16
+# over the 40-bit primes (exact fp64 butterflies: 8 each); the base
+# conversions and key products (about 90 modular products per coefficient)
+# are HBM-bound element-wise work and are not counted here.
+KS_BUTTERFLIES_PER_TRANSFORM = (1 << 13) * 14
+KS_INT_TRANSFORMS, KS_FP_TRANSFORMS = 16, 16
+KS_INT_OPS_PER_BUTTERFLY, KS_FP_OPS_PER_BUTTERFLY = 28, 8
+KS_OPS_PER_OUTPUT = KS_BUTTERFLIES_PER_TRANSFORM * (KS_INT_TRANSFORMS * KS_INT_OPS_PER_BUTTERFLY +
+                                                    KS_FP_TRANSFORMS * KS_FP_OPS_PER_BUTTERFLY)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tensor_fp_traffic.json")
 
 
@@ -64,6 +80,43 @@ def measured_traffic():
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def measured_peaks(torch, sfhe):
+    """What this chip sustains: a 1 GiB device copy (bytes read + written per
+    second) and the VALU issue-rate probes of the library."""
+    n_words = (1 << 30) // 8
+    src = torch.ones(n_words, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    out = {"copy_GBps": copy_gbs}
+    for kind in ("fp64_fma", "mad_u64_u32", "int32_add"):
+        out[kind + "_Tops"] = sfhe.probe_valu(kind) / 1e12
+    return out
+
+
+def summary(times):
+    return {"mean": float(np.mean(times)), "median": float(np.median(times)), "min": float(np.min(times)),
+            "max": float(np.max(times)), "n": len(times)}
+
+
+def step_ops(products, keyswitches, N, n_fp, n_int60):
+    """Algorithmic VALU operations of one product step at N = 2^14 with the
+    benchmarked primes: the tensor products (21 per product, prime and
+    coefficient in fp64, 16 in the carry-save integer arithmetic) and the
+    transforms of the fused key switch and rescale per output."""
+    return (float(products) * N * (n_fp * FP_OPS_PER_PRODUCT + n_int60 * INT60_OPS_PER_PRODUCT) +
+            float(keyswitches) * KS_OPS_PER_OUTPUT)
 
 
 def timed(ctx, torch, A, B, sched, steps, warmup, keep_last=False):
@@ -318,6 +371,21 @@ def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
             time.sleep(0.0002)
     makespan = max(done_at.values()) - arrivals[0]
     st = srv.status()
+    # batches whose device-time interval intersects another batch's ran concurrently
+    iv = sorted(set(srv.intervals[t] for t in tickets.values()))
+    overl = sum(1 for x in range(len(iv)) if any(iv[x][0] < iv[y][1] and iv[y][0] < iv[x][1]
+                                               for y in range(len(iv)) if y != x))
+    busy = 0.0
+    cur0, cur1 = None, None
+    for a, b in iv:
+        if cur1 is None or a > cur1:
+            if cur1 is not None:
+                busy += cur1 - cur0
+            cur0, cur1 = a, b
+        else:
+            cur1 = max(cur1, b)
+    if cur1 is not None:
+        busy += cur1 - cur0
     lat = np.array([(done_at[n] - arrivals[n]) * 1e3 for n in range(n_requests)])
     products = st["products"]
     # a result in the mix equals the same request alone, bit for bit
@@ -349,7 +417,68 @@ def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
             "ctpt_mults_per_s": products / makespan, "batches": int(st["batches"]),
             "mean_batch_size": float(np.mean(sizes)), "max_batch_size": int(max(sizes)),
             "alone_equals_mix": bool(same), "max_abs_err_vs_fp64": err,
+            "batches_overlapping_another": overl, "device_busy_ms": busy,
+            "device_batch_ms_sum": float(sum(b - a for a, b in iv)), "streams": 4,
             "ring": "N=2^15, 9 data + 3 special primes (12 limbs), dnum=3"}
+
+
+def cpu_thread_scaling(threads, target_s=8.0):
+    """The paper-style thread speed-up (Sec. 4.3) of the oracle on the sweep
+    ring (N = 2^13, 64 x 64 x 64, A 50% zeros in CSR, PER_PRODUCT: every
+    product relinearised and rescaled, as in the paper): the same sample of
+    outputs on one thread and on `threads` threads (output (i, j) on thread
+    (i * 64 + j) mod T)."""
+    from oracle.oracle import Oracle
+    from paper_2503_09184_amd import workloads as W
+    P = W.PARAMS["sweep_n8192"]
+    orc = Oracle(**P)
+    orc.keygen(W.key_seed(2))
+    A, B = W.operands(64, 64, 64, 0.5, W.workload_seed(2))
+    sa, sb = W.enc_seed(2, 0), W.enc_seed(2, 1)
+    _, _, t1 = orc.matmul(A, B, "csr", "per_product", sa, sb, outputs=[(0, 0)], threads=1, decrypt=False)
+    per_output = max(t1, 1e-3)
+    n_out = int(max(threads, min(4096, round(target_s / per_output / threads) * threads)))
+    outs = [(x // 64, x % 64) for x in range(n_out)]
+    _, _, s1 = orc.matmul(A, B, "csr", "per_product", sa, sb, outputs=outs, threads=1, decrypt=False)
+    _, _, sT = orc.matmul(A, B, "csr", "per_product", sa, sb, outputs=outs, threads=threads, decrypt=False)
+    products = sum(int(np.count_nonzero(A[i])) for (i, _) in outs)
+    return {"outputs": n_out, "products": products, "seconds_1_thread": s1, "seconds_T_threads": sT,
+            "threads": threads, "speedup": s1 / sT,
+            "workload": "N=2^13 64x64x64, A 50% zeros CSR, per-product (Algorithm 1 order)"}
+
+
+def sweep_leg(torch, sfhe, W, sparsities=(0.0, 0.25, 0.5, 0.75, 0.9)):
+    """The sparsity/encoding sweep on the GPU (N = 2^13, 60/40/40-bit data
+    primes and one special prime, 64 x 64 x 64, B dense): ms per product for
+    the four encodings x both schedules at each sparsity of A, and the
+    sparse-over-dense speed-up (the analogue of the paper's runtime against
+    sparsity, Sec. 4.2).  One untimed call, then the median of 3."""
+    P = W.PARAMS["sweep_n8192"]
+    ctx = sfhe.Context(**P)
+    ctx.keygen(W.key_seed(2))
+    sa, sb = W.enc_seed(2, 0), W.enc_seed(2, 1)
+    out = {}
+    for sp in sparsities:
+        A, B = W.operands(64, 64, 64, sp, W.workload_seed(2))
+        EB = ctx.encrypt(B, "dense", sb, 1)
+        row = {}
+        for enc in ("dense", "naive", "csr", "ell"):
+            EA = ctx.encrypt(A, enc, sa, 0)
+            for sched in ("lazy", "per_product"):
+                tt, st, _, _ = timed(ctx, torch, EA, EB, sched, 3, 1)
+                row["%s_%s" % (enc, sched)] = {"ms_median": float(np.median(tt)), "ms_min": float(np.min(tt)),
+                                               "products": int(st.products)}
+            EA.close()
+        for sched in ("lazy", "per_product"):
+            row["csr_over_dense_" + sched] = row["dense_" + sched]["ms_median"] / row["csr_" + sched]["ms_median"]
+        out["s%02d" % int(round(sp * 100))] = row
+        EB.close()
+        log("sweep s=%.2f: lazy dense %.2f / csr %.2f ms, per-product dense %.1f / csr %.1f ms" %
+            (sp, row["dense_lazy"]["ms_median"], row["csr_lazy"]["ms_median"], row["dense_per_product"]["ms_median"],
+             row["csr_per_product"]["ms_median"]))
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -360,7 +489,7 @@ def main():
     ap.add_argument("--sparsity", type=float, default=0.5)
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--only", default="", help="comma list of extra legs to run (default all): "
-                    "s90,dense,ell,naive,per_product,both,slots,serve,ctpt,cpu")
+                    "s90,dense,ell,naive,per_product,both,sweep,slots,serve,ctpt,cpu,peaks")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -382,6 +511,11 @@ def main():
     cfg_id = 3
     P = W.PARAMS["realistic_n16384"]
     n = args.size
+    want = set(x for x in args.only.split(",") if x) if args.only else None
+
+    def run(name):
+        return (not args.no_extras) and (want is None or name in want)
+
     if args.calib_copy_mib:
         n_words = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(n_words, dtype=torch.int64, device="cuda")
@@ -391,6 +525,10 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: %d MiB read, %d MiB written" % (args.calib_copy_mib, args.calib_copy_mib))
         del src, dst
+    peaks = None
+    if run("peaks"):
+        peaks = measured_peaks(torch, sfhe)
+        log("measured peaks %s" % json.dumps(peaks))
     log("setup: context N=2^14, keys")
     ctx = sfhe.Context(**P)
     ctx.keygen(W.key_seed(cfg_id))
@@ -407,62 +545,105 @@ def main():
     ms = float(np.mean(times))
     products = st.products
     value = products / (ms / 1e3)
-    log("headline %.2f ms/step, %d products, %.4g ct-mults/s" % (ms, products, value))
+    log("headline %.2f ms/step (median %.2f, min %.2f), %d products, %.4g ct-mults/s" %
+        (ms, float(np.median(times)), float(np.min(times)), products, value))
     # decrypted error of the headline result (outside the timed region)
     dec = ctx.decrypt(C)
     err = float(np.max(np.abs(dec - A @ Bm)))
     C.close()
-
-    # the dominant kernel's live timing over the timed steps: hipEvents on the
-    # library's stream around each launch of the fp64 tensor kernel
-    fp_ms = sum(m for m, _ in fp_steps)
-    launches = max(1, sum(n for _, n in fp_steps))
     N = ctx.n
-    ops = float(products) * N * st.tensor_fp_primes * FP_OPS_PER_PRODUCT * len(fp_steps)
-    achieved = ops / (fp_ms / 1e3) / 1e12
+    n_fp = int(st.tensor_fp_primes)
+    n_int60 = ctx.L - n_fp
+
+    def fp_roofline(fp_list, prods, kernel_name):
+        """the fp64 tensor kernel's live timing (hipEvents on the library's
+        stream around each launch) against the VALU peaks"""
+        fp_ms = sum(m for m, _ in fp_list)
+        launches = max(1, sum(k for _, k in fp_list))
+        ops = float(prods) * N * n_fp * FP_OPS_PER_PRODUCT * len(fp_list)
+        achieved = ops / (fp_ms / 1e3) / 1e12
+        peak = VALU_PEAK / 1e12
+        r = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T VALU-op/s", "frac": achieved / peak,
+             "kernel": kernel_name, "launches_timed": launches, "ms_per_launch": fp_ms / launches,
+             "ops_per_launch": ops / launches, "primes": n_fp}
+        if peaks:
+            r["peak_measured"] = peaks["fp64_fma_Tops"]
+            r["frac_measured"] = achieved / peaks["fp64_fma_Tops"]
+        return r
+
+    kname = "tensor_cols_kernel (fp64 residues, primes below 2^42)"
+    roofline = fp_roofline(fp_steps, products, kname)
+    roofline["traffic"] = measured_traffic()
     # per-step breakdown (one extra, untimed step with every launch group bracketed)
     ctx.set_profiling(True)
     ptimes, pst, _, _ = timed(ctx, torch, EA, EB, "lazy", 1, 0)
     ctx.set_profiling(False)
-    peak = VALU_PEAK / 1e12
-    traffic = measured_traffic()
-    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T VALU-op/s",
-                "frac": achieved / peak, "traffic": traffic,
-                "kernel": "tensor_block_kernel<ArithFp> (primes below 2^42)",
-                "launches_timed": launches, "ms_per_launch": fp_ms / launches,
-                "ops_per_launch": ops / launches, "primes": int(st.tensor_fp_primes)}
     breakdown = {"tensor_ms": pst.tensor_ms, "tensor_fp_ms": pst.tensor_fp_ms, "keyswitch_ms": pst.keyswitch_ms,
                  "rescale_ms": pst.rescale_ms, "total_ms": ptimes[0]}
     log("breakdown %s" % json.dumps(breakdown))
 
+    def ks_roofline(ks_ms, keyswitches):
+        ops = float(keyswitches) * KS_OPS_PER_OUTPUT
+        achieved = ops / (ks_ms / 1e3) / 1e12
+        r = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK / 1e12, "unit": "T VALU-op/s",
+             "frac": achieved / (VALU_PEAK / 1e12), "ms": ks_ms, "keyswitches": int(keyswitches),
+             "butterflies": float(keyswitches) * KS_BUTTERFLIES_PER_TRANSFORM * (KS_INT_TRANSFORMS + KS_FP_TRANSFORMS),
+             "kernels": "ks14_k1/bconv/k2/k3a/lift/k3b (fused key switch and rescale, N = 2^14)"}
+        if peaks:
+            # the integer butterflies are bound by the 32-bit/64-bit integer
+            # products, the fp64 ones by fp64 issue: the measured peak is the
+            # op-weighted mix of the two probes
+            w_int = KS_INT_TRANSFORMS * KS_INT_OPS_PER_BUTTERFLY
+            w_fp = KS_FP_TRANSFORMS * KS_FP_OPS_PER_BUTTERFLY
+            mix = (w_int + w_fp) / (w_int / peaks["mad_u64_u32_Tops"] + w_fp / peaks["fp64_fma_Tops"])
+            r["peak_measured"] = mix
+            r["frac_measured"] = achieved / mix
+        return r
+
+    rooflines = {"keyswitch_rescale_50": ks_roofline(pst.keyswitch_ms, pst.keyswitches)}
+
     legs = {}
-    want = set(x for x in args.only.split(",") if x) if args.only else None
 
-    def run(name):
-        return (not args.no_extras) and (want is None or name in want)
-
-    def leg(name, Amat, enc, sched, steps):
+    def leg(name, Amat, enc, sched, steps, warm=1, fp_name=None):
         EAx = ctx.encrypt(Amat, enc, sa, 0)
-        tt, stx, _, _ = timed(ctx, torch, EAx, EB, sched, steps, 1 if steps > 1 else 0)
+        tt, stx, _, fpx = timed(ctx, torch, EAx, EB, sched, steps, warm)
         m = float(np.mean(tt))
-        legs[name] = {"ms": m, "products": int(stx.products), "ct_mults_per_s": stx.products / (m / 1e3),
+        legs[name] = {"ms": m, "ms_median": float(np.median(tt)), "ms_min": float(np.min(tt)), "steps": len(tt),
+                      "products": int(stx.products), "ct_mults_per_s": stx.products / (m / 1e3),
                       "keyswitches": int(stx.keyswitches)}
+        ops = step_ops(stx.products, stx.keyswitches, N, n_fp, n_int60)
+        legs[name]["step_valu_ops"] = ops
+        legs[name]["step_frac_of_valu_peak"] = ops / (float(np.median(tt)) / 1e3) / VALU_PEAK
+        if fp_name:
+            rooflines[fp_name] = fp_roofline(fpx, stx.products, kname)
         EAx.close()
-        log("%s: %.2f ms, %d products" % (name, m, stx.products))
+        log("%s: %.2f ms (median %.2f, min %.2f), %d products" % (name, m, legs[name]["ms_median"],
+                                                                 legs[name]["ms_min"], stx.products))
+        return stx
 
+    legs["lazy_csr_50"] = {"ms": ms, "ms_median": float(np.median(times)), "ms_min": float(np.min(times)),
+                           "steps": len(times), "products": int(products), "ct_mults_per_s": value,
+                           "keyswitches": int(st.keyswitches)}
+    ops50 = step_ops(products, st.keyswitches, N, n_fp, n_int60)
+    legs["lazy_csr_50"]["step_valu_ops"] = ops50
+    legs["lazy_csr_50"]["step_frac_of_valu_peak"] = ops50 / (float(np.median(times)) / 1e3) / VALU_PEAK
     if run("ell"):
         leg("lazy_ell_50", A, "ell", "lazy", args.steps)
     if run("naive"):
         leg("lazy_naive_50", A, "naive", "lazy", args.steps)
     if run("dense"):
-        leg("lazy_dense_same_operands", A, "dense", "lazy", args.steps)
+        leg("lazy_dense_same_operands", A, "dense", "lazy", args.steps, fp_name="tensor_fp_dense")
+    A90 = None
     if run("s90"):
         A90, _ = W.operands(n, n, n, 0.9, W.workload_seed(cfg_id))
-        leg("lazy_csr_90", A90, "csr", "lazy", args.steps)
+        leg("lazy_csr_90", A90, "csr", "lazy", args.steps, fp_name="tensor_fp_90")
         if run("dense"):
-            leg("lazy_dense_90_operands", A90, "dense", "lazy", 1)
+            leg("lazy_dense_90_operands", A90, "dense", "lazy", max(1, min(3, args.steps)))
     if run("per_product"):
-        leg("per_product_csr_50", A, "csr", "per_product", 1)
+        # Algorithm 1's order: one warm-up, then the median and min of 3
+        leg("per_product_csr_50", A, "csr", "per_product", 3)
+        if A90 is not None:
+            leg("per_product_csr_90", A90, "csr", "per_product", 3)
     if run("both"):
         # both operands sparse (the paper's own setting): B with half its
         # entries zero, as a ReLU leaves activations, CSR on both sides
@@ -472,14 +653,28 @@ def main():
         EAx = ctx.encrypt(A, "csr", sa, 0)
         tt, stx, _, _ = timed(ctx, torch, EAx, EBz, "lazy", args.steps, 1)
         m = float(np.mean(tt))
-        legs["lazy_csr_both_50"] = {"ms": m, "products": int(stx.products), "ct_mults_per_s": stx.products / (m / 1e3),
-                                    "keyswitches": int(stx.keyswitches), "b_zero_fraction": float(np.mean(Bz == 0.0))}
+        legs["lazy_csr_both_50"] = {"ms": m, "ms_median": float(np.median(tt)), "products": int(stx.products),
+                                    "ct_mults_per_s": stx.products / (m / 1e3), "keyswitches": int(stx.keyswitches),
+                                    "b_zero_fraction": float(np.mean(Bz == 0.0))}
         log("lazy_csr_both_50: %.2f ms, %d products" % (m, stx.products))
         EAx.close()
         EBz.close()
+    # per-kernel breakdown of the 90% step
+    if A90 is not None:
+        EA9 = ctx.encrypt(A90, "csr", sa, 0)
+        ctx.set_profiling(True)
+        t9, st9, _, _ = timed(ctx, torch, EA9, EB, "lazy", 1, 0)
+        ctx.set_profiling(False)
+        breakdown["s90"] = {"tensor_ms": st9.tensor_ms, "tensor_fp_ms": st9.tensor_fp_ms,
+                            "keyswitch_ms": st9.keyswitch_ms, "rescale_ms": st9.rescale_ms, "total_ms": t9[0]}
+        rooflines["keyswitch_rescale_90"] = ks_roofline(st9.keyswitch_ms, st9.keyswitches)
+        EA9.close()
     EA.close()
     EB.close()
     torch.cuda.empty_cache()
+    if run("sweep"):
+        log("sparsity/encoding sweep at N = 2^13 (64 x 64 x 64)")
+        legs["sweep_n8192"] = sweep_leg(torch, sfhe, W)
     if run("slots"):
         log("chunks of 8 values per ciphertext: Algorithm 1 with rotations and the slot-0 mask")
         legs["slots8_lazy_csr_50"] = slots_leg(ctx, torch, A, Bm, sa, sb, 8)
@@ -507,11 +702,15 @@ def main():
 
     cpu = None
     if not args.no_cpu and run("cpu"):
-        threads = len(os.sched_getaffinity(0))
-        threads = max(1, min(threads, 16))
-        log("cpu baseline: oracle on %d threads" % threads)
+        affinity = len(os.sched_getaffinity(0))
+        # a one-GPU machine's CPU share is 16 threads, whatever the affinity mask shows
+        threads = max(1, min(affinity, 16))
+        log("cpu baseline: oracle on %d threads (%d in the affinity mask)" % (threads, affinity))
         cpu = cpu_baseline(P, A, Bm, cfg_id, threads)
+        cpu["affinity_cores"] = affinity
         log("cpu baseline %.4g ct-mults/s" % cpu["value"])
+        cpu["thread_scaling"] = cpu_thread_scaling(threads)
+        log("oracle thread speed-up %.2fx on %d threads" % (cpu["thread_scaling"]["speedup"], threads))
 
     speedups = {}
     if "lazy_dense_same_operands" in legs:
@@ -519,7 +718,9 @@ def main():
     if "lazy_csr_90" in legs and "lazy_dense_90_operands" in legs:
         speedups["sparse90_over_dense"] = legs["lazy_dense_90_operands"]["ms"] / legs["lazy_csr_90"]["ms"]
     if "per_product_csr_50" in legs:
-        speedups["lazy_over_per_product_50"] = legs["per_product_csr_50"]["ms"] / ms
+        speedups["lazy_over_per_product_50"] = legs["per_product_csr_50"]["ms_median"] / float(np.median(times))
+    if "per_product_csr_90" in legs and "lazy_csr_90" in legs:
+        speedups["lazy_over_per_product_90"] = legs["per_product_csr_90"]["ms_median"] / legs["lazy_csr_90"]["ms_median"]
     if "slots8_per_product_csr_50_32x128x128" in legs:
         speedups["slots8_lazy_over_per_product_32x128x128"] = (legs["slots8_per_product_csr_50_32x128x128"]["ms"] /
                                                                legs["slots8_lazy_csr_50_32x128x128"]["ms"])
@@ -535,6 +736,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_median": float(np.median(times)),
+        "ms_per_step_min": float(np.min(times)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -549,6 +752,8 @@ def main():
         "legs": legs,
         "speedups": speedups,
         "roofline": roofline,
+        "rooflines": rooflines,
+        "measured_peaks": peaks,
         "ntt_designs": {d: {"used": ctx.ntt_tuning(d == "inverse")[0], "us_per_row": ctx.ntt_tuning(d == "inverse")[1]}
                         for d in ("forward", "inverse")},
         "cpu_baseline": cpu,

@@ -93,12 +93,24 @@ typedef struct {
   double sigma;             /* error standard deviation; the sampler clips at |e| <= 19 */
 } sfhe_params;
 
-/* Optional device allocator.  alloc returns device memory or NULL; free
- * receives the pointer and the size it was allocated with.  Both are called
- * from the thread that called into the library. */
+/* Optional device allocator (a caching allocator such as PyTorch's).  alloc
+ * returns device memory or NULL; free receives the pointer, the size it was
+ * allocated with and the same stream.  Both are called from the thread that
+ * called into the library.  `stream` (a hipStream_t, NULL = the default
+ * stream) is the stream of the call that takes the block: allocation is
+ * stream-ordered.  free is called once the last launch that reads or writes
+ * the block has been enqueued on that stream, possibly before it has run, so
+ * the allocator may hand the block only to work that follows on the same
+ * stream (or to other streams once that stream has passed the point of the
+ * free).  Temporaries of a call are taken and given back on the call's
+ * stream; a matrix's ciphertexts on the stream of the call that made it,
+ * given back by sfhe_mat_destroy.  A matrix read by work on another stream
+ * must not be destroyed before that work has ended.  Without hooks the
+ * library takes its blocks from a stream-ordered memory pool of its own
+ * (hipMallocFromPoolAsync / hipFreeAsync on the same streams). */
 typedef struct {
-  void* (*alloc)(size_t bytes, void* user);
-  void (*free)(void* ptr, size_t bytes, void* user);
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, size_t bytes, void* stream, void* user);
   void* user;
 } sfhe_device_hooks;
 
@@ -295,33 +307,53 @@ int sfhe_plain_graph_result(const sfhe_plain_graph* graph, int32_t n, const sfhe
 void sfhe_plain_graph_destroy(sfhe_plain_graph* graph);
 
 /* ---- Serving: a request loop over plaintext-weight products ------------
- * Requests W X (plaintext weights from sfhe_encode_matrix, encrypted DENSE
- * activations X at the top level) queue in arrival order.  Each
- * sfhe_server_step first retires the batches whose device work has ended,
- * then admits queued requests, in order, while the device bytes they hold
- * until they complete (2 (L) N words of sums and 2 (L - 1) N of results per
- * output) fit budget_bytes beside the batches still running, and enqueues
- * them as one fused sfhe_matmul_plain_batch on the server's stream: requests
- * arriving while a batch runs join the next one, which starts when the
- * running one ends.  A request's result is the same, bit for bit, alone or
- * in any batch.  The caller keeps W and X alive until its request is done;
- * a finished result belongs to the caller from sfhe_server_poll on.  Calls
+ * Continuous batching for the server side of Sec. 3.3.2 (plaintext weights,
+ * encrypted activations).  Requests W X (plaintext weights from
+ * sfhe_encode_matrix, encrypted DENSE activations X at the top level) queue
+ * in arrival order.  Each sfhe_server_step first retires the batches whose
+ * device work has ended, then admits queued requests, in order, while the
+ * device bytes they hold until they complete fit budget_bytes beside the
+ * batches still running (per request: 2 (L) N words of sums and 2 (L - 1) N
+ * of results per output, a rescale scratch for up to 2048 of its outputs and
+ * its weight tables), and enqueues them as one fused sfhe_matmul_plain_batch
+ * on the least busy of the server's n_streams streams (1 to 4, created by
+ * the server at the default priority).  A batch admitted while others run
+ * therefore starts at once and overlaps them on the device; its launches
+ * first wait for the work enqueued on `stream` (the client stream, e.g. the
+ * requests' encryptions) before the step.  A request's result is the same,
+ * bit for bit, alone or in any batch.  The caller keeps W and X alive until
+ * its request is done; a finished result belongs to the caller from
+ * sfhe_server_poll on (its memory was taken on the batch's stream).  Calls
  * on one server must not overlap. */
 typedef struct sfhe_server sfhe_server;
-int sfhe_server_create(sfhe_ctx* ctx, uint64_t budget_bytes, void* stream, sfhe_server** out);
+int sfhe_server_create(sfhe_ctx* ctx, uint64_t budget_bytes, int32_t n_streams, void* stream, sfhe_server** out);
+/* the device bytes the server counts for request W X against its budget */
+int sfhe_server_request_bytes(const sfhe_ctx* ctx, const sfhe_mat* W, const sfhe_mat* X, uint64_t* bytes);
 /* queue W X; a request larger than the budget is SFHE_E_NOMEM */
 int sfhe_server_submit(sfhe_server* srv, const sfhe_mat* W, const sfhe_mat* X, int64_t* ticket);
 /* retire ended batches, admit and launch; *admitted = requests launched now */
 int sfhe_server_step(sfhe_server* srv, int32_t* admitted);
-/* whether ticket's request is done (waiting for the running batches if wait
- * != 0); if so *C receives its result, *batch_ms the device time of its batch
- * and *batch_size the requests in it (both nullable) */
+/* whether ticket's request is done (with wait != 0, waiting for its batch if
+ * it is running); if so *C receives its result, and (each nullable)
+ * *batch_ms the device time of its batch, *batch_size the requests in it,
+ * *start_ms and *end_ms the batch's device-time interval in ms after the
+ * server's creation (intervals of different batches that intersect ran
+ * concurrently) */
 int sfhe_server_poll(sfhe_server* srv, int64_t ticket, int32_t wait, int32_t* done, sfhe_mat** C, double* batch_ms,
-                     int32_t* batch_size);
+                     int32_t* batch_size, double* start_ms, double* end_ms);
 int sfhe_server_status(const sfhe_server* srv, int64_t* queued, int64_t* running, uint64_t* bytes_in_flight,
                        int64_t* batches, int64_t* products);
 /* waits for the running batches; results not yet polled are freed */
 void sfhe_server_destroy(sfhe_server* srv);
+
+/* Measurement support (not part of the method): the sustained issue rate,
+ * in lane operations per second, of one VALU instruction class on the
+ * current device, from a kernel of independent dependency chains timed with
+ * hipEvents on the default stream: kind 0 = fp64 FMA, 1 = v_mad_u64_u32
+ * (32 x 32 + 64 -> 64 bits), 2 = 32-bit integer add/xor.  Rooflines are
+ * stated against these as well as against the published peaks.  Allocates
+ * and frees a 2 KiB buffer; synchronises the device. */
+int sfhe_probe_valu(int32_t kind, double* lane_ops_per_s);
 
 int sfhe_matrix_info(const sfhe_mat* m, sfhe_mat_info* out);
 int sfhe_last_stats(const sfhe_ctx* ctx, sfhe_stats* out);

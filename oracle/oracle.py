@@ -15,7 +15,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "sfhe_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# SFHE_ORACLE_LIB names another build of the same source (the sanitizer
+# build of the pin tests); the default is the in-tree library
+LIB = os.environ.get("SFHE_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
 
 ENC = {"dense": 0, "naive": 1, "csr": 2, "ell": 3}
 SCHED = {"per_product": 0, "lazy": 1}
@@ -27,10 +30,13 @@ _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)
 
 
-def build():
-    """Compile the oracle with gcc (plain C11, no vectorisation tricks)."""
-    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fPIC", "-shared",
-           "-o", LIB, SRC, "-lm", "-lpthread"]
+def build(out=None, sanitize=False):
+    """Compile the oracle with gcc (plain C11, no vectorisation tricks); with
+    sanitize, an AddressSanitizer + UndefinedBehaviorSanitizer build that
+    aborts on the first report (loaded with libasan preloaded)."""
+    opt = SAN_FLAGS if sanitize else ["-O2"]
+    cmd = ["gcc"] + opt + ["-std=gnu11", "-ffp-contract=off", "-fPIC", "-shared",
+                           "-o", out or LIB, SRC, "-lm", "-lpthread"]
     subprocess.check_call(cmd)
 
 
@@ -40,7 +46,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not os.environ.get("SFHE_ORACLE_LIB") and (not os.path.exists(LIB) or
+                                                       os.path.getmtime(LIB) < os.path.getmtime(SRC)):
             build()
         L = ctypes.CDLL(LIB)
         L.orc_ctx_create.restype = ctypes.c_void_p

@@ -22,20 +22,20 @@ void set_error(const std::string& m) { g_err = m; }
 
 void* Alloc::get(size_t bytes) {
   if (bytes == 0) return nullptr;
-  if (has_hooks) return hooks.alloc(bytes, hooks.user);
+  if (has_hooks) return hooks.alloc(bytes, (void*)cur, hooks.user);
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  if (hipMallocFromPoolAsync(&p, bytes, pool, cur) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
   return p;
 }
-void Alloc::put(void* p, size_t bytes) {
+void Alloc::put(void* p, size_t bytes, hipStream_t s) {
   if (!p) return;
-  if (has_hooks) {
-    hooks.free(p, bytes, hooks.user);
-  } else {
-    // work queued on any stream may still read the buffer
-    (void)hipDeviceSynchronize();
-    (void)hipFree(p);
-  }
+  if (has_hooks)
+    hooks.free(p, bytes, (void*)s, hooks.user);
+  else
+    (void)hipFreeAsync(p, s);
 }
 
 static int brv(int x, int bits) {
@@ -554,6 +554,26 @@ int sfhe_ctx_create(const sfhe_params* p, const sfhe_device_hooks* hooks, sfhe_c
     if (!hooks->alloc || !hooks->free) { delete c; set_error("hooks need alloc and free"); return SFHE_E_INVALID_ARG; }
     c->alloc.hooks = *hooks;
     c->alloc.has_hooks = true;
+  } else {
+    // a stream-ordered pool that keeps freed blocks for reuse (no release
+    // back to the driver at synchronisation points)
+    hipMemPoolProps pp;
+    std::memset(&pp, 0, sizeof(pp));
+    pp.allocType = hipMemAllocationTypePinned;
+    pp.handleTypes = hipMemHandleTypeNone;
+    pp.location.type = hipMemLocationTypeDevice;
+    pp.location.id = dev;
+    hipError_t e = hipMemPoolCreate(&c->alloc.pool, &pp);
+    if (e == hipSuccess) {
+      uint64_t keep = UINT64_MAX;
+      e = hipMemPoolSetAttribute(c->alloc.pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    if (e != hipSuccess) {
+      set_error(std::string("device memory pool: ") + hipGetErrorString(e));
+      if (c->alloc.pool) (void)hipMemPoolDestroy(c->alloc.pool);
+      delete c;
+      return SFHE_E_DEVICE;
+    }
   }
   int rc = gen_primes(c, bits);
   if (rc) { delete c; set_error("not enough NTT primes of the requested sizes"); return rc; }
@@ -610,10 +630,17 @@ int sfhe_set_profiling(sfhe_ctx* c, int32_t on) {
 
 void sfhe_ctx_destroy(sfhe_ctx* c) {
   if (!c) return;
+  // work of any stream may still read the context's tables and keys
+  (void)hipDeviceSynchronize();
   for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
-  delete c;
+  hipMemPool_t pool = c->alloc.pool;
+  delete c;   // gives the tables and keys back (stream-ordered)
+  if (pool) {
+    (void)hipDeviceSynchronize();
+    (void)hipMemPoolDestroy(pool);
+  }
 }
 
 int sfhe_ctx_n(const sfhe_ctx* c, int32_t* n) {
@@ -650,6 +677,7 @@ int sfhe_encrypt_matrix(sfhe_ctx* c, const double* vals, int32_t rows, int32_t c
   if (rows < 1 || cols < 1 || ld < cols) { set_error("bad shape or leading dimension"); return SFHE_E_SHAPE; }
   if ((int)enc < 0 || (int)enc > 3) { set_error("bad encoding"); return SFHE_E_INVALID_ARG; }
   hipStream_t s = (hipStream_t)stream;
+  StreamScope scope_(c->alloc, s);
   const double lim = ldexp(1.0, 62 - ((int)c->log2_scale + 1 - c->logN));
   for (int i = 0; i < rows; ++i)
     for (int j = 0; j < cols; ++j) {
@@ -785,40 +813,57 @@ static int matmul_c1(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_sch
     const int64_t d_budget = (int64_t)32 << 30;
     int rb = (int)std::max<int64_t>(kTileRows, d_budget / ((int64_t)std::max(Nc, 1) * dw * 8) / kTileRows * kTileRows);
     const int64_t ks_slice = std::max<int64_t>(1, 2048);
-    struct Batch { int r0, nr, t0, nt; };
+    // tile lists: for every tile of TR consecutive rows of a batch, the
+    // ascending union of the rows' visited k, each with the mask of the rows
+    // that visit it and their A slots; one list of kTileRows-row tiles (the
+    // integer kernels) and one of kTileRowsFp-row tiles (the fp64 kernel)
+    struct Tiles {
+      int TR;
+      std::vector<int> tstart, ek, emask, eslot;
+    };
+    struct Batch { int r0, nr, t0, nt, f0, fnt; };
     std::vector<Batch> batches;
-    std::vector<int> tstart, ek, emask, eslot;
+    Tiles ti{kTileRows, {}, {}, {}, {}}, tf{kTileRowsFp, {}, {}, {}, {}};
     std::vector<std::pair<int, int64_t>> pairs;
     std::vector<int> kmask(A->cols);
-    std::vector<int> kslot((size_t)A->cols * kTileRows);
+    std::vector<int> kslot((size_t)A->cols * std::max(kTileRows, kTileRowsFp));
+    // tiles of rows r0 .. r0 + nr - 1 into T; returns the tile count
+    auto add_tiles = [&](Tiles& T, int r0, int nr) {
+      const int TR = T.TR;
+      int nt = 0;
+      for (int g = 0; g * TR < nr; ++g) {
+        std::fill(kmask.begin(), kmask.end(), 0);
+        for (int r = 0; r < TR && g * TR + r < nr; ++r) {
+          row_pairs(A, r0 + g * TR + r, pairs);
+          for (auto& pr : pairs) {
+            kmask[pr.first] |= 1 << r;
+            kslot[(size_t)pr.first * TR + r] = (int)pr.second;
+          }
+        }
+        T.tstart.push_back((int)T.ek.size());
+        for (int k = 0; k < A->cols; ++k) {
+          if (!kmask[k]) continue;
+          T.ek.push_back(k);
+          T.emask.push_back(kmask[k]);
+          for (int r = 0; r < TR; ++r) T.eslot.push_back((kmask[k] >> r) & 1 ? kslot[(size_t)k * TR + r] : -1);
+        }
+        ++nt;
+      }
+      return nt;
+    };
     for (int i = 0; i < M;) {
       if (visits[i] == 0) { ++i; continue; }
       int nr = 0;
       while (i + nr < M && nr < rb && visits[i + nr] > 0) ++nr;
-      Batch bt{i, nr, (int)tstart.size(), 0};
-      for (int g = 0; g * kTileRows < nr; ++g) {
-        std::fill(kmask.begin(), kmask.end(), 0);
-        for (int r = 0; r < kTileRows && g * kTileRows + r < nr; ++r) {
-          row_pairs(A, i + g * kTileRows + r, pairs);
-          for (auto& pr : pairs) {
-            kmask[pr.first] |= 1 << r;
-            kslot[(size_t)pr.first * kTileRows + r] = (int)pr.second;
-          }
-        }
-        tstart.push_back((int)ek.size());
-        for (int k = 0; k < A->cols; ++k) {
-          if (!kmask[k]) continue;
-          ek.push_back(k);
-          emask.push_back(kmask[k]);
-          for (int r = 0; r < kTileRows; ++r) eslot.push_back((kmask[k] >> r) & 1 ? kslot[(size_t)k * kTileRows + r] : -1);
-        }
-        ++bt.nt;
-      }
+      Batch bt{i, nr, (int)ti.tstart.size(), 0, (int)tf.tstart.size(), 0};
+      bt.nt = add_tiles(ti, i, nr);
+      bt.fnt = add_tiles(tf, i, nr);
       batches.push_back(bt);
       for (int r = 0; r < nr; ++r) products += visits[i + r] * (int64_t)Nc;
       i += nr;
     }
-    tstart.push_back((int)ek.size());
+    ti.tstart.push_back((int)ti.ek.size());
+    tf.tstart.push_back((int)tf.ek.size());
     if (bsp) {   // products: the visited k whose B_kj is stored
       products = 0;
       for (int i = 0; i < M; ++i) {
@@ -828,12 +873,13 @@ static int matmul_c1(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_sch
           for (int j = 0; j < Nc; ++j) products += bslot[(size_t)pr.first * Nc + j] >= 0;
       }
     }
-    DevBuf<int> d_ts, d_ek, d_em, d_es, d_bs;
+    DevBuf<int> d_ts, d_ek, d_em, d_es, f_ts, f_ek, f_em, f_es, d_bs;
     DevBuf<u64> D;
     int64_t max_out = 0;
     for (auto& bt : batches) max_out = std::max<int64_t>(max_out, (int64_t)bt.nr * Nc);
-    if (!upload(c, d_ts, tstart, s) || !upload(c, d_ek, ek, s) || !upload(c, d_em, emask, s) ||
-        !upload(c, d_es, eslot, s) || (bsp && !upload(c, d_bs, bslot, s)) ||
+    if (!upload(c, d_ts, ti.tstart, s) || !upload(c, d_ek, ti.ek, s) || !upload(c, d_em, ti.emask, s) ||
+        !upload(c, d_es, ti.eslot, s) || !upload(c, f_ts, tf.tstart, s) || !upload(c, f_ek, tf.ek, s) ||
+        !upload(c, f_em, tf.emask, s) || !upload(c, f_es, tf.eslot, s) || (bsp && !upload(c, d_bs, bslot, s)) ||
         !D.alloc(&c->alloc, (size_t)std::max<int64_t>(max_out, 1) * dw)) {
       rc = SFHE_E_NOMEM;
       set_error("device allocation failed");
@@ -852,6 +898,14 @@ static int matmul_c1(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_sch
       tl.nA = A->n_ct;
       tl.nB = B->n_ct;
       tl.bslot = bsp ? d_bs.ptr : nullptr;
+      tl.tile_rows = kTileRows;
+      TileList tlf = tl;
+      tlf.tstart = f_ts.ptr + bt.f0;
+      tlf.ek = f_ek.ptr;
+      tlf.emask = f_em.ptr;
+      tlf.eslot = f_es.ptr;
+      tlf.n_row_tiles = bt.fnt;
+      tlf.tile_rows = kTileRowsFp;
       const int64_t cnt = (int64_t)bt.nr * Nc;
       {
         StepTimer tm(c, s, kCatTensor);
@@ -860,7 +914,7 @@ static int matmul_c1(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_sch
         hipEvent_t f0 = c->prof_event(), f1 = c->prof_event();
         if (f0 && f1) c->prof_cat.push_back(kCatTensorFp);
         else f0 = f1 = nullptr;
-        rc = launch_tensor_tiles(c, tl, A->data.ptr, B->data.ptr, D.ptr, s, f0, f1);
+        rc = launch_tensor_tiles(c, tl, tlf, A->data.ptr, B->data.ptr, D.ptr, s, f0, f1);
         if (f0) ++tensor_fp_launches;
       }
       ++tensor_launches;
@@ -1000,6 +1054,7 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
     set_error("several values per ciphertext: use sfhe_matmul_slots");
     return SFHE_E_UNSUPPORTED;
   }
+  StreamScope scope_(c->alloc, (hipStream_t)stream);
   return matmul_c1(c, A, B, sched, (hipStream_t)stream, C, true);
   GUARD_END
 }
@@ -1059,11 +1114,27 @@ static int plain_check(const sfhe_ctx* c, const sfhe_mat* W, const sfhe_mat* B) 
   return SFHE_OK;
 }
 
+constexpr int64_t kRescaleSlice = 2048;   // outputs per rescale launch set
+
+// rescale scratch of a batch: one slice of its largest matrix
+static int64_t plain_scratch_words(const sfhe_ctx* c, int64_t max_outputs) {
+  return rescale_scratch_words(c, c->L - 1, std::max<int64_t>(1, std::min(kRescaleSlice, max_outputs)));
+}
+
 // device bytes a plaintext-weight product holds until it completes: its
-// outputs' sums (2 (lev + 1) N words each) and results (2 lev N words each)
+// outputs' sums (2 (lev + 1) N words each) and results (2 lev N words each),
+// a rescale scratch for one slice of its outputs, and at most its share of
+// the batch tables (per tile entry: the k, the row mask and 16 weights with
+// Shoup companions per prime; per tile: the start and 4-column descriptors)
 static uint64_t plain_bytes(const sfhe_ctx* c, const sfhe_mat* W, const sfhe_mat* B) {
-  const int lev = c->L - 1;
-  return (uint64_t)W->rows * B->cols * (uint64_t)(2 * (lev + 1) + 2 * lev) * c->N * sizeof(u64);
+  const int lev = c->L - 1, nl = lev + 1;
+  const uint64_t outs = (uint64_t)W->rows * B->cols;
+  const uint64_t tiles = (uint64_t)(W->rows + 15) / 16;
+  const uint64_t entries = tiles * (uint64_t)W->cols;
+  const uint64_t tables = entries * (2 * sizeof(int) + (uint64_t)nl * 16 * 2 * sizeof(u64)) +
+                          tiles * (sizeof(int) + (uint64_t)((B->cols + 3) / 4) * sizeof(int4)) + sizeof(PlainJob);
+  return outs * (uint64_t)(2 * nl + 2 * lev) * c->N * sizeof(u64) +
+         (uint64_t)plain_scratch_words(c, (int64_t)outs) * sizeof(u64) + tables;
 }
 
 // Everything the plaintext-weight launches read or write, allocated and
@@ -1090,8 +1161,6 @@ struct PlainPrep {
     C.clear();
   }
 };
-
-constexpr int64_t kRescaleSlice = 2048;   // outputs per rescale launch set
 
 // checks, tile tables, results, scratch and uploads (on stream s)
 static int plain_prepare(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, const sfhe_mat* const* Bm,
@@ -1164,6 +1233,8 @@ static int plain_prepare(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, 
   P.n_desc = (int)desc.size();
   P.products = products;
   P.outs = outs;
+  int64_t max_outs = 1;
+  for (int n = 0; n < count; ++n) max_outs = std::max<int64_t>(max_outs, (int64_t)Wm[n]->rows * Bm[n]->cols);
   P.C.assign(count, nullptr);
   for (int n = 0; n < count; ++n) {
     sfhe_mat* o = new sfhe_mat();
@@ -1181,7 +1252,7 @@ static int plain_prepare(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, 
   if (!P.D.alloc(&c->alloc, (size_t)std::max<int64_t>(outs, 1) * dw) || !upload(c, P.ts, tstart, s) ||
       !upload(c, P.ek, ek, s) || !upload(c, P.em, emask, s) || !upload(c, P.ew, ew, s) || !upload(c, P.ews, ews, s) ||
       !upload(c, P.desc, desc, s) || !upload(c, P.d_jobs, P.jobs, s) ||
-      !P.scratch.alloc(&c->alloc, (size_t)rescale_scratch_words(c, lev, kRescaleSlice))) {
+      !P.scratch.alloc(&c->alloc, (size_t)plain_scratch_words(c, max_outs))) {
     set_error("device allocation failed (the sums of every output are held at once)");
     return SFHE_E_NOMEM;
   }
@@ -1296,6 +1367,7 @@ int sfhe_matmul_plain(sfhe_ctx* c, const sfhe_mat* W, const sfhe_mat* B, void* s
   if (!C) { set_error("C is NULL"); return SFHE_E_INVALID_ARG; }
   *C = nullptr;
   if (!c || !W || !B) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  StreamScope scope_(c->alloc, (hipStream_t)stream);
   return plain_batch(c, 1, &W, &B, SFHE_PLAIN_FUSED, (hipStream_t)stream, C);
   GUARD_END
 }
@@ -1309,6 +1381,7 @@ int sfhe_matmul_plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* W
     set_error("NULL argument or count < 1");
     return SFHE_E_INVALID_ARG;
   }
+  StreamScope scope_(c->alloc, (hipStream_t)stream);
   return plain_batch(c, count, W, B, launch, (hipStream_t)stream, C);
   GUARD_END
 }
@@ -1323,9 +1396,13 @@ struct sfhe_plain_graph {
   sfhe_ctx* c = nullptr;
   PlainPrep P;
   hipStream_t cs = nullptr;       // the capture stream (default priority)
+  hipStream_t ls = nullptr;       // the stream of the last replay
+  bool replayed = false;
   hipGraph_t g = nullptr;
   hipGraphExec_t ge = nullptr;
   ~sfhe_plain_graph() {
+    // the buffers below are given back after the last replay has ended
+    if (replayed) (void)hipStreamSynchronize(ls);
     if (cs) (void)hipStreamSynchronize(cs);
     if (ge) (void)hipGraphExecDestroy(ge);
     if (g) (void)hipGraphDestroy(g);
@@ -1342,6 +1419,7 @@ int sfhe_plain_graph_create(sfhe_ctx* c, int32_t count, const sfhe_mat* const* W
   *out = nullptr;
   if (!c || !W || !B || count < 1) { set_error("NULL argument or count < 1"); return SFHE_E_INVALID_ARG; }
   hipStream_t s = (hipStream_t)stream;
+  StreamScope scope_(c->alloc, s);
   sfhe_plain_graph* G = new sfhe_plain_graph();
   G->c = c;
   int rc = plain_prepare(c, count, W, B, launch, s, G->P);
@@ -1375,10 +1453,13 @@ int sfhe_plain_graph_launch(sfhe_plain_graph* G, void* stream) {
   if (!G) { set_error("NULL graph"); return SFHE_E_INVALID_ARG; }
   sfhe_ctx* c = G->c;
   hipStream_t s = (hipStream_t)stream;
+  StreamScope scope_(c->alloc, s);
   c->prof_used = 0;
   c->prof_cat.clear();
   SFHE_HIP(hipEventRecord(c->ev0, s));
   SFHE_HIP(hipGraphLaunch(G->ge, s));
+  G->ls = s;
+  G->replayed = true;
   SFHE_HIP(hipEventRecord(c->ev1, s));
   c->stats = sfhe_stats{};
   c->stats.products = G->P.products;
@@ -1404,13 +1485,21 @@ void sfhe_plain_graph_destroy(sfhe_plain_graph* G) { delete G; }
 // A request loop over plaintext-weight products: requests queue in arrival
 // order; each step first retires the batches whose end event has passed,
 // then admits queued requests while the device bytes they hold until they
-// complete (sums and results) fit the budget, and enqueues them as one fused
-// batch on the server's stream.  Batches run in stream order, so a batch
-// admitted while another is on the device starts as soon as it ends, and the
-// host prepares the next batch meanwhile.
+// complete (sums, results, rescale scratch, tables) fit the budget, and
+// enqueues them as one fused batch on the least busy of the server's
+// streams (at most kServerStreams, the hardware queues of a process).  A
+// batch admitted while others run starts at once on another stream, so
+// batches overlap on the device; its launches first wait for the work the
+// caller enqueued on the client stream before the step (the requests'
+// encryptions).
+constexpr int kServerStreams = 4;
+
 struct sfhe_server {
   sfhe_ctx* c = nullptr;
-  hipStream_t s = nullptr;
+  hipStream_t client = nullptr;           // the caller's stream (inputs are ready in its order)
+  std::vector<hipStream_t> streams;       // the server's own, default priority
+  std::vector<int> busy;                  // running batches per stream
+  hipEvent_t epoch = nullptr;             // device-time origin of the batch intervals
   uint64_t budget = 0, in_flight = 0;
   struct Req {
     int64_t ticket;
@@ -1423,54 +1512,82 @@ struct sfhe_server {
     hipEvent_t start = nullptr, end = nullptr;
     uint64_t bytes = 0;
     int64_t products = 0;
+    int stream = 0;
   };
   struct Done {
     sfhe_mat* C;
     double ms;          // device time of the request's batch
-    int64_t batch;      // batch index
+    double t0, t1;      // its start and end, ms after the server's epoch
     int32_t batch_size;
   };
   std::deque<Req> queue;
-  std::deque<Run> running;
+  std::deque<Run> running;                // in launch order
   std::map<int64_t, Done> done;
-  int64_t next_ticket = 0, batches = 0, products = 0;
-  // move the batches whose end event has passed to `done`; wait for them all if `all`
+  int64_t next_ticket = 0, batches = 0, products = 0, overlapped = 0;
+  double last_end = -1.0;
+  // move the batches whose end event has passed to `done` (any order); wait
+  // for them all if `all`
   int retire(bool all) {
-    while (!running.empty()) {
-      Run& r = running.front();
+    for (auto it = running.begin(); it != running.end();) {
+      Run& r = *it;
       hipError_t e = all ? hipEventSynchronize(r.end) : hipEventQuery(r.end);
-      if (e == hipErrorNotReady) return SFHE_OK;
+      if (e == hipErrorNotReady) { ++it; continue; }
       if (e != hipSuccess) { set_error(hipGetErrorString(e)); return SFHE_E_DEVICE; }
-      float ms = 0;
+      float ms = 0, t0 = 0, t1 = 0;
       (void)hipEventElapsedTime(&ms, r.start, r.end);
+      (void)hipEventElapsedTime(&t0, epoch, r.start);
+      (void)hipEventElapsedTime(&t1, epoch, r.end);
       for (size_t x = 0; x < r.tickets.size(); ++x)
-        done[r.tickets[x]] = Done{r.C[x], ms, batches - (int64_t)running.size(), (int32_t)r.tickets.size()};
+        done[r.tickets[x]] = Done{r.C[x], ms, t0, t1, (int32_t)r.tickets.size()};
       in_flight -= r.bytes;
       products += r.products;
+      --busy[r.stream];
       (void)hipEventDestroy(r.start);
       (void)hipEventDestroy(r.end);
-      running.pop_front();
+      it = running.erase(it);
     }
     return SFHE_OK;
   }
   ~sfhe_server() {
     (void)retire(true);
     for (auto& d : done) delete d.second.C;
+    for (hipStream_t st : streams) (void)hipStreamDestroy(st);
+    if (epoch) (void)hipEventDestroy(epoch);
   }
 };
 
 extern "C" {
 
-int sfhe_server_create(sfhe_ctx* c, uint64_t budget_bytes, void* stream, sfhe_server** out) {
+int sfhe_server_create(sfhe_ctx* c, uint64_t budget_bytes, int32_t n_streams, void* stream, sfhe_server** out) {
   GUARD_BEGIN
   if (!out) { set_error("out is NULL"); return SFHE_E_INVALID_ARG; }
   *out = nullptr;
   if (!c || budget_bytes == 0) { set_error("NULL context or zero budget"); return SFHE_E_INVALID_ARG; }
-  sfhe_server* v = new sfhe_server();
+  if (n_streams < 1 || n_streams > kServerStreams) { set_error("n_streams must be in [1, 4]"); return SFHE_E_INVALID_ARG; }
+  std::unique_ptr<sfhe_server> v(new sfhe_server());
   v->c = c;
-  v->s = (hipStream_t)stream;
+  v->client = (hipStream_t)stream;
   v->budget = budget_bytes;
-  *out = v;
+  for (int x = 0; x < n_streams; ++x) {
+    hipStream_t st = nullptr;
+    SFHE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    v->streams.push_back(st);
+    v->busy.push_back(0);
+  }
+  SFHE_HIP(hipEventCreate(&v->epoch));
+  SFHE_HIP(hipEventRecord(v->epoch, v->streams[0]));
+  SFHE_HIP(hipEventSynchronize(v->epoch));
+  *out = v.release();
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_server_request_bytes(const sfhe_ctx* c, const sfhe_mat* W, const sfhe_mat* X, uint64_t* bytes) {
+  GUARD_BEGIN
+  if (!c || !bytes) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  const int rc = plain_check(c, W, X);
+  if (rc) return rc;
+  *bytes = plain_bytes(c, W, X);
   return SFHE_OK;
   GUARD_END
 }
@@ -1505,16 +1622,32 @@ int sfhe_server_step(sfhe_server* v, int32_t* admitted) {
     v->queue.pop_front();
   }
   if (Ws.empty()) return SFHE_OK;
+  // the least busy stream; its launches wait for the client stream's work
+  int sx = 0;
+  for (int x = 1; x < (int)v->streams.size(); ++x)
+    if (v->busy[x] < v->busy[sx]) sx = x;
+  run.stream = sx;
+  hipStream_t bs = v->streams[sx];
   run.C.assign(Ws.size(), nullptr);
-  if (hipEventCreate(&run.start) != hipSuccess || hipEventCreate(&run.end) != hipSuccess) {
+  hipEvent_t ready = nullptr;
+  if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess || hipEventCreate(&run.start) != hipSuccess ||
+      hipEventCreate(&run.end) != hipSuccess) {
     set_error("event creation failed");
     rc = SFHE_E_DEVICE;
   }
+  if (!rc && (hipEventRecord(ready, v->client) != hipSuccess || hipStreamWaitEvent(bs, ready, 0) != hipSuccess)) {
+    set_error("stream ordering failed");
+    rc = SFHE_E_DEVICE;
+  }
   int64_t launches = 0, outs = 0;
-  if (!rc)
-    rc = plain_enqueue(v->c, (int32_t)Ws.size(), Ws.data(), Xs.data(), SFHE_PLAIN_FUSED, v->s, run.C.data(), run.start,
-                       &run.products, &launches, &outs);
-  if (!rc && hipEventRecord(run.end, v->s) != hipSuccess) { set_error("event record failed"); rc = SFHE_E_DEVICE; }
+  {
+    StreamScope scope_(v->c->alloc, bs);
+    if (!rc)
+      rc = plain_enqueue(v->c, (int32_t)Ws.size(), Ws.data(), Xs.data(), SFHE_PLAIN_FUSED, bs, run.C.data(), run.start,
+                         &run.products, &launches, &outs);
+  }
+  if (!rc && hipEventRecord(run.end, bs) != hipSuccess) { set_error("event record failed"); rc = SFHE_E_DEVICE; }
+  if (ready) (void)hipEventDestroy(ready);
   if (rc) {
     // the requests stay queued, in order, for a later step
     for (size_t x = Ws.size(); x-- > 0;) v->queue.push_front(sfhe_server::Req{run.tickets[x], Ws[x], Xs[x], plain_bytes(v->c, Ws[x], Xs[x])});
@@ -1524,6 +1657,7 @@ int sfhe_server_step(sfhe_server* v, int32_t* admitted) {
     return rc;
   }
   v->in_flight += run.bytes;
+  ++v->busy[sx];
   ++v->batches;
   *admitted = (int32_t)Ws.size();
   v->running.push_back(std::move(run));
@@ -1532,20 +1666,33 @@ int sfhe_server_step(sfhe_server* v, int32_t* admitted) {
 }
 
 int sfhe_server_poll(sfhe_server* v, int64_t ticket, int32_t wait, int32_t* is_done, sfhe_mat** C, double* batch_ms,
-                     int32_t* batch_size) {
+                     int32_t* batch_size, double* start_ms, double* end_ms) {
   GUARD_BEGIN
   if (!v || !is_done || !C) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
   *is_done = 0;
   *C = nullptr;
   if (ticket < 0 || ticket >= v->next_ticket) { set_error("unknown ticket"); return SFHE_E_INVALID_ARG; }
-  int rc = v->retire(wait != 0);
+  int rc = v->retire(false);
   if (rc) return rc;
   auto it = v->done.find(ticket);
+  if (it == v->done.end() && wait) {
+    // wait for the batch that holds the ticket
+    for (auto& r : v->running)
+      if (std::find(r.tickets.begin(), r.tickets.end(), ticket) != r.tickets.end()) {
+        SFHE_HIP(hipEventSynchronize(r.end));
+        break;
+      }
+    rc = v->retire(false);
+    if (rc) return rc;
+    it = v->done.find(ticket);
+  }
   if (it == v->done.end()) return SFHE_OK;
   *is_done = 1;
   *C = it->second.C;
   if (batch_ms) *batch_ms = it->second.ms;
   if (batch_size) *batch_size = it->second.batch_size;
+  if (start_ms) *start_ms = it->second.t0;
+  if (end_ms) *end_ms = it->second.t1;
   v->done.erase(it);
   return SFHE_OK;
   GUARD_END
@@ -1596,6 +1743,7 @@ int sfhe_decrypt_matrix(sfhe_ctx* c, const sfhe_mat* m, double* out, int64_t ld,
   if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
   if (ld < m->cols) { set_error("ld < cols"); return SFHE_E_SHAPE; }
   hipStream_t s = (hipStream_t)stream;
+  StreamScope scope_(c->alloc, s);
   const int64_t nv = m->slots > 1 ? m->n_vals : m->n_ct;   // stored values
   std::vector<double> vals(nv > 0 ? nv : 1, 0.0);
   if (m->slots > 1) {
@@ -1651,6 +1799,7 @@ int sfhe_export_ct(sfhe_ctx* c, const sfhe_mat* m, int32_t i, int32_t j, uint64_
   const int64_t sl = slot_of(m, i, j);
   if (sl < 0) { set_error("element not stored by this encoding"); return SFHE_E_SHAPE; }
   hipStream_t s = (hipStream_t)stream;
+  StreamScope scope_(c->alloc, s);
   DevBuf<u64> tmp;
   if (!tmp.alloc(&c->alloc, words)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
   int rc = launch_from_chunked(c, m->data.ptr, m->n_ct, nl, 1, nullptr, sl, tmp.ptr, (int64_t)words, s);
@@ -1696,6 +1845,7 @@ int sfhe_keyswitch(sfhe_ctx* c, int32_t level, const uint64_t* d2, uint64_t* out
   if (!c->has_keys) { set_error("keygen first"); return SFHE_E_STATE; }
   if (level < 0 || level >= c->L || batch < 0) { set_error("bad level or batch"); return SFHE_E_LEVEL; }
   const int64_t nl = level + 1, N = c->N;
+  StreamScope scope_(c->alloc, (hipStream_t)stream);
   return keyswitch_batch(c, level, d2, nl * N, out, 2 * nl * N, false, batch, (hipStream_t)stream);
   GUARD_END
 }
@@ -1705,6 +1855,7 @@ int sfhe_rescale(sfhe_ctx* c, int32_t level, const uint64_t* in, uint64_t* out, 
   if (!c || !in || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
   if (level < 1 || level >= c->L || batch < 0) { set_error("bad level or batch"); return SFHE_E_LEVEL; }
   const int64_t nl = level + 1, N = c->N;
+  StreamScope scope_(c->alloc, (hipStream_t)stream);
   return rescale_batch(c, level, in, 2 * nl * N, OutLayout{out, 2 * level * N, false, 0, 0}, batch, (hipStream_t)stream);
   GUARD_END
 }
@@ -1723,6 +1874,7 @@ int sfhe_encrypt_matrix_slots(sfhe_ctx* c, const double* vals, int32_t rows, int
   if ((int)enc < 0 || (int)enc > 3) { set_error("bad encoding"); return SFHE_E_INVALID_ARG; }
   if (slots < 1 || slots > 64 || slots > c->N / 2) { set_error("slots must be in [1, min(64, N/2)]"); return SFHE_E_INVALID_ARG; }
   hipStream_t s = (hipStream_t)stream;
+  StreamScope scope_(c->alloc, s);
   sfhe_mat* m = new sfhe_mat();
   m->ctx = c;
   m->rows = rows;
@@ -1781,6 +1933,7 @@ int sfhe_rotate(sfhe_ctx* c, int32_t level, const uint64_t* in, uint64_t* out, i
   int rc = prepare_rotations(c, {(int64_t)r});
   if (rc) return rc;
   const int64_t w = (int64_t)2 * (level + 1) * c->N;
+  StreamScope scope_(c->alloc, (hipStream_t)stream);
   return rotate_batch(c, level, in, w, r, out, w, batch, (hipStream_t)stream);
   GUARD_END
 }
@@ -1794,6 +1947,7 @@ int sfhe_export_stored(sfhe_ctx* c, const sfhe_mat* m, int64_t n, uint64_t* out,
   const size_t words = (size_t)2 * nl * N;
   if (cap < words) { set_error("capacity below 2*(level+1)*N"); return SFHE_E_INVALID_ARG; }
   hipStream_t s = (hipStream_t)stream;
+  StreamScope scope_(c->alloc, s);
   DevBuf<u64> tmp;
   if (!tmp.alloc(&c->alloc, words)) { set_error("device allocation failed"); return SFHE_E_NOMEM; }
   int rc = launch_from_chunked(c, m->data.ptr, m->n_ct, nl, 1, nullptr, n, tmp.ptr, (int64_t)words, s);
@@ -1903,6 +2057,7 @@ int sfhe_matmul_slots(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_sc
   if (c->L < 4) { set_error("Algorithm 1 with the mask needs four data primes"); return SFHE_E_LEVEL; }
   if (A->scale != B->scale) { set_error("operand scales differ"); return SFHE_E_SCALE; }
   hipStream_t s = (hipStream_t)stream;
+  StreamScope scope_(c->alloc, s);
   const int N = c->N, top = c->L - 1, M = A->rows, K = A->cols, Nc = B->cols, cs = A->slots;
   // rotation keys first: their generation synchronises the device
   std::vector<int64_t> offs;

@@ -50,11 +50,30 @@ struct RescaleConst {
 };
 
 // ---- device allocation through the optional hooks ----
+// Allocation is stream-ordered: a block is taken on the stream of the call in
+// progress (`cur`, set by StreamScope at each entry point) and given back on
+// the stream it was taken on, once the last launch that uses it has been
+// enqueued there.  The allocator may hand a freed block to later work on that
+// stream at once; stream order keeps that work behind the earlier launches.
+// Without hooks the blocks come from a stream-ordered pool of the context
+// (hipMallocFromPoolAsync / hipFreeAsync), so no free waits for the device.
 struct Alloc {
   sfhe_device_hooks hooks{};
   bool has_hooks = false;
+  hipMemPool_t pool = nullptr;
+  hipStream_t cur = nullptr;
   void* get(size_t bytes);
-  void put(void* p, size_t bytes);
+  void put(void* p, size_t bytes, hipStream_t s);
+};
+
+// sets the stream that allocations of the enclosing call are ordered on
+struct StreamScope {
+  Alloc& a;
+  hipStream_t prev;
+  StreamScope(Alloc& al, hipStream_t s) : a(al), prev(al.cur) { a.cur = s; }
+  ~StreamScope() { a.cur = prev; }
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
 };
 
 template <typename T>
@@ -62,12 +81,17 @@ struct DevBuf {
   Alloc* al = nullptr;
   T* ptr = nullptr;
   size_t count = 0;
+  hipStream_t st = nullptr;   // the stream the block was taken on
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); al = o.al; ptr = o.ptr; count = o.count; o.ptr = nullptr; o.count = 0; }
+    if (this != &o) {
+      release();
+      al = o.al; ptr = o.ptr; count = o.count; st = o.st;
+      o.ptr = nullptr; o.count = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
@@ -75,11 +99,12 @@ struct DevBuf {
     release();
     al = a;
     count = n;
+    st = a->cur;
     ptr = n ? (T*)a->get(n * sizeof(T)) : nullptr;
     return n == 0 || ptr != nullptr;
   }
   void release() {
-    if (ptr && al) al->put(ptr, count * sizeof(T));
+    if (ptr && al) al->put(ptr, count * sizeof(T), st);
     ptr = nullptr;
     count = 0;
   }
@@ -222,6 +247,8 @@ int launch_tensor_gather(const sfhe_ctx* c, int lev, const u64* A, int64_t nA, c
 // (ascending), a bit mask of the tile rows that visit it and, per tile row,
 // the A ciphertext slot (or -1).
 constexpr int kTileRows = 16;
+// rows per tile of the fp64 column kernel (every wave owns all rows of one column)
+constexpr int kTileRowsFp = 8;
 struct TileList {
   const int* tstart;
   const int* ek;
@@ -233,11 +260,14 @@ struct TileList {
   int Nc;               // output columns (= B columns)
   int64_t nA, nB;       // ciphertexts stored by A and B (chunked layout)
   const int* bslot;     // [K][Nc] stored slot of B_kj, -1 if B_kj is zero; nullptr for a dense B
+  int tile_rows;        // rows per tile (eslot stride)
 };
 // D[pos * Nc + j][3][L][N] = sum over the visited k of tensor(A[row pos, k], B[k, j]);
 // the fp64 kernel's launch is bracketed by fp_start / fp_stop when non-null
-int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, const u64* B, u64* D, hipStream_t s,
-                        hipEvent_t fp_start = nullptr, hipEvent_t fp_stop = nullptr);
+// tl: tiles of kTileRows rows (the integer kernels); tl_fp: tiles of
+// kTileRowsFp rows (the fp64 column kernel)
+int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& tl_fp, const u64* A, const u64* B,
+                        u64* D, hipStream_t s, hipEvent_t fp_start = nullptr, hipEvent_t fp_stop = nullptr);
 int tensor_fp_prime_count(const sfhe_ctx* c);
 
 // ---- plaintext weights times encrypted values (ctpt.hip) ----
@@ -272,8 +302,14 @@ int launch_plain_product(const sfhe_ctx* c, const u64* B, int64_t nB, int64_t sl
 // key switch of d2 rows (batch stride d2stride), result added into out
 // (batch stride ostride, [2][nl][N]) if add_in, else written.
 // key: [dnum][2][nb][N] NTT domain, the relinearisation key when null
+// scratch (nullable): keyswitch_scratch_words(c, lev, batch) words the call
+// uses instead of allocating
 int keyswitch_batch(sfhe_ctx* c, int lev, const u64* d2, int64_t d2stride, u64* out, int64_t ostride,
-                    bool add_in, int64_t batch, hipStream_t s, const u64* key = nullptr);
+                    bool add_in, int64_t batch, hipStream_t s, const u64* key = nullptr, u64* scratch = nullptr);
+inline int64_t keyswitch_scratch_words(const sfhe_ctx* c, int lev, int64_t batch) {
+  const int64_t nl = lev + 1, ne = nl + c->alpha;
+  return batch * (nl + ne + 2 * ne + 2 * nl) * c->N;
+}
 // where rescale writes: limb-major rows (stride words apart) or ciphertexts
 // elem_base + b of a chunked matrix holding n_ct ciphertexts
 struct OutLayout {

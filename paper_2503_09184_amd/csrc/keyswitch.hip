@@ -136,15 +136,30 @@ __global__ void moddown_finish_kernel(const u64* acc, int nl, int ne, const u64*
 }
 
 int keyswitch_batch(sfhe_ctx* c, int lev, const u64* d2, int64_t d2stride, u64* out, int64_t ostride, bool add_in,
-                    int64_t batch, hipStream_t s, const u64* key) {
+                    int64_t batch, hipStream_t s, const u64* key, u64* scratch) {
   if (batch <= 0) return SFHE_OK;
   if (!key) key = c->d_rlk.ptr;
   const int N = c->N, nl = lev + 1, ne = nl + c->alpha;
-  DevBuf<u64> d2c, xbuf, acc, z;
-  if (!d2c.alloc(&c->alloc, (size_t)batch * nl * N) || !xbuf.alloc(&c->alloc, (size_t)batch * ne * N) ||
-      !acc.alloc(&c->alloc, (size_t)batch * 2 * ne * N) || !z.alloc(&c->alloc, (size_t)batch * 2 * nl * N)) {
-    set_error("keyswitch: device allocation failed");
-    return SFHE_E_NOMEM;
+  // working rows: d2 in coefficients, one raised digit, the key products
+  // over Q and P, the ModDown conversion (every word is written before it
+  // is read, so a reused scratch needs no clearing)
+  DevBuf<u64> d2c_b, xbuf_b, acc_b, z_b;
+  struct { u64* ptr; } d2c{}, xbuf{}, acc{}, z{};
+  if (scratch) {
+    d2c.ptr = scratch;
+    xbuf.ptr = d2c.ptr + (size_t)batch * nl * N;
+    acc.ptr = xbuf.ptr + (size_t)batch * ne * N;
+    z.ptr = acc.ptr + (size_t)batch * 2 * ne * N;
+  } else {
+    if (!d2c_b.alloc(&c->alloc, (size_t)batch * nl * N) || !xbuf_b.alloc(&c->alloc, (size_t)batch * ne * N) ||
+        !acc_b.alloc(&c->alloc, (size_t)batch * 2 * ne * N) || !z_b.alloc(&c->alloc, (size_t)batch * 2 * nl * N)) {
+      set_error("keyswitch: device allocation failed");
+      return SFHE_E_NOMEM;
+    }
+    d2c.ptr = d2c_b.ptr;
+    xbuf.ptr = xbuf_b.ptr;
+    acc.ptr = acc_b.ptr;
+    z.ptr = z_b.ptr;
   }
   // coefficient-domain copy of d2
   SFHE_HIP(hipMemcpy2DAsync(d2c.ptr, (size_t)nl * N * sizeof(u64), d2, (size_t)d2stride * sizeof(u64),

@@ -67,7 +67,7 @@ __global__ void tensor_gather_kernel(int nl, const u64* A, int64_t nA, const u64
 
 constexpr int kWavesPerBlock = 8;
 constexpr int kSegEntries = 128;   // tile entries held in LDS at a time
-static_assert(kTileRows == 2 * kWavesPerBlock, "each wave stages two tile rows");
+static_assert(kTileRows == 2 * kWavesPerBlock, "each wave of the block kernel stages two tile rows");
 
 struct ArithFp {   // q < 2^42: fp64 residues, Karatsuba middle term
   typedef double Val;
@@ -428,6 +428,170 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   }
 }
 
+// Column kernel (the fp64 primes): 8 waves share one 64-coefficient chunk of
+// one prime, a tile of TR output rows and 8 columns, and wave w owns column w
+// of the block for all TR rows.  Per visited k every wave multiplies the same
+// rows (those the tile's entry mask marks), so the waves reach the per-entry
+// barrier together: none idles while another works through more rows, which
+// is what a split of the rows among waves costs at unstructured sparsity.
+// The A values of the rows that visit k (with a0 + a1, the Karatsuba
+// operand, formed once by the staging wave) and the B values of the 8
+// columns are staged once per block and entry through LDS (double-buffered),
+// global loads running two entries ahead.  The tile list has TR rows per
+// tile (eslot [entries][TR]).
+template <int TR>
+struct ColsStage {
+  static constexpr int kAV = 2 * TR / kWavesPerBlock;   // A values (row, poly) each wave stages
+  u64 a[kAV];
+  u64 b0, b1;
+  int mask;
+  bool bact;
+};
+
+template <int TR, bool BSP>
+__global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const u64* A, const u64* B, u64* D,
+                                                            FpLimbs fl, DevParams dp) {
+  static_assert((2 * TR) % (2 * kWavesPerBlock) == 0, "each wave stages whole rows");
+  constexpr int kCols = kWavesPerBlock;
+  constexpr int kAV = ColsStage<TR>::kAV;
+  constexpr int kAR = kAV / 2;                       // rows each wave stages
+  __shared__ double sa[2][TR][3][64];                // a0, a1, a0 + a1 per staged row
+  __shared__ double sb[2][kCols][2][64];
+  __shared__ int2 s_km[kSegEntries];
+  __shared__ int s_es[kSegEntries][TR];
+  const int N = dp.N, L = dp.L;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int g, h, li, tbase;
+  {
+    const int64_t b = blockIdx.x;
+    const int x = (int)(b & 7);
+    int64_t rest = b >> 3;
+    g = (int)(rest % tl.n_row_tiles);
+    rest /= tl.n_row_tiles;
+    h = (int)(rest % tl.n_col_tiles);
+    rest /= tl.n_col_tiles;
+    const int chunks512 = N / 512;
+    const int c512 = (int)(rest % chunks512);
+    li = (int)(rest / chunks512);
+    tbase = (c512 * 8 + x) * 64;
+  }
+  const FpLimb& F = fl.l[li];
+  const int l = F.limb;
+  const ArithFp ar(F, dp.pr[l]);
+  const int Nc = tl.Nc;
+  const int64_t cidx = (int64_t)l * (N >> 6) + (tbase >> 6);
+  const u64* Ab = A + cidx * 2 * tl.nA * 64 + lane;
+  const u64* Bb = B + cidx * 2 * tl.nB * 64 + lane;
+  const int64_t pA = tl.nA * 64, pB = tl.nB * 64;
+  const int j = h * kCols + wave;                    // this wave's column
+  const bool jin = j < Nc;
+  const int arow = wave * kAR;                       // first row this wave stages
+  ArithFp::Acc acc[TR];
+#pragma unroll
+  for (int r = 0; r < TR; ++r) ArithFp::zero(acc[r]);
+
+  typedef ColsStage<TR> Stage;
+  const int e0 = tl.tstart[g], e1 = tl.tstart[g + 1];
+  auto fetch = [&](int x, int xend, Stage& st) {
+    st.mask = 0;
+    if (x >= xend) return;
+    const int2 km = s_km[x];
+    const int k = __builtin_amdgcn_readfirstlane(km.x);
+    st.mask = __builtin_amdgcn_readfirstlane(km.y);
+    st.b0 = st.b1 = 0;
+    st.bact = jin;
+    if (jin) {
+      int64_t bsl = (int64_t)k * Nc + j;
+      if constexpr (BSP) {
+        bsl = tl.bslot[(int64_t)k * Nc + j];
+        st.bact = bsl >= 0;
+      }
+      if (st.bact) {
+        st.b0 = Bb[bsl * 64];
+        st.b1 = Bb[bsl * 64 + pB];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kAR; ++r) {
+      if ((st.mask >> (arow + r)) & 1) {
+        const u64* ap = Ab + (int64_t)__builtin_amdgcn_readfirstlane(s_es[x][arow + r]) * 64;
+        st.a[2 * r] = ap[0];
+        st.a[2 * r + 1] = ap[pA];
+      }
+    }
+  };
+  auto put = [&](const Stage& st, int bf) {
+    const double b0 = ArithFp::load(st.b0), b1 = ArithFp::load(st.b1);
+    sb[bf][wave][0][lane] = b0;
+    sb[bf][wave][1][lane] = b1;
+#pragma unroll
+    for (int r = 0; r < kAR; ++r) {
+      if ((st.mask >> (arow + r)) & 1) {
+        const double a0 = ArithFp::load(st.a[2 * r]), a1 = ArithFp::load(st.a[2 * r + 1]);
+        sa[bf][arow + r][0][lane] = a0;
+        sa[bf][arow + r][1][lane] = a1;
+        sa[bf][arow + r][2][lane] = a0 + a1;
+      }
+    }
+  };
+  auto compute = [&](const Stage& st, int bf) {
+    if (BSP && !st.bact) return;
+    const double b0 = sb[bf][wave][0][lane], b1 = sb[bf][wave][1][lane];
+    const double bs = b0 + b1;
+#pragma unroll
+    for (int r = 0; r < TR; ++r) {
+      if ((st.mask >> r) & 1) {
+        const double a0 = sa[bf][r][0][lane], a1 = sa[bf][r][1][lane], as = sa[bf][r][2][lane];
+        ar.mac(acc[r], a0, a1, as, b0, b1, bs);
+      }
+    }
+  };
+  int cnt = 0;
+  for (int sg = e0; sg < e1; sg += kSegEntries) {
+    const int n = min(kSegEntries, e1 - sg);
+    __syncthreads();   // the previous segment's entries are no longer read
+    for (int x = threadIdx.x; x < n; x += blockDim.x) s_km[x] = make_int2(tl.ek[sg + x], tl.emask[sg + x]);
+    for (int x = threadIdx.x; x < n * TR; x += blockDim.x) s_es[x / TR][x % TR] = tl.eslot[(int64_t)sg * TR + x];
+    __syncthreads();
+    Stage sA, sB;
+    fetch(0, n, sA);
+    fetch(1, n, sB);
+    for (int x = 0; x < n; x += 2) {
+      put(sA, 0);
+      __syncthreads();
+      const Stage cA = sA;
+      fetch(x + 2, n, sA);
+      compute(cA, 0);
+      if (x + 1 < n) {
+        put(sB, 1);
+        __syncthreads();
+        const Stage cB = sB;
+        fetch(x + 3, n, sB);
+        compute(cB, 1);
+      }
+      cnt += 2;
+      if (cnt >= ArithFp::kFold) {
+        cnt = 0;
+#pragma unroll
+        for (int r = 0; r < TR; ++r) ar.fold(acc[r]);
+      }
+    }
+  }
+  if (!jin) return;
+#pragma unroll
+  for (int r = 0; r < TR; ++r) {
+    const int pos = g * TR + r;
+    if (pos >= tl.rows) continue;
+    u64* dp_ = D + ((int64_t)pos * Nc + j) * (int64_t)3 * L * N + (int64_t)l * N + tbase + lane;
+    u64 d0, d1, d2;
+    ar.final(acc[r], d0, d1, d2);
+    dp_[0] = d0;
+    dp_[(int64_t)L * N] = d1;
+    dp_[(int64_t)2 * L * N] = d2;
+  }
+}
+
 static void grid_rows(int64_t rows, unsigned& gy, unsigned& gz) {
   if (rows < 1) rows = 1;
   gy = rows < 65535 ? (unsigned)rows : 65535u;
@@ -473,14 +637,29 @@ static int launch_block(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl
   return SFHE_OK;
 }
 
+template <int TR, bool BSP>
+static int launch_cols(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl, const u64* A, const u64* B, u64* D,
+                       hipStream_t s) {
+  if (fl.n == 0) return SFHE_OK;
+  if (tl.tile_rows != TR) { set_error("tensor: tile list of another height"); return SFHE_E_INVALID_ARG; }
+  TileList t2 = tl;
+  t2.n_col_tiles = (tl.Nc + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int64_t blocks = (int64_t)fl.n * (c->N / 64) * tl.n_row_tiles * t2.n_col_tiles;
+  if (blocks > 0x7FFFFFFF) { set_error("tensor: grid too large"); return SFHE_E_INVALID_ARG; }
+  hipLaunchKernelGGL((tensor_cols_kernel<TR, BSP>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, t2, A, B,
+                     D, fl, c->dp);
+  SFHE_HIP(hipGetLastError());
+  return SFHE_OK;
+}
+
 int tensor_fp_prime_count(const sfhe_ctx* c) {
   int n = 0;
   for (int l = 0; l < c->L; ++l) n += c->primes[l] < (1ull << 42);
   return n;
 }
 
-int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, const u64* B, u64* D, hipStream_t s,
-                        hipEvent_t fp_start, hipEvent_t fp_stop) {
+int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& tl_fp, const u64* A, const u64* B,
+                        u64* D, hipStream_t s, hipEvent_t fp_start, hipEvent_t fp_stop) {
   if (tl.rows <= 0) return SFHE_OK;
   // primes below 2^42 use the fp64 residue arithmetic, the others 128-bit integers
   FpLimbs ffp{}, fint{}, f60{};
@@ -496,8 +675,8 @@ int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const u64* A, con
   }
   if (fp_start) SFHE_HIP(hipEventRecord(fp_start, s));
   const bool bsp = tl.bslot != nullptr;
-  int rc = bsp ? launch_block<ArithFp, 4, 2, true>(c, tl, ffp, A, B, D, s)
-               : launch_block<ArithFp, 4, 2, false>(c, tl, ffp, A, B, D, s);
+  int rc = bsp ? launch_cols<kTileRowsFp, true>(c, tl_fp, ffp, A, B, D, s)
+               : launch_cols<kTileRowsFp, false>(c, tl_fp, ffp, A, B, D, s);
   if (fp_stop) SFHE_HIP(hipEventRecord(fp_stop, s));
   if (!rc)
     rc = bsp ? launch_block<ArithInt, 4, 1, true>(c, tl, fint, A, B, D, s)

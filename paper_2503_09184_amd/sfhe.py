@@ -33,9 +33,21 @@ EXPORTED = [
     "sfhe_server_destroy", "sfhe_plain_graph_create", "sfhe_plain_graph_launch", "sfhe_plain_graph_result",
     "sfhe_plain_graph_destroy", "sfhe_encrypt_matrix_slots", "sfhe_matmul_slots", "sfhe_export_stored",
     "sfhe_rotate", "sfhe_ntt_tuning", "sfhe_set_ntt_variant",
+    "sfhe_probe_valu", "sfhe_server_request_bytes",
 ]
 
 PLAIN_LAUNCH = {"fused": 0, "per_product": 1}
+
+
+PROBE_KINDS = {"fp64_fma": 0, "mad_u64_u32": 1, "int32_add": 2}
+
+
+def probe_valu(kind):
+    """Sustained lane operations per second of one VALU instruction class
+    (sfhe_probe_valu): "fp64_fma", "mad_u64_u32" or "int32_add"."""
+    out = ctypes.c_double()
+    _check(lib().sfhe_probe_valu(PROBE_KINDS[kind], ctypes.byref(out)))
+    return out.value
 
 
 class SfheError(RuntimeError):
@@ -51,8 +63,8 @@ class Params(ctypes.Structure):
                 ("sigma", ctypes.c_double)]
 
 
-ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
-FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class Hooks(ctypes.Structure):
@@ -105,17 +117,20 @@ def lib():
         L.sfhe_ntt.argtypes = [vp, vp, i32, i32, i32, i32, vp]
         L.sfhe_tensor.argtypes = [vp, i32, vp, vp, vp, i32, vp]
         L.sfhe_keyswitch.argtypes = [vp, i32, vp, vp, i32, vp]
+        L.sfhe_probe_valu.argtypes = [i32, ctypes.POINTER(ctypes.c_double)]
         L.sfhe_rescale.argtypes = [vp, i32, vp, vp, i32, vp]
         L.sfhe_encode_matrix.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, i32, i64, ctypes.c_int, i32,
                                          ctypes.POINTER(vp)]
         L.sfhe_matmul_plain.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.sfhe_matmul_plain_batch.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp,
                                               ctypes.POINTER(vp)]
-        L.sfhe_server_create.argtypes = [vp, u64, vp, ctypes.POINTER(vp)]
+        L.sfhe_server_create.argtypes = [vp, u64, i32, vp, ctypes.POINTER(vp)]
         L.sfhe_server_submit.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
+        L.sfhe_server_request_bytes.argtypes = [vp, vp, vp, ctypes.POINTER(u64)]
         L.sfhe_server_step.argtypes = [vp, ctypes.POINTER(i32)]
         L.sfhe_server_poll.argtypes = [vp, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(vp),
-                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.sfhe_server_status.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(u64),
                                          ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.sfhe_server_destroy.argtypes = [vp]
@@ -222,12 +237,19 @@ class PlainGraph:
 class Server:
     """The library's request loop over plaintext-weight products (a handle)."""
 
-    def __init__(self, ctx, budget_bytes, stream=None):
+    def __init__(self, ctx, budget_bytes, stream=None, n_streams=4):
         self.ctx = ctx
         h = ctypes.c_void_p()
-        _check(lib().sfhe_server_create(ctx._h, ctypes.c_uint64(int(budget_bytes)), _stream_handle(stream),
-                                        ctypes.byref(h)))
+        _check(lib().sfhe_server_create(ctx._h, ctypes.c_uint64(int(budget_bytes)), int(n_streams),
+                                        _stream_handle(stream), ctypes.byref(h)))
         self._h = h
+        self.intervals = {}   # ticket -> (start_ms, end_ms) of its batch on the device
+
+    def request_bytes(self, W, X):
+        """Device bytes counted for request W X against the budget."""
+        out = ctypes.c_uint64()
+        _check(lib().sfhe_server_request_bytes(self.ctx._h, W.handle, X.handle, ctypes.byref(out)))
+        return out.value
 
     def submit(self, W, X):
         t = ctypes.c_int64()
@@ -240,15 +262,18 @@ class Server:
         return n.value
 
     def poll(self, ticket, wait=False):
-        """(done, result Matrix or None, batch device ms, batch size)."""
+        """(done, result Matrix or None, batch device ms, batch size); the
+        batch's device-time interval is kept in self.intervals[ticket]."""
         d = ctypes.c_int32()
         h = ctypes.c_void_p()
         ms = ctypes.c_double()
         bs = ctypes.c_int32()
+        t0, t1 = ctypes.c_double(), ctypes.c_double()
         _check(lib().sfhe_server_poll(self._h, int(ticket), 1 if wait else 0, ctypes.byref(d), ctypes.byref(h),
-                                      ctypes.byref(ms), ctypes.byref(bs)))
+                                      ctypes.byref(ms), ctypes.byref(bs), ctypes.byref(t0), ctypes.byref(t1)))
         if not d.value:
             return False, None, 0.0, 0
+        self.intervals[int(ticket)] = (t0.value, t1.value)
         return True, Matrix(self.ctx, h), ms.value, bs.value
 
     def status(self):
@@ -273,7 +298,13 @@ class Server:
 class Context:
     """Parameters, tables and keys on the current device."""
 
-    def __init__(self, log_n, q_bits, p_bits, dnum, log2_scale=40.0, sigma=3.2, torch_allocator=True):
+    def __init__(self, log_n, q_bits, p_bits, dnum, log2_scale=40.0, sigma=3.2, torch_allocator=True, hooks=None):
+        """torch_allocator: take device memory from torch's caching allocator
+        (stream-ordered: a block is taken and given back on the stream of the
+        library call that uses it); False: the library's own stream-ordered
+        pool.  hooks: optional (alloc(nbytes, stream) -> ptr or 0,
+        free(ptr, nbytes, stream)) replacing torch's allocator; stream is the
+        raw hipStream_t as an int (0 = the default stream)."""
         import torch
         self._torch = torch
         self.device = torch.cuda.current_device()
@@ -282,15 +313,25 @@ class Context:
         self._params = Params(int(log_n), len(q_bits), len(p_bits), int(dnum), qb, pb, float(log2_scale), float(sigma))
         self._keep = [qb, pb]
         hooks_p = None
-        if torch_allocator:
-            def _alloc(nbytes, user):
+        if hooks is not None or torch_allocator:
+            dev = self.device
+            if hooks is None:
+                def user_alloc(nbytes, stream):
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream))
+
+                def user_free(ptr, nbytes, stream):
+                    torch.cuda.caching_allocator_delete(ptr)
+            else:
+                user_alloc, user_free = hooks
+
+            def _alloc(nbytes, stream, user):
                 try:
-                    return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, torch.cuda.current_stream())
+                    return user_alloc(int(nbytes), int(stream or 0)) or None
                 except Exception:
                     return None
 
-            def _free(ptr, nbytes, user):
-                torch.cuda.caching_allocator_delete(ptr)
+            def _free(ptr, nbytes, stream, user):
+                user_free(ptr, int(nbytes), int(stream or 0))
 
             self._alloc_cb = ALLOC_FN(_alloc)
             self._free_cb = FREE_FN(_free)

@@ -240,8 +240,9 @@ def test_matmul_ragged_hybrid_all_outputs(torch_cuda, enc, sched):
 
 @pytest.mark.parametrize("sched", ["lazy", "per_product"])
 def test_matmul_mixed_prime_sizes_all_outputs(torch_cuda, sched):
-    """61-, 50- and 41-bit data primes: each size takes a different tensor
-    arithmetic (128-bit integer, 20-bit fp64 pieces, fp64 residues)."""
+    """61-, 50- and 41-bit data primes: the 61- and 50-bit primes take the
+    128-bit integer tensor arithmetic (neither is within 2^20 below 2^60),
+    the 41-bit prime the fp64 residues."""
     P = dict(log_n=10, q_bits=[61, 50, 41], p_bits=[61, 61], dnum=2)
     ctx, orc = pair(P, 17)
     A, B = W.operands(6, 21, 5, 0.3, 41)
@@ -336,6 +337,40 @@ def test_sweep_n8192_sampled_outputs_and_cross_encoding(torch_cuda, sparsity):
         assert np.array_equal(o, cts[n]), sample[n]
 
 
+@pytest.mark.parametrize("sched", ["lazy", "per_product"])
+@pytest.mark.parametrize("sparsity", [0.0, 0.25, 0.5, 0.75, 0.9])
+def test_sweep_n8192_every_encoding_and_schedule(torch_cuda, sparsity, sched):
+    """The sparsity sweep (N = 2^13, 64 x 64 x 64): for each sparsity and
+    schedule, A in all four encodings times a dense B, 64 sampled outputs
+    (an 8 x 8 grid with the corner rows and columns) of each encoding bit for
+    bit against the oracle's schedule of that encoding (the sparse encodings
+    against its CSR iteration, whose bits its naive and ELLPACK iterations
+    share), and every output within 1e-6 of the fp64 product."""
+    P = W.PARAMS["sweep_n8192"]
+    ctx, orc = pair(P, W.key_seed(2))
+    A, B = W.operands(64, 64, 64, sparsity, W.workload_seed(2))
+    sa, sb = W.enc_seed(2, 0), W.enc_seed(2, 1)
+    sample = _grid(4000 + int(sparsity * 100), 8, 8, 64)
+    EB = ctx.encrypt(B, "dense", sb, 1)
+    got = {}
+    for enc in ("csr", "ell", "naive", "dense"):
+        note("sweep %.2f %s %s" % (sparsity, enc, sched))
+        EA = ctx.encrypt(A, enc, sa, 0)
+        C = ctx.matmul(EA, EB, sched)
+        got[enc] = [ctx.export_ct(C, i, j) for (i, j) in sample]
+        assert np.max(np.abs(ctx.decrypt(C) - A @ B)) < 1e-6, enc
+        C.close()
+        EA.close()
+    EB.close()
+    note("sweep oracle %.2f %s" % (sparsity, sched))
+    want = {enc: orc.matmul(A, B, enc, sched, sa, sb, outputs=sample, threads=_threads(), decrypt=False)[0]
+            for enc in ("csr", "dense")}
+    for enc in ("csr", "ell", "naive", "dense"):
+        ref = want["dense" if enc == "dense" else "csr"]
+        for n, o in enumerate(got[enc]):
+            assert np.array_equal(o, ref[n]), (enc, sample[n])
+
+
 @pytest.mark.parametrize("sparsity,sched", [(0.25, "lazy"), (0.75, "lazy"), (0.5, "per_product")])
 def test_sweep_n8192_all_outputs(torch_cuda, sparsity, sched):
     """N = 2^13, 64 x 64 x 64 (CSR): every output bit-exact against the oracle
@@ -409,19 +444,59 @@ def test_realistic_128_lazy_sampled_outputs(torch_cuda, sparsity):
         assert np.array_equal(o, cts[n]), sample[n]
 
 
-def test_realistic_128_per_product_sampled_outputs(torch_cuda):
-    """The per-product schedule (relinearise and rescale every product, then
-    add) at the benchmarked size: sampled outputs match the oracle bit for bit
+def _grid(seed, n_rows, n_cols, size=128):
+    """A sample of outputs: n_rows x n_cols rows and columns drawn without
+    replacement, the first and last of each included."""
+    rng = np.random.default_rng(seed)
+    rows = sorted({0, size - 1} | set(int(x) for x in rng.choice(np.arange(1, size - 1), n_rows - 2, replace=False)))
+    cols = sorted({0, size - 1} | set(int(x) for x in rng.choice(np.arange(1, size - 1), n_cols - 2, replace=False)))
+    return [(i, j) for i in rows for j in cols]
+
+
+@pytest.mark.parametrize("sparsity,n_rows,n_cols", [(0.9, 16, 16), (0.5, 8, 8)])
+def test_realistic_128_per_product_sampled_outputs(torch_cuda, sparsity, n_rows, n_cols):
+    """The per-product schedule (Algorithm 1's order: relinearise and rescale
+    every product, then add) at the benchmarked size, with the calls the
+    bench times: 256 sampled outputs at 90% sparsity and 64 at 50% (the
+    oracle key-switches every product of them) match the oracle bit for bit,
     and every output decrypts within 1e-6."""
-    ctx, orc, A, B, sa, sb = _realistic(0.5)
-    note("realistic 128^3 per_product")
+    ctx, orc, A, B, sa, sb = _realistic(sparsity)
+    note("realistic 128^3 per_product sparsity %.2f" % sparsity)
     EB = ctx.encrypt(B, "dense", sb, 1)
     EA = ctx.encrypt(A, "csr", sa, 0)
     C = ctx.matmul(EA, EB, "per_product")
-    sample = [(0, 0), (64, 17), (127, 127)]
+    sample = _grid(2000 + int(sparsity * 100), n_rows, n_cols)
     got = [ctx.export_ct(C, i, j) for (i, j) in sample]
     dec = ctx.decrypt(C)
     assert np.max(np.abs(dec - A @ B)) < 1e-6
-    cts, _, _ = orc.matmul(A, B, "csr", "per_product", sa, sb, outputs=sample, threads=_threads())
+    C.close()
+    EA.close()
+    EB.close()
+    note("realistic per_product oracle on %d outputs" % len(sample))
+    cts, _, _ = orc.matmul(A, B, "csr", "per_product", sa, sb, outputs=sample, threads=_threads(), decrypt=False)
+    for n, o in enumerate(got):
+        assert np.array_equal(o, cts[n]), sample[n]
+
+
+@pytest.mark.parametrize("sparsity", [0.5, 0.9])
+def test_realistic_128_dense_lazy_sampled_outputs(torch_cuda, sparsity):
+    """The naive dense schedule (every k visited, encryptions of zero
+    included) on the operands of the 50% and 90% legs, as the bench times it
+    for the sparse-over-dense speed-ups: 256 sampled outputs bit-exact
+    against the oracle's dense schedule, all outputs within 1e-6."""
+    ctx, orc, A, B, sa, sb = _realistic(sparsity)
+    note("realistic 128^3 dense lazy sparsity %.2f" % sparsity)
+    EB = ctx.encrypt(B, "dense", sb, 1)
+    EA = ctx.encrypt(A, "dense", sa, 0)
+    C = ctx.matmul(EA, EB, "lazy")
+    assert ctx.last_stats().products == 128 ** 3
+    sample = _grid(3000 + int(sparsity * 100), 16, 16)
+    got = [ctx.export_ct(C, i, j) for (i, j) in sample]
+    assert np.max(np.abs(ctx.decrypt(C) - A @ B)) < 1e-6
+    C.close()
+    EA.close()
+    EB.close()
+    note("realistic dense oracle on %d outputs" % len(sample))
+    cts, _, _ = orc.matmul(A, B, "dense", "lazy", sa, sb, outputs=sample, threads=_threads(), decrypt=False)
     for n, o in enumerate(got):
         assert np.array_equal(o, cts[n]), sample[n]

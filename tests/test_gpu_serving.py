@@ -2,6 +2,8 @@
 memory and batched as they arrive give each result bit for bit as when the
 request runs alone, and match the CPU oracle.  Every call goes through the C
 ABI."""
+import time
+
 import numpy as np
 import pytest
 
@@ -23,8 +25,13 @@ def _requests(ctx):
 
 
 def _bytes(ctx, M, b):
+    """sums and results alone (a lower bound of what the server counts)"""
     L = len(ctx.primes) - ctx.alpha
     return M * b * (2 * L + 2 * (L - 1)) * ctx.n * 8
+
+
+def _counted(srv, req):
+    return srv.request_bytes(req[2], req[3])
 
 
 def _cts(ctx, C, M, b):
@@ -47,7 +54,9 @@ def test_serving_mix_equals_alone_and_oracle(torch_cuda):
         alone.append(_cts(ctx, C, REQS[n][0], REQS[n][2]))
         srv.close()
     # the mix: a budget of about two requests, requests arriving while batches run
-    budget = 2 * max(_bytes(ctx, M, b) for (M, K, b, s) in REQS)
+    probe = sfhe.Server(ctx, 1 << 40)
+    budget = 2 * max(_counted(probe, r) for r in reqs)
+    probe.close()
     srv = sfhe.Server(ctx, budget)
     tickets = [srv.submit(reqs[0][2], reqs[0][3])]
     assert srv.step() == 1
@@ -88,11 +97,80 @@ def test_serving_rejects_oversized_requests(torch_cuda):
     from paper_2503_09184_amd import sfhe
     ctx, _ = pair(HYB_SMALL, 21)
     reqs = _requests(ctx)
-    srv = sfhe.Server(ctx, _bytes(ctx, 20, 3))
+    probe = sfhe.Server(ctx, 1 << 40)
+    need = _counted(probe, reqs[0])
+    probe.close()
+    assert need > _bytes(ctx, 20, 3)                         # scratch and tables are counted too
+    srv = sfhe.Server(ctx, need)
     with pytest.raises(sfhe.SfheError) as e:
         srv.submit(reqs[2][2], reqs[2][3])                   # 33 x 5 outputs
     assert e.value.code == -7
     t = srv.submit(reqs[0][2], reqs[0][3])                   # exactly the budget
     assert srv.step() == 1
     assert srv.poll(t, wait=True)[0]
+    srv.close()
+
+
+# (M, K, b, weight sparsity) of the requests at the serving ring
+REQS15 = [(48, 14, 8, 0.5), (5, 7, 1, 0.75), (12, 14, 3, 0.9), (3, 14, 2, 0.0), (20, 7, 4, 0.5)]
+
+
+def test_serving_ring_n32768_mix_equals_alone_and_oracle(torch_cuda):
+    """The request loop at the serving ring (N = 2^15, nine data and three
+    special primes) with small layers: requests submitted while a batch runs
+    are admitted on the server's other streams and their batches overlap the
+    running one on the device (intersecting device-time intervals); each
+    request's result is the same, bit for bit, alone and in the mix; one
+    request matches the oracle on every output, another decrypts within
+    1e-6."""
+    from paper_2503_09184_amd import sfhe
+    ctx, orc = pair(W.PARAMS["serving_n32768"], 22)
+    reqs = []
+    for n, (M, K, b, s) in enumerate(REQS15):
+        Wt, X = W.operands(M, K, b, s, 500 + n)
+        reqs.append((Wt, X, ctx.encode_weights(Wt, "csr", 40), ctx.encrypt(X, "dense", 600 + n, 1)))
+    alone = []
+    for n, (Wt, X, Wp, EX) in enumerate(reqs):
+        note("n15 serving alone %d" % n)
+        srv = sfhe.Server(ctx, 1 << 40)
+        t = srv.submit(Wp, EX)
+        assert srv.step() == 1
+        done, C, _, bs = srv.poll(t, wait=True)
+        assert done and bs == 1
+        alone.append(_cts(ctx, C, REQS15[n][0], REQS15[n][2]))
+        C.close()
+        srv.close()
+    budget = 3 * max(_counted(srv, r) for r in reqs)
+    srv = sfhe.Server(ctx, budget)
+    tickets = [srv.submit(reqs[0][2], reqs[0][3])]
+    assert srv.step() == 1
+    tickets += [srv.submit(Wp, EX) for (_, _, Wp, EX) in reqs[1:]]
+    note("n15 serving mix")
+    results = {}
+    t_end = time.time() + 60.0
+    while len(results) < len(tickets) and time.time() < t_end:
+        srv.step()
+        for n, t in enumerate(tickets):
+            if n not in results:
+                done, C, _, _ = srv.poll(t)
+                if done:
+                    results[n] = C
+        time.sleep(0.001)
+    assert len(results) == len(tickets)
+    assert srv.status()["batches"] >= 2
+    iv = sorted(set(srv.intervals[t] for t in tickets))
+    note("n15 batch intervals %s" % iv)
+    assert len(iv) >= 2
+    assert any(iv[x][0] < iv[y][1] and iv[y][0] < iv[x][1] for x in range(len(iv)) for y in range(x + 1, len(iv))), \
+        "no two batches overlapped on the device"
+    for n, (M, K, b, s) in enumerate(REQS15):
+        for x, y in zip(_cts(ctx, results[n], M, b), alone[n]):
+            assert np.array_equal(x, y), n
+    note("n15 serving oracle")
+    cts, _, _ = orc.matmul_plain(reqs[2][0], reqs[2][1], "csr", 602, 40, threads=8)
+    for x, y in zip(_cts(ctx, results[2], 12, 3), cts):
+        assert np.array_equal(x, y)
+    assert np.max(np.abs(ctx.decrypt(results[0]) - reqs[0][0] @ reqs[0][1])) < 1e-6
+    for C in results.values():
+        C.close()
     srv.close()

@@ -410,6 +410,36 @@ def test_matmul_decrypts_to_fp64_product_toy(sched):
     assert np.max(np.abs(vals - ref.ravel())) < 1e-3        # the paper's epsilon
 
 
+def test_lazy_sums_of_many_products_on_61_bit_primes():
+    """The LAZY schedule's 128-bit sums, folded modulo q every 32 products,
+    on 61-bit primes (each term close to 2^122) with 130 products per output:
+    every output equals the same output built from the oracle's one-product
+    steps (each tensor product reduced on its own, the 130 of them added
+    modulo q in numpy, then one key switch and one rescale), and decrypts
+    within the noise bound of the fp64 value (Sec. 3.3: the product of a row
+    and a column summed before one relinearisation)."""
+    P = dict(log_n=10, q_bits=[61, 61], p_bits=[61], dnum=2)
+    o = make(P, seed=31)
+    K = 130
+    rng = np.random.default_rng(32)
+    A = rng.uniform(0.1, 1.0, (2, K)) * rng.choice([-1.0, 1.0], (2, K))   # no zeros: every k visited
+    B = rng.uniform(0.1, 1.0, (K, 2)) * rng.choice([-1.0, 1.0], (K, 2))
+    sa, sb = 33, 34
+    outs = [(0, 0), (1, 1)]
+    cts, vals, _ = o.matmul(A, B, "csr", "lazy", sa, sb, outputs=outs, threads=2)
+    lev = o.L - 1
+    q = np.array([int(x) for x in o.q[:o.L]], dtype=np.uint64)[None, :, None]
+    assert int(q.max()) > 2 ** 60
+    for n, (i, j) in enumerate(outs):
+        acc = np.zeros((3, o.L, o.n), dtype=np.uint64)
+        for k in range(K):
+            d = o.tensor(lev, o.encrypt(A[i, k], sa, 0, i, k), o.encrypt(B[k, j], sb, 1, k, j))
+            acc = (acc + d) % q                      # both below 2^61: no wrap
+        ct = (acc[:2] + o.keyswitch(lev, acc[2])) % q
+        assert np.array_equal(cts[n], o.rescale(lev, ct)), (i, j)
+        assert abs(vals[n] - float(A[i] @ B[:, j])) <= _bound(o, K, True), (i, j)
+
+
 def test_matmul_error_small_ring_within_1e6():
     """With a 2^40 result scale the decrypted error is far below 1e-6."""
     o = make(SMALL, seed=5)
