@@ -22,9 +22,11 @@
  * Ownership: handles are opaque and owned by the library; the caller destroys
  * them.  Host arrays passed in are borrowed for the duration of the call only.
  * Device memory comes from the optional allocation hooks (a caching
- * allocator), otherwise from hipMalloc.  A `stream` argument is a hipStream_t
- * (NULL = the default stream); work is enqueued on it and calls that return
- * host data synchronise it.
+ * allocator), otherwise from a stream-ordered memory pool of the context;
+ * either way a block is taken and given back in the order of the stream of
+ * the call that uses it (sfhe_device_hooks).  A `stream` argument is a
+ * hipStream_t (NULL = the default stream); work is enqueued on it and calls
+ * that return host data synchronise it.
  *
  * The library plays both parties for benchmarking: the secret key lives in
  * the context and never leaves it.
@@ -122,7 +124,9 @@ typedef struct {
   int64_t n_ciphertexts;    /* stored ciphertexts (ELL padding included) */
   int64_t nnz;              /* nonzero elements (the values that are encrypted) */
   int32_t ell_width;        /* ELL only, else 0 */
-  uint64_t device_bytes;    /* ciphertext bytes held on the device (Sec. 4.4 memory) */
+  uint64_t device_bytes;    /* ciphertext bytes held on the device: the memory of the
+                               ciphertexts Sec. 4.1 records, compared across encodings
+                               in Sec. 4.6 */
   int32_t slots;            /* values per ciphertext (the chunk size c of Sec. 3.2) */
 } sfhe_mat_info;
 
@@ -145,9 +149,12 @@ typedef struct {
   int32_t reserved;
 } sfhe_stats;
 
-/* Create a context: generate the primes, twiddle and conversion tables and
- * upload them.  hooks may be NULL.  Fails with SFHE_E_PARAMS for an invalid
- * set and SFHE_E_DEVICE when no gfx950 device is usable. */
+/* Create a context for the RNS CKKS scheme of Sec. 3.1 (ring degree N, the
+ * modulus chain of data primes, the special primes of key switching, the
+ * encoding scale): generate the primes, twiddle and conversion tables and
+ * upload them.  This is the context set-up Sec. 4.1 keeps outside the timed
+ * region.  hooks may be NULL.  Fails with SFHE_E_PARAMS for an invalid set
+ * and SFHE_E_DEVICE when no gfx950 device is usable. */
 int sfhe_ctx_create(const sfhe_params* params, const sfhe_device_hooks* hooks, sfhe_ctx** out);
 void sfhe_ctx_destroy(sfhe_ctx* ctx);
 
@@ -156,12 +163,18 @@ void sfhe_ctx_destroy(sfhe_ctx* ctx);
 int sfhe_ctx_n(const sfhe_ctx* ctx, int32_t* n);
 int sfhe_ctx_primes(const sfhe_ctx* ctx, uint64_t* out, size_t cap);
 
-/* Generate the ternary secret and the relinearisation key from seed (keys
- * stay on the device).  Must precede any encryption. */
+/* Generate the scheme's keys (Sec. 3.1): the ternary secret and the
+ * relinearisation key every ciphertext product needs (Algorithm 1's
+ * relinearise step), from seed; the keys stay on the device.  Part of the
+ * set-up outside the timed region (Sec. 4.1).  Must precede any
+ * encryption. */
 int sfhe_keygen(sfhe_ctx* ctx, uint64_t seed);
 
-/* Encrypt a rows x cols row-major fp64 matrix (leading dimension ld >= cols)
- * with the given encoding: one secret-key ciphertext per stored element,
+/* Encrypt an operand matrix (Sec. 4.1: the operands are encrypted before the
+ * timed product; Sec. 3.2: chunk size 1, one value per ciphertext; Sec.
+ * 3.3.2: the encoding decides which elements are stored, the structure stays
+ * plaintext).  A rows x cols row-major fp64 matrix (leading dimension ld >=
+ * cols) with the given encoding: one secret-key ciphertext per stored element,
  * value in slot 0, at the top level with scale 2^log2_scale.  Element (i, j)
  * draws its randomness from (seed, operand_id, i, j) only, so an element has
  * the same ciphertext under every encoding.  An element is zero iff it
@@ -182,12 +195,16 @@ int sfhe_encrypt_matrix(sfhe_ctx* ctx, const double* vals, int32_t rows, int32_t
 int sfhe_matmul(sfhe_ctx* ctx, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched,
                 void* stream, sfhe_mat** C);
 
-/* Decrypt and decode every element to out (row-major, leading dimension ld).
- * Elements that an encoding does not store decrypt to 0.0. */
+/* Decrypt and decode every element to out (row-major, leading dimension ld),
+ * the step after the product with which Sec. 4.5 compares the encrypted
+ * result against the plaintext one.  Elements that an encoding does not
+ * store decrypt to 0.0. */
 int sfhe_decrypt_matrix(sfhe_ctx* ctx, const sfhe_mat* m, double* out, int64_t ld, void* stream);
 
 /* Copy one stored ciphertext of element (i, j), in the coefficient domain
- * with residues in [0, q), to host memory: out[2][level+1][N].  cap is the
+ * with residues in [0, q), to host memory: out[2][level+1][N] (for checking
+ * a result word for word against another implementation of the same
+ * scheme, beside the decrypted comparison of Sec. 4.5).  cap is the
  * capacity in entries.  An element the encoding does not store is an error
  * (SFHE_E_SHAPE); an ELL padding slot is not addressable. */
 int sfhe_export_ct(sfhe_ctx* ctx, const sfhe_mat* m, int32_t i, int32_t j, uint64_t* out, size_t cap,
@@ -356,6 +373,10 @@ void sfhe_server_destroy(sfhe_server* srv);
 int sfhe_probe_valu(int32_t kind, double* lane_ops_per_s);
 
 int sfhe_matrix_info(const sfhe_mat* m, sfhe_mat_info* out);
+/* Statistics of the last product call: its device time from hipEvents
+ * around the multiplication alone (Sec. 4.1: execution time excluding
+ * context set-up, encryption and decryption), products, relinearisations
+ * and outputs; waits for the call's events. */
 int sfhe_last_stats(const sfhe_ctx* ctx, sfhe_stats* out);
 
 /* Per-step device timing of sfhe_matmul (off by default): with on != 0 the
