@@ -489,8 +489,10 @@ def main():
     ap.add_argument("--sparsity", type=float, default=0.5)
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--only", default="", help="comma list of extra legs to run (default all): "
-                    "s90,dense,ell,naive,per_product,both,sweep,slots,serve,ctpt,cpu,peaks")
+                    "s90,dense,ell,naive,per_product,both,sweep,slots,serve,ctpt,cpu,peaks,kstune")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--ctpt-count", type=int, default=32,
+                    help="products in the uneven plaintext-weight batch (32 is the workload; fewer for profiling)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size kernel for "
@@ -621,6 +623,18 @@ def main():
                                                                  legs[name]["ms_min"], stx.products))
         return stx
 
+    # the key-switch slice the tuner chose (at the first product) against
+    # the untuned default of 2048 outputs per launch group
+    ks_slice, ks_us = ctx.ks_tuning()
+    ks_tuning = {"slice_in_use": ks_slice, "us_per_output_by_slice": {str(k): v for k, v in ks_us.items()}}
+    if run("kstune") and ks_slice not in (0, 2048):
+        ctx.set_ks_slice(2048)
+        tt, _, _, _ = timed(ctx, torch, EA, EB, "lazy", max(2, min(args.steps, 5)), 1)
+        ctx.set_ks_slice(-1)
+        ks_tuning["untuned_2048_ms_median"] = float(np.median(tt))
+        ks_tuning["tuned_ms_median"] = float(np.median(times))
+        log("key-switch slice: tuned %d (%.2f ms/step) vs 2048 (%.2f ms/step)" %
+            (ks_slice, float(np.median(times)), float(np.median(tt))))
     legs["lazy_csr_50"] = {"ms": ms, "ms_median": float(np.median(times)), "ms_min": float(np.min(times)),
                            "steps": len(times), "products": int(products), "ct_mults_per_s": value,
                            "keyswitches": int(st.keyswitches)}
@@ -695,7 +709,7 @@ def main():
              legs["serving"]["ctpt_mults_per_s"], legs["serving"]["batches"]))
     if run("ctpt"):
         log("plaintext weights x encrypted values: uneven batch of 32 products")
-        legs["ctpt_uneven_batch"] = ctpt_leg(torch, sfhe, W)
+        legs["ctpt_uneven_batch"] = ctpt_leg(torch, sfhe, W, args.ctpt_count)
         log("ctpt: %d products in %.1f ms, %.4g ct-pt mults/s" %
             (legs["ctpt_uneven_batch"]["products"], legs["ctpt_uneven_batch"]["ms"],
              legs["ctpt_uneven_batch"]["ctpt_mults_per_s"]))
@@ -756,6 +770,7 @@ def main():
         "measured_peaks": peaks,
         "ntt_designs": {d: {"used": ctx.ntt_tuning(d == "inverse")[0], "us_per_row": ctx.ntt_tuning(d == "inverse")[1]}
                         for d in ("forward", "inverse")},
+        "ks_slice_tuning": ks_tuning,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

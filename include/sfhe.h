@@ -210,6 +210,27 @@ int sfhe_decrypt_matrix(sfhe_ctx* ctx, const sfhe_mat* m, double* out, int64_t l
 int sfhe_export_ct(sfhe_ctx* ctx, const sfhe_mat* m, int32_t i, int32_t j, uint64_t* out, size_t cap,
                    void* stream);
 
+/* The launches of one LAZY sfhe_matmul (the batched form: every product of
+ * the layer summed per output, one relinearisation and rescale per output,
+ * Sec. 3.3 with Algorithm 1's steps) captured into a HIP graph for replay.
+ * Creation prepares the tile lists, lazy sums, key-switch scratch and the
+ * result once (on stream), runs the product once outside the capture (this
+ * tunes the key-switch slice if the context has not yet), then captures its
+ * launches on a stream of its own.  Each sfhe_matmul_graph_launch replays
+ * them on stream, recomputing the result from the current contents of A and
+ * B (which must outlive the graph); sfhe_last_stats reports the replay's
+ * device time and counts.  The result belongs to the graph (read-only
+ * handle from sfhe_matmul_graph_result, for export and decryption) and is
+ * freed with it; destroying the graph waits for its last replay.  Replays
+ * of one graph must not overlap.  Errors as sfhe_matmul; matrices with
+ * several values per ciphertext are SFHE_E_UNSUPPORTED. */
+typedef struct sfhe_matmul_graph sfhe_matmul_graph;
+int sfhe_matmul_graph_create(sfhe_ctx* ctx, const sfhe_mat* A, const sfhe_mat* B, void* stream,
+                             sfhe_matmul_graph** out);
+int sfhe_matmul_graph_launch(sfhe_matmul_graph* graph, void* stream);
+int sfhe_matmul_graph_result(const sfhe_matmul_graph* graph, const sfhe_mat** out);
+void sfhe_matmul_graph_destroy(sfhe_matmul_graph* graph);
+
 /* ---- Several values per ciphertext (Sec. 3.2, Algorithm 1) -------------
  * A matrix is a list of ciphertexts ("chunks") holding up to c = slots
  * values each.  The stored values of an encoding (all rows x cols entries
@@ -419,6 +440,20 @@ int sfhe_ntt_tuning(const sfhe_ctx* ctx, int32_t inverse, int32_t* variant, doub
 /* Use design `variant` for direction `inverse` (SFHE_E_UNSUPPORTED if it does
  * not apply to the ring); -1 returns to the measured choice. */
 int sfhe_set_ntt_variant(sfhe_ctx* ctx, int32_t inverse, int32_t variant);
+
+/* Key-switch slice tuning (the fused key switch and rescale at N = 2^14):
+ * the outputs of a LAZY product are key-switched in slices, one launch of
+ * each fused kernel per slice.  Small slices keep the working rows (about
+ * 60 rows of N words per output) in the Infinity Cache, large ones fill the
+ * GPU better; the first LAZY product of a context with at least 1024
+ * outputs times every candidate (128 .. 4096 outputs) on its first outputs
+ * and keeps the fastest.  *slice: the size in use (0: not tuned yet);
+ * sizes[0..cap) / us_per_output[0..cap): the candidates and their measured
+ * microseconds per output (-1: not measured). */
+int sfhe_ks_tuning(const sfhe_ctx* ctx, int32_t* slice, int32_t* sizes, double* us_per_output, int32_t cap);
+/* Use `slice` outputs per launch group (a power of two in [64, 4096]); 0
+ * tunes again at the next LAZY product, -1 returns to the tuned size. */
+int sfhe_set_ks_slice(sfhe_ctx* ctx, int32_t slice);
 
 /* In-place negacyclic NTT (inverse = 0) or inverse NTT (inverse = 1) of
  * `batch` groups of n_limbs rows laid out [batch][n_limbs][N]; row l of a

@@ -60,7 +60,7 @@ struct StepTimer {
   hipStream_t s;
   hipEvent_t stop = nullptr;
   StepTimer(sfhe_ctx* ctx, hipStream_t st, int cat) : c(ctx), s(st) {
-    if (!c->profiling) return;
+    if (!c->profiling || cat < 0) return;   // cat < 0: no events (launches under graph capture)
     hipEvent_t a = c->prof_event(), b = c->prof_event();
     if (!a || !b) return;
     (void)hipEventRecord(a, s);
@@ -622,6 +622,27 @@ int sfhe_set_ntt_variant(sfhe_ctx* c, int32_t inverse, int32_t variant) {
   return SFHE_OK;
 }
 
+int sfhe_ks_tuning(const sfhe_ctx* c, int32_t* slice, int32_t* sizes, double* us_per_output, int32_t cap) {
+  if (!c || !slice) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  *slice = c->ks_slice;
+  for (int x = 0; x < kKsNumCandidates && x < cap; ++x) {
+    if (sizes) sizes[x] = (int32_t)kKsCandidates[x];
+    if (us_per_output) us_per_output[x] = c->ks_us[x];
+  }
+  return SFHE_OK;
+}
+
+int sfhe_set_ks_slice(sfhe_ctx* c, int32_t slice) {
+  if (!c) { set_error("NULL context"); return SFHE_E_INVALID_ARG; }
+  if (slice == -1) { c->ks_slice = c->ks_tuned_slice; return SFHE_OK; }
+  if (slice != 0 && (slice < 64 || slice > 4096 || (slice & (slice - 1)))) {
+    set_error("slice must be a power of two in [64, 4096], 0 (tune again) or -1 (the tuned choice)");
+    return SFHE_E_INVALID_ARG;
+  }
+  c->ks_slice = slice;
+  return SFHE_OK;
+}
+
 int sfhe_set_profiling(sfhe_ctx* c, int32_t on) {
   if (!c) { set_error("NULL context"); return SFHE_E_INVALID_ARG; }
   c->profiling = on != 0;
@@ -633,6 +654,8 @@ void sfhe_ctx_destroy(sfhe_ctx* c) {
   // work of any stream may still read the context's tables and keys
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+  if (c->tune_ev0) (void)hipEventDestroy(c->tune_ev0);
+  if (c->tune_ev1) (void)hipEventDestroy(c->tune_ev1);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   hipMemPool_t pool = c->alloc.pool;
@@ -755,12 +778,280 @@ void sfhe_mat_destroy(sfhe_mat* m) { delete m; }
 
 }  // extern "C"
 
+// Key-switch slice tuning (N = 2^14, fused kernels): the key switch and
+// rescale of the first n outputs of a LAZY product's sums D are run once per
+// candidate slice size, each timed with an event pair on s, and the fastest
+// is kept in c->ks_slice; c->ks_us records microseconds per output.  Every
+// run writes the same ciphertexts, so *done = n outputs are finished.
+static int tune_ks_slice(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout ol, int64_t n, hipStream_t s,
+                         int64_t* done) {
+  *done = 0;
+  if (!c->tune_ev0) {
+    SFHE_HIP(hipEventCreate(&c->tune_ev0));
+    SFHE_HIP(hipEventCreate(&c->tune_ev1));
+  }
+  DevBuf<u64> scr;
+  if (!scr.alloc(&c->alloc, (size_t)keyswitch_rescale_n14_scratch_words(c, lev, std::min<int64_t>(n, kKsCandidates[kKsNumCandidates - 1])))) {
+    set_error("device allocation failed for the key-switch tuning scratch");
+    return SFHE_E_NOMEM;
+  }
+  double best = 0;
+  int best_s = 0;
+  for (int x = 0; x < kKsNumCandidates; ++x) {
+    c->ks_us[x] = -1;
+    const int64_t S = kKsCandidates[x];
+    if (S > n) continue;
+    for (int rep = 0; rep < 2; ++rep) {   // the first run warms the caches and the code objects
+      SFHE_HIP(hipEventRecord(c->tune_ev0, s));
+      for (int64_t o0 = 0; o0 < n; o0 += S) {
+        OutLayout o = ol;
+        o.elem_base += o0;
+        const int rc = keyswitch_rescale_n14(c, lev, D + o0 * dw, dw, o, std::min(S, n - o0), s, scr.ptr);
+        if (rc) return rc;
+      }
+      SFHE_HIP(hipEventRecord(c->tune_ev1, s));
+      SFHE_HIP(hipEventSynchronize(c->tune_ev1));
+    }
+    float ms = 0;
+    SFHE_HIP(hipEventElapsedTime(&ms, c->tune_ev0, c->tune_ev1));
+    c->ks_us[x] = 1e3 * ms / (double)n;
+    if (best_s == 0 || c->ks_us[x] < best) { best = c->ks_us[x]; best_s = (int)S; }
+  }
+  c->ks_slice = best_s;
+  c->ks_tuned_slice = best_s;
+  *done = n;
+  return SFHE_OK;
+}
+
+// ---------------------------------------------------------------- LAZY product
+// Everything the LAZY product's launches read or write, prepared before
+// them, so that the launches alone can also be captured into a graph: the
+// result, the tile lists of every batch (one per tile height: kTileRows for
+// the 128-bit integer kernel, kTileRowsFp for the fp64 column kernel,
+// kTileRowsInt60 for the carry-save column kernel), the lazy sums D, the
+// key-switch scratch, the B slot table and the outputs with no product.
+struct LazyPrep {
+  struct Batch { int r0, nr, t0, nt, f0, fnt, q0, qnt; };
+  sfhe_mat* out = nullptr;
+  const sfhe_mat *A = nullptr, *B = nullptr;
+  std::vector<Batch> batches;
+  DevBuf<int> d_ts, d_ek, d_em, d_es, f_ts, f_ek, f_em, f_es, q_ts, q_ek, q_em, q_es, d_bs;
+  DevBuf<u64> D, kss;
+  DevBuf<int64_t> d_empty;
+  int64_t n_empty = 0, products = 0, keyswitches = 0, max_out = 0, ks_slice = 2048, dw = 0;
+  int lev = 0, Nc = 0;
+  bool bsp = false, fused = false;
+  ~LazyPrep() { delete out; }
+};
+
+// host tables and uploads of a LAZY product (P.out holds the allocated result)
+static int lazy_prepare(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, hipStream_t s, LazyPrep& P) {
+  const int N = c->N, lev = A->level, nl = lev + 1, M = A->rows, Nc = B->cols;
+  P.A = A;
+  P.B = B;
+  P.lev = lev;
+  P.Nc = Nc;
+  std::vector<int64_t> visits(M);
+  for (int i = 0; i < M; ++i) visits[i] = row_visits(A, i);
+  // a sparse right operand: products whose B_kj is zero are skipped too
+  P.bsp = B->enc != SFHE_ENC_DENSE;
+  std::vector<int> bslot;
+  if (P.bsp) value_slots(B, bslot);
+  // outputs with no product are trivial zeros
+  std::vector<int64_t> empty;
+  for (int i = 0; i < M; ++i)
+    if (visits[i] == 0)
+      for (int j = 0; j < Nc; ++j) empty.push_back((int64_t)i * Nc + j);
+  P.n_empty = (int64_t)empty.size();
+  // batches: runs of consecutive non-empty rows whose degree-2 sums D fit a
+  // 32 GiB budget (all 128 rows at N = 2^14, L = 5); one tensor launch per
+  // batch, then key switching and rescaling in slices
+  const int64_t dw = (int64_t)3 * nl * N;
+  P.dw = dw;
+  const int64_t d_budget = (int64_t)32 << 30;
+  int rb = (int)std::max<int64_t>(kTileRows, d_budget / ((int64_t)std::max(Nc, 1) * dw * 8) / kTileRows * kTileRows);
+  P.fused = keyswitch_rescale_n14_supported(c);
+  // outputs per key-switch launch group: the fused N = 2^14 kernels take
+  // the tuned slice, the others 2048
+  P.ks_slice = P.fused && c->ks_slice > 0 ? c->ks_slice : 2048;
+  // tile lists: for every tile of TR consecutive rows of a batch, the
+  // ascending union of the rows' visited k, each with the mask of the rows
+  // that visit it and their A slots
+  struct Tiles {
+    int TR;
+    std::vector<int> tstart, ek, emask, eslot;
+  };
+  Tiles ti{kTileRows, {}, {}, {}, {}}, tf{kTileRowsFp, {}, {}, {}, {}}, tq{kTileRowsInt60, {}, {}, {}, {}};
+  std::vector<std::pair<int, int64_t>> pairs;
+  std::vector<int> kmask(A->cols);
+  std::vector<int> kslot((size_t)A->cols * std::max(kTileRows, std::max(kTileRowsFp, kTileRowsInt60)));
+  // tiles of rows r0 .. r0 + nr - 1 into T; returns the tile count
+  auto add_tiles = [&](Tiles& T, int r0, int nr) {
+    const int TR = T.TR;
+    int nt = 0;
+    for (int g = 0; g * TR < nr; ++g) {
+      std::fill(kmask.begin(), kmask.end(), 0);
+      for (int r = 0; r < TR && g * TR + r < nr; ++r) {
+        row_pairs(A, r0 + g * TR + r, pairs);
+        for (auto& pr : pairs) {
+          kmask[pr.first] |= 1 << r;
+          kslot[(size_t)pr.first * TR + r] = (int)pr.second;
+        }
+      }
+      T.tstart.push_back((int)T.ek.size());
+      for (int k = 0; k < A->cols; ++k) {
+        if (!kmask[k]) continue;
+        T.ek.push_back(k);
+        T.emask.push_back(kmask[k]);
+        for (int r = 0; r < TR; ++r) T.eslot.push_back((kmask[k] >> r) & 1 ? kslot[(size_t)k * TR + r] : -1);
+      }
+      ++nt;
+    }
+    return nt;
+  };
+  for (int i = 0; i < M;) {
+    if (visits[i] == 0) { ++i; continue; }
+    int nr = 0;
+    while (i + nr < M && nr < rb && visits[i + nr] > 0) ++nr;
+    LazyPrep::Batch bt{i, nr, (int)ti.tstart.size(), 0, (int)tf.tstart.size(), 0, (int)tq.tstart.size(), 0};
+    bt.nt = add_tiles(ti, i, nr);
+    bt.fnt = add_tiles(tf, i, nr);
+    bt.qnt = add_tiles(tq, i, nr);
+    P.batches.push_back(bt);
+    for (int r = 0; r < nr; ++r) P.products += visits[i + r] * (int64_t)Nc;
+    P.keyswitches += (int64_t)nr * Nc;
+    i += nr;
+  }
+  ti.tstart.push_back((int)ti.ek.size());
+  tf.tstart.push_back((int)tf.ek.size());
+  tq.tstart.push_back((int)tq.ek.size());
+  if (P.bsp) {   // products: the visited k whose B_kj is stored
+    P.products = 0;
+    for (int i = 0; i < M; ++i) {
+      if (visits[i] == 0) continue;
+      row_pairs(A, i, pairs);
+      for (auto& pr : pairs)
+        for (int j = 0; j < Nc; ++j) P.products += bslot[(size_t)pr.first * Nc + j] >= 0;
+    }
+  }
+  for (auto& bt : P.batches) P.max_out = std::max<int64_t>(P.max_out, (int64_t)bt.nr * Nc);
+  if (!upload(c, P.d_ts, ti.tstart, s) || !upload(c, P.d_ek, ti.ek, s) || !upload(c, P.d_em, ti.emask, s) ||
+      !upload(c, P.d_es, ti.eslot, s) || !upload(c, P.f_ts, tf.tstart, s) || !upload(c, P.f_ek, tf.ek, s) ||
+      !upload(c, P.f_em, tf.emask, s) || !upload(c, P.f_es, tf.eslot, s) || !upload(c, P.q_ts, tq.tstart, s) ||
+      !upload(c, P.q_ek, tq.ek, s) || !upload(c, P.q_em, tq.emask, s) || !upload(c, P.q_es, tq.eslot, s) ||
+      (P.bsp && !upload(c, P.d_bs, bslot, s)) || !upload(c, P.d_empty, empty, s) ||
+      !P.D.alloc(&c->alloc, (size_t)std::max<int64_t>(P.max_out, 1) * dw)) {
+    set_error("device allocation failed");
+    return SFHE_E_NOMEM;
+  }
+  return SFHE_OK;
+}
+
+// the launches of a LAZY product: per batch the tensor step and the key
+// switch and rescale in slices, then the trivial zeros.  With events the
+// steps are bracketed for sfhe_last_stats (not under graph capture); with
+// tune, a context whose slice is not tuned yet tunes it on the first batch.
+static int lazy_launch(sfhe_ctx* c, LazyPrep& P, hipStream_t s, bool events, bool tune, int64_t* tensor_launches,
+                       int64_t* tensor_fp_launches) {
+  const int N = c->N, lev = P.lev, nl = lev + 1, Nc = P.Nc;
+  const int64_t dw = P.dw;
+  sfhe_mat* out = P.out;
+  int rc = SFHE_OK;
+  for (size_t bi = 0; bi < P.batches.size() && !rc; ++bi) {
+    const LazyPrep::Batch& bt = P.batches[bi];
+    TileList tl;
+    tl.tstart = P.d_ts.ptr + bt.t0;
+    tl.ek = P.d_ek.ptr;
+    tl.emask = P.d_em.ptr;
+    tl.eslot = P.d_es.ptr;
+    tl.n_row_tiles = bt.nt;
+    tl.n_col_tiles = 0;
+    tl.rows = bt.nr;
+    tl.Nc = Nc;
+    tl.nA = P.A->n_ct;
+    tl.nB = P.B->n_ct;
+    tl.bslot = P.bsp ? P.d_bs.ptr : nullptr;
+    tl.tile_rows = kTileRows;
+    TileList tlf = tl;
+    tlf.tstart = P.f_ts.ptr + bt.f0;
+    tlf.ek = P.f_ek.ptr;
+    tlf.emask = P.f_em.ptr;
+    tlf.eslot = P.f_es.ptr;
+    tlf.n_row_tiles = bt.fnt;
+    tlf.tile_rows = kTileRowsFp;
+    TileList tlq = tl;
+    tlq.tstart = P.q_ts.ptr + bt.q0;
+    tlq.ek = P.q_ek.ptr;
+    tlq.emask = P.q_em.ptr;
+    tlq.eslot = P.q_es.ptr;
+    tlq.n_row_tiles = bt.qnt;
+    tlq.tile_rows = kTileRowsInt60;
+    const int64_t cnt = (int64_t)bt.nr * Nc;
+    if (events) {
+      StepTimer tm(c, s, kCatTensor);
+      // the fp64 tensor launch is always bracketed (two events per step):
+      // its duration is the dominant kernel's time in every timed product
+      hipEvent_t f0 = c->prof_event(), f1 = c->prof_event();
+      if (f0 && f1) c->prof_cat.push_back(kCatTensorFp);
+      else f0 = f1 = nullptr;
+      rc = launch_tensor_tiles(c, tl, tlf, tlq, P.A->data.ptr, P.B->data.ptr, P.D.ptr, s, f0, f1);
+      if (f0) ++*tensor_fp_launches;
+    } else {
+      rc = launch_tensor_tiles(c, tl, tlf, tlq, P.A->data.ptr, P.B->data.ptr, P.D.ptr, s);
+    }
+    ++*tensor_launches;
+    int64_t o_start = 0;
+    if (tune && P.fused && !rc && c->ks_slice == 0 && cnt >= kKsTuneMin) {
+      // first LAZY product of the context: time the key switch of the first
+      // outputs with each candidate slice and keep the fastest (the outputs
+      // are written identically by every candidate)
+      rc = tune_ks_slice(c, lev, P.D.ptr, dw, OutLayout{out->data.ptr, 0, true, out->n_ct, (int64_t)bt.r0 * Nc},
+                         std::min<int64_t>(cnt, kKsCandidates[kKsNumCandidates - 1]), s, &o_start);
+      if (c->ks_slice > 0) P.ks_slice = c->ks_slice;
+    }
+    // the key-switch (and rescale) scratch of one slice, allocated once
+    const int64_t sl = std::min(P.ks_slice, P.max_out);
+    const int64_t ks_words = P.fused ? keyswitch_rescale_n14_scratch_words(c, lev, sl) : keyswitch_scratch_words(c, lev, sl);
+    if (!rc && !P.kss.ptr) {
+      StreamScope scope_(c->alloc, s);
+      // rescale_batch's scratch: the last prime's rows and the lifted rows
+      const int64_t rs_words = P.fused ? 0 : sl * 2 * N * (1 + lev);
+      if (!P.kss.alloc(&c->alloc, (size_t)(ks_words + rs_words))) {
+        rc = SFHE_E_NOMEM;
+        set_error("device allocation failed for the key-switch scratch");
+      }
+    }
+    for (int64_t o0 = o_start; o0 < cnt && !rc; o0 += P.ks_slice) {
+      const int64_t n = std::min(P.ks_slice, cnt - o0);
+      u64* Ds = P.D.ptr + o0 * dw;
+      const OutLayout ol{out->data.ptr, 0, true, out->n_ct, (int64_t)bt.r0 * Nc + o0};
+      if (P.fused) {   // fused transforms (key switch and rescale together)
+        if (events) {
+          StepTimer tm(c, s, kCatKeyswitch);
+          rc = keyswitch_rescale_n14(c, lev, Ds, dw, ol, n, s, P.kss.ptr);
+        } else {
+          rc = keyswitch_rescale_n14(c, lev, Ds, dw, ol, n, s, P.kss.ptr);
+        }
+        continue;
+      }
+      {
+        StepTimer tm(c, s, events ? kCatKeyswitch : -1);
+        rc = keyswitch_batch(c, lev, Ds + (int64_t)2 * nl * N, dw, Ds, dw, true, n, s, nullptr, P.kss.ptr);
+      }
+      if (!rc) {
+        StepTimer tm(c, s, events ? kCatRescale : -1);
+        rc = rescale_batch(c, lev, Ds, dw, ol, n, s, P.kss.ptr + ks_words);
+      }
+    }
+  }
+  if (!rc && P.n_empty) rc = launch_zero_outputs(c, out->data.ptr, out->n_ct, lev, P.d_empty.ptr, P.n_empty, s);
+  return rc;
+}
+
 // The one-value-per-ciphertext product (chunk size 1).  With timed, the
 // call's device time is bracketed by the context's event pair.
-static int matmul_c1(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched, hipStream_t s,
-                     sfhe_mat** C, bool timed) {
-  if (!C) { set_error("C is NULL"); return SFHE_E_INVALID_ARG; }
-  *C = nullptr;
+// operand checks of a one-value-per-ciphertext product
+static int matmul_check(const sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched) {
   if (!c || !A || !B) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
   if (A->ctx != c || B->ctx != c) { set_error("matrices belong to another context"); return SFHE_E_INVALID_ARG; }
   if (A->plain || B->plain) { set_error("plaintext weights: use sfhe_matmul_plain"); return SFHE_E_UNSUPPORTED; }
@@ -772,24 +1063,41 @@ static int matmul_c1(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_sch
   if (A->level != c->L - 1) { set_error("operands must be at the top level"); return SFHE_E_LEVEL; }
   if (A->level < 1) { set_error("no prime left to rescale"); return SFHE_E_LEVEL; }
   if (A->scale != B->scale) { set_error("operand scales differ"); return SFHE_E_SCALE; }
-  const int N = c->N, lev = A->level, nl = lev + 1, M = A->rows, Nc = B->cols;
-  if (timed) SFHE_HIP(hipEventRecord(c->ev0, s));
+  return SFHE_OK;
+}
+
+// the (uninitialised) DENSE result of A B: one level lower, scale^2 / q_level
+static sfhe_mat* new_product(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B) {
+  const int lev = A->level;
   sfhe_mat* out = new sfhe_mat();
   out->ctx = c;
-  out->rows = M;
-  out->cols = Nc;
+  out->rows = A->rows;
+  out->cols = B->cols;
   out->level = lev - 1;
   out->scale = A->scale * B->scale / (double)c->primes[lev];
   out->enc = SFHE_ENC_DENSE;
-  out->n_ct = (int64_t)M * Nc;
+  out->n_ct = (int64_t)A->rows * B->cols;
   out->nnz = out->n_ct;
-  const int64_t ctw = (int64_t)2 * lev * N;   // words per output ciphertext
-  int rc = SFHE_OK;
-  if (!out->data.alloc(&c->alloc, (size_t)out->n_ct * ctw)) {
+  out->n_vals = out->n_ct;
+  if (!out->data.alloc(&c->alloc, (size_t)out->n_ct * 2 * lev * c->N)) {
     delete out;
     set_error("device allocation failed for the result");
-    return SFHE_E_NOMEM;
+    return nullptr;
   }
+  return out;
+}
+
+static int matmul_c1(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched, hipStream_t s,
+                     sfhe_mat** C, bool timed) {
+  if (!C) { set_error("C is NULL"); return SFHE_E_INVALID_ARG; }
+  *C = nullptr;
+  int rc = matmul_check(c, A, B, sched);
+  if (rc) return rc;
+  const int N = c->N, lev = A->level, nl = lev + 1, M = A->rows, Nc = B->cols;
+  if (timed) SFHE_HIP(hipEventRecord(c->ev0, s));
+  sfhe_mat* out = new_product(c, A, B);
+  if (!out) return SFHE_E_NOMEM;
+  const int64_t ctw = (int64_t)2 * lev * N;   // words per output ciphertext
   std::vector<int64_t> visits(M);
   for (int i = 0; i < M; ++i) visits[i] = row_visits(A, i);
   // a sparse right operand: products whose B_kj is zero are skipped too
@@ -806,138 +1114,16 @@ static int matmul_c1(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_sch
     if (visits[i] == 0)
       for (int j = 0; j < Nc; ++j) empty.push_back((int64_t)i * Nc + j);
   if (sched == SFHE_SCHED_LAZY) {
-    // batches: runs of consecutive non-empty rows whose degree-2 sums D fit a
-    // 32 GiB budget (all 128 rows at N = 2^14, L = 5); one tensor launch per
-    // batch, then key switching and rescaling in slices of ~2048 outputs
-    const int64_t dw = (int64_t)3 * nl * N;
-    const int64_t d_budget = (int64_t)32 << 30;
-    int rb = (int)std::max<int64_t>(kTileRows, d_budget / ((int64_t)std::max(Nc, 1) * dw * 8) / kTileRows * kTileRows);
-    const int64_t ks_slice = std::max<int64_t>(1, 2048);
-    // tile lists: for every tile of TR consecutive rows of a batch, the
-    // ascending union of the rows' visited k, each with the mask of the rows
-    // that visit it and their A slots; one list of kTileRows-row tiles (the
-    // integer kernels) and one of kTileRowsFp-row tiles (the fp64 kernel)
-    struct Tiles {
-      int TR;
-      std::vector<int> tstart, ek, emask, eslot;
-    };
-    struct Batch { int r0, nr, t0, nt, f0, fnt; };
-    std::vector<Batch> batches;
-    Tiles ti{kTileRows, {}, {}, {}, {}}, tf{kTileRowsFp, {}, {}, {}, {}};
-    std::vector<std::pair<int, int64_t>> pairs;
-    std::vector<int> kmask(A->cols);
-    std::vector<int> kslot((size_t)A->cols * std::max(kTileRows, kTileRowsFp));
-    // tiles of rows r0 .. r0 + nr - 1 into T; returns the tile count
-    auto add_tiles = [&](Tiles& T, int r0, int nr) {
-      const int TR = T.TR;
-      int nt = 0;
-      for (int g = 0; g * TR < nr; ++g) {
-        std::fill(kmask.begin(), kmask.end(), 0);
-        for (int r = 0; r < TR && g * TR + r < nr; ++r) {
-          row_pairs(A, r0 + g * TR + r, pairs);
-          for (auto& pr : pairs) {
-            kmask[pr.first] |= 1 << r;
-            kslot[(size_t)pr.first * TR + r] = (int)pr.second;
-          }
-        }
-        T.tstart.push_back((int)T.ek.size());
-        for (int k = 0; k < A->cols; ++k) {
-          if (!kmask[k]) continue;
-          T.ek.push_back(k);
-          T.emask.push_back(kmask[k]);
-          for (int r = 0; r < TR; ++r) T.eslot.push_back((kmask[k] >> r) & 1 ? kslot[(size_t)k * TR + r] : -1);
-        }
-        ++nt;
-      }
-      return nt;
-    };
-    for (int i = 0; i < M;) {
-      if (visits[i] == 0) { ++i; continue; }
-      int nr = 0;
-      while (i + nr < M && nr < rb && visits[i + nr] > 0) ++nr;
-      Batch bt{i, nr, (int)ti.tstart.size(), 0, (int)tf.tstart.size(), 0};
-      bt.nt = add_tiles(ti, i, nr);
-      bt.fnt = add_tiles(tf, i, nr);
-      batches.push_back(bt);
-      for (int r = 0; r < nr; ++r) products += visits[i + r] * (int64_t)Nc;
-      i += nr;
-    }
-    ti.tstart.push_back((int)ti.ek.size());
-    tf.tstart.push_back((int)tf.ek.size());
-    if (bsp) {   // products: the visited k whose B_kj is stored
-      products = 0;
-      for (int i = 0; i < M; ++i) {
-        if (visits[i] == 0) continue;
-        row_pairs(A, i, pairs);
-        for (auto& pr : pairs)
-          for (int j = 0; j < Nc; ++j) products += bslot[(size_t)pr.first * Nc + j] >= 0;
-      }
-    }
-    DevBuf<int> d_ts, d_ek, d_em, d_es, f_ts, f_ek, f_em, f_es, d_bs;
-    DevBuf<u64> D;
-    int64_t max_out = 0;
-    for (auto& bt : batches) max_out = std::max<int64_t>(max_out, (int64_t)bt.nr * Nc);
-    if (!upload(c, d_ts, ti.tstart, s) || !upload(c, d_ek, ti.ek, s) || !upload(c, d_em, ti.emask, s) ||
-        !upload(c, d_es, ti.eslot, s) || !upload(c, f_ts, tf.tstart, s) || !upload(c, f_ek, tf.ek, s) ||
-        !upload(c, f_em, tf.emask, s) || !upload(c, f_es, tf.eslot, s) || (bsp && !upload(c, d_bs, bslot, s)) ||
-        !D.alloc(&c->alloc, (size_t)std::max<int64_t>(max_out, 1) * dw)) {
-      rc = SFHE_E_NOMEM;
-      set_error("device allocation failed");
-    }
-    for (size_t bi = 0; bi < batches.size() && !rc; ++bi) {
-      const Batch& bt = batches[bi];
-      TileList tl;
-      tl.tstart = d_ts.ptr + bt.t0;
-      tl.ek = d_ek.ptr;
-      tl.emask = d_em.ptr;
-      tl.eslot = d_es.ptr;
-      tl.n_row_tiles = bt.nt;
-      tl.n_col_tiles = 0;
-      tl.rows = bt.nr;
-      tl.Nc = Nc;
-      tl.nA = A->n_ct;
-      tl.nB = B->n_ct;
-      tl.bslot = bsp ? d_bs.ptr : nullptr;
-      tl.tile_rows = kTileRows;
-      TileList tlf = tl;
-      tlf.tstart = f_ts.ptr + bt.f0;
-      tlf.ek = f_ek.ptr;
-      tlf.emask = f_em.ptr;
-      tlf.eslot = f_es.ptr;
-      tlf.n_row_tiles = bt.fnt;
-      tlf.tile_rows = kTileRowsFp;
-      const int64_t cnt = (int64_t)bt.nr * Nc;
-      {
-        StepTimer tm(c, s, kCatTensor);
-        // the fp64 tensor launch is always bracketed (two events per step):
-        // its duration is the dominant kernel's time in every timed product
-        hipEvent_t f0 = c->prof_event(), f1 = c->prof_event();
-        if (f0 && f1) c->prof_cat.push_back(kCatTensorFp);
-        else f0 = f1 = nullptr;
-        rc = launch_tensor_tiles(c, tl, tlf, A->data.ptr, B->data.ptr, D.ptr, s, f0, f1);
-        if (f0) ++tensor_fp_launches;
-      }
-      ++tensor_launches;
-      for (int64_t o0 = 0; o0 < cnt && !rc; o0 += ks_slice) {
-        const int64_t n = std::min(ks_slice, cnt - o0);
-        u64* Ds = D.ptr + o0 * dw;
-        const OutLayout ol{out->data.ptr, 0, true, out->n_ct, (int64_t)bt.r0 * Nc + o0};
-        if (keyswitch_rescale_n14_supported(c)) {   // fused transforms (key switch and rescale together)
-          StepTimer tm(c, s, kCatKeyswitch);
-          rc = keyswitch_rescale_n14(c, lev, Ds, dw, ol, n, s);
-          continue;
-        }
-        {
-          StepTimer tm(c, s, kCatKeyswitch);
-          rc = keyswitch_batch(c, lev, Ds + (int64_t)2 * nl * N, dw, Ds, dw, true, n, s);
-        }
-        if (!rc) {
-          StepTimer tm(c, s, kCatRescale);
-          rc = rescale_batch(c, lev, Ds, dw, ol, n, s);
-        }
-      }
-      keyswitches += cnt;
-    }
+    LazyPrep P;
+    P.out = out;   // P owns the result until it is handed over
+    out = nullptr;
+    rc = lazy_prepare(c, A, B, s, P);
+    if (!rc) rc = lazy_launch(c, P, s, true, true, &tensor_launches, &tensor_fp_launches);
+    products = P.products;
+    keyswitches = P.keyswitches;
+    empty.clear();   // the trivial zeros are part of the LAZY launches
+    out = P.out;
+    P.out = nullptr;
   } else {
     // Algorithm 1 order: every product is relinearised and rescaled, then summed
     if (!rc) rc = launch_zero(out->data.ptr, out->n_ct * ctw, s);
@@ -1387,6 +1573,105 @@ int sfhe_matmul_plain_batch(sfhe_ctx* c, int32_t count, const sfhe_mat* const* W
 }
 
 // ---------------------------------------------------------------- graphs
+}  // extern "C"
+
+// a LAZY ct x ct product captured once into a HIP graph: its tile lists,
+// lazy sums, key-switch scratch and result stay allocated, and every replay
+// recomputes the result from the current contents of A and B
+struct sfhe_matmul_graph {
+  sfhe_ctx* c = nullptr;
+  LazyPrep P;
+  hipStream_t cs = nullptr;       // the capture stream (default priority)
+  hipStream_t ls = nullptr;       // the stream of the last replay
+  bool replayed = false;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  int64_t launches = 0;
+  ~sfhe_matmul_graph() {
+    // the buffers of P are given back after the last replay has ended
+    if (replayed) (void)hipStreamSynchronize(ls);
+    if (cs) (void)hipStreamSynchronize(cs);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
+
+extern "C" {
+
+int sfhe_matmul_graph_create(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, void* stream,
+                             sfhe_matmul_graph** out) {
+  GUARD_BEGIN
+  if (!out) { set_error("out is NULL"); return SFHE_E_INVALID_ARG; }
+  *out = nullptr;
+  int rc = matmul_check(c, A, B, SFHE_SCHED_LAZY);
+  if (rc) return rc;
+  if (A->slots > 1 || B->slots > 1) { set_error("several values per ciphertext: not a graph product"); return SFHE_E_UNSUPPORTED; }
+  hipStream_t s = (hipStream_t)stream;
+  StreamScope scope_(c->alloc, s);
+  std::unique_ptr<sfhe_matmul_graph> G(new sfhe_matmul_graph());
+  G->c = c;
+  G->P.out = new_product(c, A, B);
+  if (!G->P.out) return SFHE_E_NOMEM;
+  rc = lazy_prepare(c, A, B, s, G->P);
+  if (rc) return rc;
+  SFHE_HIP(hipStreamSynchronize(s));
+  SFHE_HIP(hipStreamCreate(&G->cs));
+  // one run outside the capture: kernel attributes, the key-switch slice
+  // (tuned here if the context has not tuned it yet) and its scratch
+  int64_t tl = 0, fl = 0;
+  rc = lazy_launch(c, G->P, G->cs, false, true, &tl, &fl);
+  if (rc) return rc;
+  SFHE_HIP(hipStreamSynchronize(G->cs));
+  G->launches = tl;
+  if (hipStreamBeginCapture(G->cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    set_error("stream capture failed");
+    return SFHE_E_DEVICE;
+  }
+  rc = lazy_launch(c, G->P, G->cs, false, false, &tl, &fl);
+  const hipError_t e = hipStreamEndCapture(G->cs, &G->g);
+  if (rc) return rc;
+  if (e != hipSuccess) { set_error(hipGetErrorString(e)); return SFHE_E_DEVICE; }
+  if (hipGraphInstantiate(&G->ge, G->g, nullptr, nullptr, 0) != hipSuccess) {
+    set_error("graph instantiation failed");
+    return SFHE_E_DEVICE;
+  }
+  *out = G.release();
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_matmul_graph_launch(sfhe_matmul_graph* G, void* stream) {
+  GUARD_BEGIN
+  if (!G) { set_error("NULL graph"); return SFHE_E_INVALID_ARG; }
+  sfhe_ctx* c = G->c;
+  hipStream_t s = (hipStream_t)stream;
+  c->prof_used = 0;
+  c->prof_cat.clear();
+  SFHE_HIP(hipEventRecord(c->ev0, s));
+  SFHE_HIP(hipGraphLaunch(G->ge, s));
+  G->ls = s;
+  G->replayed = true;
+  SFHE_HIP(hipEventRecord(c->ev1, s));
+  c->stats = sfhe_stats{};
+  c->stats.products = G->P.products;
+  c->stats.keyswitches = G->P.keyswitches;
+  c->stats.outputs = G->P.out->n_ct;
+  c->stats.tensor_launches = G->launches;
+  c->stats.tensor_fp_primes = tensor_fp_prime_count(c);
+  c->stats_pending = true;
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_matmul_graph_result(const sfhe_matmul_graph* G, const sfhe_mat** out) {
+  if (!G || !out) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
+  *out = G->P.out;
+  return SFHE_OK;
+}
+
+void sfhe_matmul_graph_destroy(sfhe_matmul_graph* G) { delete G; }
+
 }  // extern "C"
 
 // a plaintext-weight batch captured once into a HIP graph: its tables, sums,

@@ -137,6 +137,12 @@ struct sfhe_ctx {
   // not apply to the ring
   int ntt_var[2] = {0, 0}, ntt_tuned[2] = {0, 0};
   double ntt_us[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
+  // outputs per fused key-switch launch group (N = 2^14): in use (0 = tune
+  // at the next LAZY product), as tuned, and the microseconds per output
+  // measured for each candidate (-1: not measured)
+  int ks_slice = 0, ks_tuned_slice = 0;
+  double ks_us[6] = {-1, -1, -1, -1, -1, -1};
+  hipEvent_t tune_ev0 = nullptr, tune_ev1 = nullptr;
   // keys
   bool has_keys = false;
   sfhe::DevBuf<sfhe::u64> d_s;           // secret, NTT domain [nb][N]
@@ -186,6 +192,12 @@ struct sfhe_mat {
 };
 
 namespace sfhe {
+
+// candidate key-switch slices (outputs per launch group) and the smallest
+// product whose first batch is large enough to tune on
+constexpr int64_t kKsCandidates[6] = {128, 256, 512, 1024, 2048, 4096};
+constexpr int kKsNumCandidates = 6;
+constexpr int64_t kKsTuneMin = 1024;
 
 // Storage layout of an encrypted matrix: residue t of poly p (0, 1) of prime
 // i of stored ciphertext e sits at ((i * (N/64) + t/64) * 2 + p) * n_ct * 64
@@ -247,8 +259,11 @@ int launch_tensor_gather(const sfhe_ctx* c, int lev, const u64* A, int64_t nA, c
 // (ascending), a bit mask of the tile rows that visit it and, per tile row,
 // the A ciphertext slot (or -1).
 constexpr int kTileRows = 16;
-// rows per tile of the fp64 column kernel (every wave owns all rows of one column)
+// rows per tile of the column kernels (every wave owns all rows of one
+// column): fp64 residues (3 sums per output) and the carry-save sums of the
+// primes 2^60 - c (9 sums per output)
 constexpr int kTileRowsFp = 8;
+constexpr int kTileRowsInt60 = 4;
 struct TileList {
   const int* tstart;
   const int* ek;
@@ -264,10 +279,12 @@ struct TileList {
 };
 // D[pos * Nc + j][3][L][N] = sum over the visited k of tensor(A[row pos, k], B[k, j]);
 // the fp64 kernel's launch is bracketed by fp_start / fp_stop when non-null
-// tl: tiles of kTileRows rows (the integer kernels); tl_fp: tiles of
-// kTileRowsFp rows (the fp64 column kernel)
-int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& tl_fp, const u64* A, const u64* B,
-                        u64* D, hipStream_t s, hipEvent_t fp_start = nullptr, hipEvent_t fp_stop = nullptr);
+// tl: tiles of kTileRows rows (the 128-bit integer kernel); tl_fp: tiles of
+// kTileRowsFp rows (the fp64 column kernel); tl_i60: tiles of kTileRowsInt60
+// rows (the carry-save column kernel of the primes 2^60 - c)
+int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& tl_fp, const TileList& tl_i60,
+                        const u64* A, const u64* B, u64* D, hipStream_t s, hipEvent_t fp_start = nullptr,
+                        hipEvent_t fp_stop = nullptr);
 int tensor_fp_prime_count(const sfhe_ctx* c);
 
 // ---- plaintext weights times encrypted values (ctpt.hip) ----
@@ -328,7 +345,11 @@ inline int64_t rescale_scratch_words(const sfhe_ctx* c, int lev, int64_t batch) 
 // N = 2^14 only: Rescale((d0, d1) + KeySwitch(d2)) for n lazy sums D[b]
 // (stride dw words; rows d0, d1, d2 of lev + 1 primes, NTT domain) in four
 // fused transform kernels; the result goes to out (NTT domain, lev primes)
-int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s);
+// scratch (nullable): keyswitch_rescale_n14_scratch_words(c, lev, n) words
+// used instead of allocating (every word is written before it is read)
+int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s,
+                          u64* scratch = nullptr);
+int64_t keyswitch_rescale_n14_scratch_words(const sfhe_ctx* c, int lev, int64_t n);
 // N = 2^14 only: Rescale((d0, d1)) for n sums D[b] (stride dw words, rows d0,
 // d1 of lev + 1 primes, NTT domain) in two transform kernels
 int rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s,

@@ -670,8 +670,34 @@ int rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, i
   return SFHE_OK;
 }
 
+// rows of each working buffer per output, in allocation order: y, ext,
+// accQ, part, yP, r, w
+static void ks14_rows(const sfhe_ctx* c, int lev, bool rescale, int64_t rows[7]) {
+  const int nl = lev + 1, ne = nl + c->alpha;
+  int next = 0;
+  for (int j = 0; j < c->dnum; ++j) {
+    const int lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, nl);
+    if (lo >= hi) break;
+    next += ne - (hi - lo);
+  }
+  rows[0] = nl;
+  rows[1] = next;
+  rows[2] = 2 * nl;
+  rows[3] = 2 * c->alpha;
+  rows[4] = 2 * c->alpha;
+  rows[5] = 2;
+  rows[6] = 2 * (rescale ? lev : nl);
+}
+
+int64_t keyswitch_rescale_n14_scratch_words(const sfhe_ctx* c, int lev, int64_t n) {
+  int64_t rows[7], t = 0;
+  ks14_rows(c, lev, true, rows);
+  for (int x = 0; x < 7; ++x) t += rows[x];
+  return t * n * kN;
+}
+
 static int ks14_run(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, const u64* key,
-                    const u64* key_s, bool rescale, hipStream_t s) {
+                    const u64* key_s, bool rescale, hipStream_t s, u64* scratch = nullptr) {
   if (n <= 0) return SFHE_OK;
   if (!keyswitch_rescale_n14_supported(c)) {
     set_error("fused key switch: N = 2^14, 1 <= alpha <= 4 and dnum <= 4 only");
@@ -693,25 +719,34 @@ static int ks14_run(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout ou
     set_error("key switch: slice too large");
     return SFHE_E_INVALID_ARG;
   }
-  DevBuf<u64> y, ext, accQ, part, yP, r, w;
-  if (!y.alloc(&c->alloc, (size_t)n * nl * kN) || !ext.alloc(&c->alloc, (size_t)n * next * kN) ||
-      !accQ.alloc(&c->alloc, (size_t)n * 2 * nl * kN) || !part.alloc(&c->alloc, (size_t)n * 2 * c->alpha * kN) ||
-      !yP.alloc(&c->alloc, (size_t)n * 2 * c->alpha * kN) || !r.alloc(&c->alloc, (size_t)n * 2 * kN) ||
-      !w.alloc(&c->alloc, (size_t)n * 2 * (rescale ? lev : nl) * kN)) {
-    set_error("key switch: device allocation failed");
-    return SFHE_E_NOMEM;
+  // working rows: from the caller's scratch (ks14_rows order), else allocated
+  int64_t rows[7];
+  ks14_rows(c, lev, rescale, rows);
+  DevBuf<u64> bufs[7];
+  u64* ptr[7];
+  for (int x = 0; x < 7; ++x) {
+    if (scratch) {
+      ptr[x] = scratch;
+      scratch += (size_t)n * rows[x] * kN;
+    } else {
+      if (!bufs[x].alloc(&c->alloc, (size_t)n * rows[x] * kN)) {
+        set_error("key switch: device allocation failed");
+        return SFHE_E_NOMEM;
+      }
+      ptr[x] = bufs[x].ptr;
+    }
   }
   Ks14Args a;
   a.D = D;
   a.dw = dw;
-  a.y = y.ptr;
-  a.ext = ext.ptr;
+  a.y = ptr[0];
+  a.ext = ptr[1];
   a.next = next;
-  a.accQ = accQ.ptr;
-  a.part = part.ptr;
-  a.yP = yP.ptr;
-  a.r = r.ptr;
-  a.w = w.ptr;
+  a.accQ = ptr[2];
+  a.part = ptr[3];
+  a.yP = ptr[4];
+  a.r = ptr[5];
+  a.w = ptr[6];
   a.rlk = key;
   a.rlk_s = key_s;
   a.mu = c->d_modup.ptr + (size_t)lev * c->dnum;
@@ -728,8 +763,9 @@ static int ks14_run(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout ou
   }
 }
 
-int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s) {
-  return ks14_run(c, lev, D, dw, out, n, c->d_rlk.ptr, c->d_rlk_s.ptr, true, s);
+int keyswitch_rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, hipStream_t s,
+                          u64* scratch) {
+  return ks14_run(c, lev, D, dw, out, n, c->d_rlk.ptr, c->d_rlk_s.ptr, true, s, scratch);
 }
 
 int keyswitch_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, int64_t n, const u64* key,

@@ -71,6 +71,7 @@ static_assert(kTileRows == 2 * kWavesPerBlock, "each wave of the block kernel st
 
 struct ArithFp {   // q < 2^42: fp64 residues, Karatsuba middle term
   typedef double Val;
+  static constexpr bool kSum = true;   // uses a0 + a1 (Karatsuba)
   struct Acc {
     double d0, d2, ss;   // sums of a0 b0, a1 b1, (a0 + a1)(b0 + b1)
   };
@@ -114,6 +115,7 @@ __device__ __forceinline__ void mac_wide(U128& acc, u64 a, u64 b) {
 
 struct ArithInt {   // q < 2^61: 128-bit integer sums, Karatsuba middle term
   typedef u64 Val;
+  static constexpr bool kSum = true;
   struct Acc {
     U128 d0, d2, ss;   // sums of a0 b0, a1 b1, (a0 + a1)(b0 + b1)
   };
@@ -159,6 +161,7 @@ __device__ __forceinline__ u64 madw(u32 a, u32 b, u64 acc) { return (u64)a * b +
 
 struct ArithInt60 {
   typedef u64 Val;   // (x mod 2^30) | (x >> 30) << 32
+  static constexpr bool kSum = false;
   struct Sums {
     u64 L, M, H;
   };
@@ -431,32 +434,36 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
 // Column kernel (the fp64 primes): 8 waves share one 64-coefficient chunk of
 // one prime, a tile of TR output rows and 8 columns, and wave w owns column w
 // of the block for all TR rows.  Per visited k every wave multiplies the same
-// rows (those the tile's entry mask marks), so the waves reach the per-entry
-// barrier together: none idles while another works through more rows, which
-// is what a split of the rows among waves costs at unstructured sparsity.
-// The A values of the rows that visit k (with a0 + a1, the Karatsuba
-// operand, formed once by the staging wave) and the B values of the 8
-// columns are staged once per block and entry through LDS (double-buffered),
-// global loads running two entries ahead.  The tile list has TR rows per
-// tile (eslot [entries][TR]).
+// rows (those the tile's entry mask marks), so the waves reach each barrier
+// together: none idles while another works through more rows, which is what
+// a split of the rows among waves costs at unstructured sparsity.
+//
+// Entries go in pairs.  The A values of the rows that visit the pair's two k
+// (with a0 + a1, the Karatsuba operand, formed once by the staging wave:
+// wave w stages row w) are staged through LDS, double-buffered, with one
+// barrier per pair.  B needs no exchange: wave w is the only user of column
+// w, so it loads B[k][j] straight into registers.  Global loads run one pair
+// (two entries) ahead.  The tile list has TR rows per tile (eslot
+// [entries][TR]).
 template <int TR>
-struct ColsStage {
-  static constexpr int kAV = 2 * TR / kWavesPerBlock;   // A values (row, poly) each wave stages
+struct ColsEntry {
+  static constexpr int kAV = 2 * TR / kWavesPerBlock < 2 ? 2 : 2 * TR / kWavesPerBlock;   // A values (row, poly) a staging wave loads
   u64 a[kAV];
   u64 b0, b1;
   int mask;
   bool bact;
 };
 
-template <int TR, bool BSP>
+template <typename Arith, int TR, bool BSP>
 __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const u64* A, const u64* B, u64* D,
                                                             FpLimbs fl, DevParams dp) {
-  static_assert((2 * TR) % (2 * kWavesPerBlock) == 0, "each wave stages whole rows");
+  typedef typename Arith::Val Val;
   constexpr int kCols = kWavesPerBlock;
-  constexpr int kAV = ColsStage<TR>::kAV;
-  constexpr int kAR = kAV / 2;                       // rows each wave stages
-  __shared__ double sa[2][TR][3][64];                // a0, a1, a0 + a1 per staged row
-  __shared__ double sb[2][kCols][2][64];
+  constexpr int kAV = ColsEntry<TR>::kAV;
+  constexpr int kAR = kAV < 2 ? 1 : kAV / 2;         // rows each staging wave stages
+  constexpr int kStagers = TR / kAR;                 // waves that stage A rows
+  constexpr int kNV = Arith::kSum ? 3 : 2;           // staged values per row
+  __shared__ Val sa[2][2][TR][kNV][64];              // [buffer][entry of the pair][row]: a0, a1 (, a0 + a1)
   __shared__ int2 s_km[kSegEntries];
   __shared__ int s_es[kSegEntries][TR];
   const int N = dp.N, L = dp.L;
@@ -478,7 +485,7 @@ __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const 
   }
   const FpLimb& F = fl.l[li];
   const int l = F.limb;
-  const ArithFp ar(F, dp.pr[l]);
+  const Arith ar(F, dp.pr[l]);
   const int Nc = tl.Nc;
   const int64_t cidx = (int64_t)l * (N >> 6) + (tbase >> 6);
   const u64* Ab = A + cidx * 2 * tl.nA * 64 + lane;
@@ -486,20 +493,24 @@ __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const 
   const int64_t pA = tl.nA * 64, pB = tl.nB * 64;
   const int j = h * kCols + wave;                    // this wave's column
   const bool jin = j < Nc;
-  const int arow = wave * kAR;                       // first row this wave stages
-  ArithFp::Acc acc[TR];
+  const bool stager = wave < kStagers;
+  const int arow = stager ? wave * kAR : 0;          // first row this wave stages
+  typename Arith::Acc acc[TR];
 #pragma unroll
-  for (int r = 0; r < TR; ++r) ArithFp::zero(acc[r]);
+  for (int r = 0; r < TR; ++r) Arith::zero(acc[r]);
 
-  typedef ColsStage<TR> Stage;
+  typedef ColsEntry<TR> Entry;
+  struct Pair {
+    Entry e[2];
+  };
   const int e0 = tl.tstart[g], e1 = tl.tstart[g + 1];
-  auto fetch = [&](int x, int xend, Stage& st) {
+  auto fetch = [&](int x, int xend, Entry& st) {
     st.mask = 0;
+    st.bact = false;
     if (x >= xend) return;
     const int2 km = s_km[x];
     const int k = __builtin_amdgcn_readfirstlane(km.x);
     st.mask = __builtin_amdgcn_readfirstlane(km.y);
-    st.b0 = st.b1 = 0;
     st.bact = jin;
     if (jin) {
       int64_t bsl = (int64_t)k * Nc + j;
@@ -512,6 +523,7 @@ __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const 
         st.b1 = Bb[bsl * 64 + pB];
       }
     }
+    if (!stager) return;
 #pragma unroll
     for (int r = 0; r < kAR; ++r) {
       if ((st.mask >> (arow + r)) & 1) {
@@ -521,31 +533,51 @@ __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const 
       }
     }
   };
-  auto put = [&](const Stage& st, int bf) {
-    const double b0 = ArithFp::load(st.b0), b1 = ArithFp::load(st.b1);
-    sb[bf][wave][0][lane] = b0;
-    sb[bf][wave][1][lane] = b1;
+  auto put = [&](const Entry& st, int bf, int ep) {
+    if (!stager) return;
 #pragma unroll
     for (int r = 0; r < kAR; ++r) {
       if ((st.mask >> (arow + r)) & 1) {
-        const double a0 = ArithFp::load(st.a[2 * r]), a1 = ArithFp::load(st.a[2 * r + 1]);
-        sa[bf][arow + r][0][lane] = a0;
-        sa[bf][arow + r][1][lane] = a1;
-        sa[bf][arow + r][2][lane] = a0 + a1;
+        const Val a0 = Arith::load(st.a[2 * r]), a1 = Arith::load(st.a[2 * r + 1]);
+        sa[bf][ep][arow + r][0][lane] = a0;
+        sa[bf][ep][arow + r][1][lane] = a1;
+        if constexpr (Arith::kSum) sa[bf][ep][arow + r][kNV - 1][lane] = Arith::sum(a0, a1);
       }
     }
   };
-  auto compute = [&](const Stage& st, int bf) {
-    if (BSP && !st.bact) return;
-    const double b0 = sb[bf][wave][0][lane], b1 = sb[bf][wave][1][lane];
-    const double bs = b0 + b1;
+  // what a pair's products need besides LDS: the B words and the row masks
+  // (zero for an entry whose B_kj is zero or whose column is outside B)
+  struct PairB {
+    u64 b00, b01, b10, b11;
+    int m0, m1;
+  };
+  auto take_b = [&](const Pair& pr) {
+    PairB q;
+    q.b00 = pr.e[0].b0;
+    q.b01 = pr.e[0].b1;
+    q.b10 = pr.e[1].b0;
+    q.b11 = pr.e[1].b1;
+    q.m0 = pr.e[0].bact ? pr.e[0].mask : 0;
+    q.m1 = pr.e[1].bact ? pr.e[1].mask : 0;
+    return q;
+  };
+  // the products of one entry of a pair (B from registers, A from LDS)
+  auto compute1 = [&](u64 ub0, u64 ub1, int m, int bf, int ep) {
+    if (!m) return;
+    const Val b0 = Arith::load(ub0), b1 = Arith::load(ub1);
+    const Val bs = Arith::sum(b0, b1);
 #pragma unroll
     for (int r = 0; r < TR; ++r) {
-      if ((st.mask >> r) & 1) {
-        const double a0 = sa[bf][r][0][lane], a1 = sa[bf][r][1][lane], as = sa[bf][r][2][lane];
+      if ((m >> r) & 1) {
+        const Val a0 = sa[bf][ep][r][0][lane], a1 = sa[bf][ep][r][1][lane];
+        const Val as = sa[bf][ep][r][kNV - 1][lane];
         ar.mac(acc[r], a0, a1, as, b0, b1, bs);
       }
     }
+  };
+  auto compute = [&](const PairB& pb, int bf) {
+    compute1(pb.b00, pb.b01, pb.m0, bf, 0);
+    compute1(pb.b10, pb.b11, pb.m1, bf, 1);
   };
   int cnt = 0;
   for (int sg = e0; sg < e1; sg += kSegEntries) {
@@ -554,24 +586,30 @@ __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const 
     for (int x = threadIdx.x; x < n; x += blockDim.x) s_km[x] = make_int2(tl.ek[sg + x], tl.emask[sg + x]);
     for (int x = threadIdx.x; x < n * TR; x += blockDim.x) s_es[x / TR][x % TR] = tl.eslot[(int64_t)sg * TR + x];
     __syncthreads();
-    Stage sA, sB;
-    fetch(0, n, sA);
-    fetch(1, n, sB);
-    for (int x = 0; x < n; x += 2) {
-      put(sA, 0);
+    // one pair in flight: pair p's A goes to LDS buffer p mod 2, its B
+    // words to registers, then pair p + 1 is fetched while pair p computes
+    Pair pn;
+    fetch(0, n, pn.e[0]);
+    fetch(1, n, pn.e[1]);
+    for (int x = 0; x < n; x += 4) {
+      put(pn.e[0], 0, 0);
+      put(pn.e[1], 0, 1);
+      const PairB cA = take_b(pn);
       __syncthreads();
-      const Stage cA = sA;
-      fetch(x + 2, n, sA);
+      fetch(x + 2, n, pn.e[0]);
+      fetch(x + 3, n, pn.e[1]);
       compute(cA, 0);
-      if (x + 1 < n) {
-        put(sB, 1);
+      if (x + 2 < n) {
+        put(pn.e[0], 1, 0);
+        put(pn.e[1], 1, 1);
+        const PairB cB = take_b(pn);
         __syncthreads();
-        const Stage cB = sB;
-        fetch(x + 3, n, sB);
+        fetch(x + 4, n, pn.e[0]);
+        fetch(x + 5, n, pn.e[1]);
         compute(cB, 1);
       }
-      cnt += 2;
-      if (cnt >= ArithFp::kFold) {
+      cnt += 4;
+      if (cnt >= Arith::kFold) {
         cnt = 0;
 #pragma unroll
         for (int r = 0; r < TR; ++r) ar.fold(acc[r]);
@@ -637,7 +675,7 @@ static int launch_block(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl
   return SFHE_OK;
 }
 
-template <int TR, bool BSP>
+template <typename Arith, int TR, bool BSP>
 static int launch_cols(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl, const u64* A, const u64* B, u64* D,
                        hipStream_t s) {
   if (fl.n == 0) return SFHE_OK;
@@ -646,7 +684,7 @@ static int launch_cols(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl,
   t2.n_col_tiles = (tl.Nc + kWavesPerBlock - 1) / kWavesPerBlock;
   const int64_t blocks = (int64_t)fl.n * (c->N / 64) * tl.n_row_tiles * t2.n_col_tiles;
   if (blocks > 0x7FFFFFFF) { set_error("tensor: grid too large"); return SFHE_E_INVALID_ARG; }
-  hipLaunchKernelGGL((tensor_cols_kernel<TR, BSP>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, t2, A, B,
+  hipLaunchKernelGGL((tensor_cols_kernel<Arith, TR, BSP>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, t2, A, B,
                      D, fl, c->dp);
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;
@@ -658,8 +696,8 @@ int tensor_fp_prime_count(const sfhe_ctx* c) {
   return n;
 }
 
-int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& tl_fp, const u64* A, const u64* B,
-                        u64* D, hipStream_t s, hipEvent_t fp_start, hipEvent_t fp_stop) {
+int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& tl_fp, const TileList& tl_i60,
+                        const u64* A, const u64* B, u64* D, hipStream_t s, hipEvent_t fp_start, hipEvent_t fp_stop) {
   if (tl.rows <= 0) return SFHE_OK;
   // primes below 2^42 use the fp64 residue arithmetic, the others 128-bit integers
   FpLimbs ffp{}, fint{}, f60{};
@@ -675,15 +713,15 @@ int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& t
   }
   if (fp_start) SFHE_HIP(hipEventRecord(fp_start, s));
   const bool bsp = tl.bslot != nullptr;
-  int rc = bsp ? launch_cols<kTileRowsFp, true>(c, tl_fp, ffp, A, B, D, s)
-               : launch_cols<kTileRowsFp, false>(c, tl_fp, ffp, A, B, D, s);
+  int rc = bsp ? launch_cols<ArithFp, kTileRowsFp, true>(c, tl_fp, ffp, A, B, D, s)
+               : launch_cols<ArithFp, kTileRowsFp, false>(c, tl_fp, ffp, A, B, D, s);
   if (fp_stop) SFHE_HIP(hipEventRecord(fp_stop, s));
   if (!rc)
     rc = bsp ? launch_block<ArithInt, 4, 1, true>(c, tl, fint, A, B, D, s)
              : launch_block<ArithInt, 4, 1, false>(c, tl, fint, A, B, D, s);
   if (!rc)
-    rc = bsp ? launch_block<ArithInt60, 4, 1, true>(c, tl, f60, A, B, D, s)
-             : launch_block<ArithInt60, 4, 1, false>(c, tl, f60, A, B, D, s);
+    rc = bsp ? launch_cols<ArithInt60, kTileRowsInt60, true>(c, tl_i60, f60, A, B, D, s)
+             : launch_cols<ArithInt60, kTileRowsInt60, false>(c, tl_i60, f60, A, B, D, s);
   return rc;
 }
 

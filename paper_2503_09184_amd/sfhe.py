@@ -33,7 +33,8 @@ EXPORTED = [
     "sfhe_server_destroy", "sfhe_plain_graph_create", "sfhe_plain_graph_launch", "sfhe_plain_graph_result",
     "sfhe_plain_graph_destroy", "sfhe_encrypt_matrix_slots", "sfhe_matmul_slots", "sfhe_export_stored",
     "sfhe_rotate", "sfhe_ntt_tuning", "sfhe_set_ntt_variant",
-    "sfhe_probe_valu", "sfhe_server_request_bytes",
+    "sfhe_probe_valu", "sfhe_server_request_bytes", "sfhe_ks_tuning", "sfhe_set_ks_slice",
+    "sfhe_matmul_graph_create", "sfhe_matmul_graph_launch", "sfhe_matmul_graph_result", "sfhe_matmul_graph_destroy",
 ]
 
 PLAIN_LAUNCH = {"fused": 0, "per_product": 1}
@@ -141,6 +142,11 @@ def lib():
         L.sfhe_plain_graph_result.argtypes = [vp, i32, ctypes.POINTER(vp)]
         L.sfhe_plain_graph_destroy.argtypes = [vp]
         L.sfhe_plain_graph_destroy.restype = None
+        L.sfhe_matmul_graph_create.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.sfhe_matmul_graph_launch.argtypes = [vp, vp]
+        L.sfhe_matmul_graph_result.argtypes = [vp, ctypes.POINTER(vp)]
+        L.sfhe_matmul_graph_destroy.argtypes = [vp]
+        L.sfhe_matmul_graph_destroy.restype = None
         L.sfhe_encrypt_matrix_slots.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, i32, i64, ctypes.c_int, i32,
                                                 u64, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
         L.sfhe_matmul_slots.argtypes = [vp, vp, vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
@@ -148,6 +154,9 @@ def lib():
         L.sfhe_rotate.argtypes = [vp, i32, vp, vp, i32, i32, vp]
         L.sfhe_ntt_tuning.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), i32]
         L.sfhe_set_ntt_variant.argtypes = [vp, i32, i32]
+        L.sfhe_ks_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                     i32]
+        L.sfhe_set_ks_slice.argtypes = [vp, i32]
         _lib = L
     return _lib
 
@@ -225,6 +234,36 @@ class PlainGraph:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().sfhe_plain_graph_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MatmulGraph:
+    """A LAZY ct x ct product captured into a HIP graph (library handle)."""
+
+    def __init__(self, ctx, A, B, stream=None):
+        self.ctx = ctx
+        self._keep = (A, B)
+        h = ctypes.c_void_p()
+        _check(lib().sfhe_matmul_graph_create(ctx._h, A.handle, B.handle, _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().sfhe_matmul_graph_launch(self._h, _stream_handle(stream)))
+
+    def result(self):
+        h = ctypes.c_void_p()
+        _check(lib().sfhe_matmul_graph_result(self._h, ctypes.byref(h)))
+        return _Borrowed(self.ctx, h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sfhe_matmul_graph_destroy(self._h)
         self._h = None
 
     def __del__(self):
@@ -316,11 +355,16 @@ class Context:
         if hooks is not None or torch_allocator:
             dev = self.device
             if hooks is None:
+                # bound now: at interpreter exit the torch module's attributes
+                # may be gone before the context is destroyed
+                t_alloc = torch.cuda.caching_allocator_alloc
+                t_free = torch.cuda.caching_allocator_delete
+
                 def user_alloc(nbytes, stream):
-                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream))
+                    return t_alloc(int(nbytes), dev, int(stream))
 
                 def user_free(ptr, nbytes, stream):
-                    torch.cuda.caching_allocator_delete(ptr)
+                    t_free(ptr)
             else:
                 user_alloc, user_free = hooks
 
@@ -472,6 +516,17 @@ class Context:
         us = (ctypes.c_double * 4)()
         _check(lib().sfhe_ntt_tuning(self._h, 1 if inverse else 0, ctypes.byref(v), us, 4))
         return self.NTT_DESIGNS[v.value], {n: us[i] for i, n in enumerate(self.NTT_DESIGNS) if us[i] >= 0}
+
+    def ks_tuning(self):
+        """(slice in use, {candidate slice: measured us per output})."""
+        sl = ctypes.c_int32()
+        sizes = (ctypes.c_int32 * 6)()
+        us = (ctypes.c_double * 6)()
+        _check(lib().sfhe_ks_tuning(self._h, ctypes.byref(sl), sizes, us, 6))
+        return sl.value, {int(sizes[x]): float(us[x]) for x in range(6)}
+
+    def set_ks_slice(self, slice_):
+        _check(lib().sfhe_set_ks_slice(self._h, int(slice_)))
 
     def set_ntt_design(self, inverse, design):
         """Force a design by name, or None for the measured choice."""
