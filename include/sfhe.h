@@ -473,6 +473,21 @@ int sfhe_tensor(sfhe_ctx* ctx, int32_t level, const uint64_t* a, const uint64_t*
 int sfhe_keyswitch(sfhe_ctx* ctx, int32_t level, const uint64_t* d2, uint64_t* out, int32_t batch,
                    void* stream);
 
+/* sfhe_keyswitch for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same operation and bits, with every working row in one fixed device
+ * array of 64 MiB per GPU that the library holds until the process ends
+ * (its address is looked up when a context is created on the device).  The
+ * call allocates nothing, host or device.  A batch needs
+ * batch * (3 (level + 1) + 3 (level + 1 + n_p)) * N * 8 bytes of it (at
+ * N = 2^14, five data and three special primes, level 4: up to 13
+ * ciphertexts); a larger batch is SFHE_E_INVALID_ARG, to be split by the
+ * caller.  All calls on one GPU share the array: calls whose work overlaps
+ * on the device (other streams, other host threads or contexts) race and
+ * must be ordered by the caller. */
+int sfhe_keyswitch_noalloc(sfhe_ctx* ctx, int32_t level, const uint64_t* d2, uint64_t* out, int32_t batch,
+                           void* stream);
+
 /* Rescale by the last prime of `level` (level >= 1), NTT domain, with exact
  * rounding (centered lift): in [batch][2][level+1][N] -> out [batch][2][level][N]. */
 int sfhe_rescale(sfhe_ctx* ctx, int32_t level, const uint64_t* in, uint64_t* out, int32_t batch,

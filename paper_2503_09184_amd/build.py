@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsfhe.so")
-SOURCES = ["ntt.hip", "sample.hip", "tensor.hip", "keyswitch.hip", "ks14.hip", "ctpt.hip", "rotate.hip", "probe.hip", "capi.hip"]
+SOURCES = ["ntt.hip", "sample.hip", "tensor.hip", "keyswitch.hip", "ks14.hip", "ctpt.hip", "rotate.hip", "noalloc.hip", "probe.hip", "capi.hip"]
 
 
 def hipcc():

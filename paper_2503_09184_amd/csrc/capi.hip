@@ -595,6 +595,7 @@ int sfhe_ctx_create(const sfhe_params* p, const sfhe_device_hooks* hooks, sfhe_c
     return SFHE_E_DEVICE;
   }
   rc = tune_ntt(c);
+  if (!rc) rc = noalloc_setup(c);
   if (rc) {
     delete c;
     return rc;

@@ -327,6 +327,10 @@ inline int64_t keyswitch_scratch_words(const sfhe_ctx* c, int lev, int64_t batch
   const int64_t nl = lev + 1, ne = nl + c->alpha;
   return batch * (nl + ne + 2 * ne + 2 * nl) * c->N;
 }
+// the allocation-free entry point's device scratch (noalloc.hip): its
+// address on the context's device, looked up once per device at context
+// creation; SFHE_OK or SFHE_E_DEVICE
+int noalloc_setup(sfhe_ctx* c);
 // where rescale writes: limb-major rows (stride words apart) or ciphertexts
 // elem_base + b of a chunked matrix holding n_ct ciphertexts
 struct OutLayout {

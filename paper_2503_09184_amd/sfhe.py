@@ -32,7 +32,7 @@ EXPORTED = [
     "sfhe_server_create", "sfhe_server_submit", "sfhe_server_step", "sfhe_server_poll", "sfhe_server_status",
     "sfhe_server_destroy", "sfhe_plain_graph_create", "sfhe_plain_graph_launch", "sfhe_plain_graph_result",
     "sfhe_plain_graph_destroy", "sfhe_encrypt_matrix_slots", "sfhe_matmul_slots", "sfhe_export_stored",
-    "sfhe_rotate", "sfhe_ntt_tuning", "sfhe_set_ntt_variant",
+    "sfhe_rotate", "sfhe_ntt_tuning", "sfhe_set_ntt_variant", "sfhe_keyswitch_noalloc",
     "sfhe_probe_valu", "sfhe_server_request_bytes", "sfhe_ks_tuning", "sfhe_set_ks_slice",
     "sfhe_matmul_graph_create", "sfhe_matmul_graph_launch", "sfhe_matmul_graph_result", "sfhe_matmul_graph_destroy",
 ]
@@ -118,6 +118,7 @@ def lib():
         L.sfhe_ntt.argtypes = [vp, vp, i32, i32, i32, i32, vp]
         L.sfhe_tensor.argtypes = [vp, i32, vp, vp, vp, i32, vp]
         L.sfhe_keyswitch.argtypes = [vp, i32, vp, vp, i32, vp]
+        L.sfhe_keyswitch_noalloc.argtypes = [vp, i32, vp, vp, i32, vp]
         L.sfhe_probe_valu.argtypes = [i32, ctypes.POINTER(ctypes.c_double)]
         L.sfhe_rescale.argtypes = [vp, i32, vp, vp, i32, vp]
         L.sfhe_encode_matrix.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, i32, i64, ctypes.c_int, i32,
@@ -567,6 +568,18 @@ class Context:
         _check(lib().sfhe_keyswitch(self._h, level, ctypes.c_void_p(d2.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                     batch, _stream_handle(stream)))
         return out.view(batch, 2, nl, self.n)
+
+    def keyswitch_noalloc(self, level, d2, out, stream=None):
+        """sfhe_keyswitch_noalloc: d2 [batch, level+1, N] into the caller's
+        out [batch, 2, level+1, N] (int64 device tensors); nothing is
+        allocated, the library's fixed device scratch is used."""
+        nl = level + 1
+        assert d2.is_contiguous() and out.is_contiguous()
+        batch = d2.numel() // (nl * self.n)
+        assert out.numel() == batch * 2 * nl * self.n
+        _check(lib().sfhe_keyswitch_noalloc(self._h, level, ctypes.c_void_p(d2.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), batch, _stream_handle(stream)))
+        return out
 
     def rescale(self, level, ct, stream=None):
         nl = level + 1
