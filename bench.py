@@ -229,7 +229,24 @@ def ctpt_leg(torch, sfhe, W, count=32):
         for x in Cs + Bs + Ws:
             x.close()
         del Cs, Bs, Ws
-    # one launch per product against the fused form, on the smallest job
+    ctx.close()
+    torch.cuda.empty_cache()
+    return {"matmuls": len(jobs), "shapes_MKN_sparsity": [list(j) for j in jobs], "waves": len(waves),
+            "units": len(units), "products": int(products), "ms": total_ms,
+            "ctpt_mults_per_s": products / (total_ms / 1e3), "fused_launches": int(launches),
+            "host_wall_s": wall}
+
+
+def ctpt_launch_leg(torch, sfhe, W, count=32):
+    """The one-launch-per-product form of the plaintext-weight product against
+    the fused form, on the job of the uneven batch (the ct_pt leg's jobs) with
+    the fewest products, each also captured into a HIP graph and replayed."""
+    P = W.PARAMS["plain_n16384"]
+    cfg = 4
+    ctx = sfhe.Context(**P)
+    ctx.keygen(W.key_seed(cfg))
+    jobs = W.uneven_batch(W.workload_seed(cfg), count)
+    ops = {jn: W.operands(M, K, Nc, s, W.workload_seed(cfg) + 1 + jn) for jn, (M, K, Nc, s) in enumerate(jobs)}
     jn = min(range(len(jobs)), key=lambda x: int(np.count_nonzero(ops[x][0])) * jobs[x][2])
     Wm = ctx.encode_weights(ops[jn][0], "csr", 40)
     Bm = ctx.encrypt(ops[jn][1], "dense", W.enc_seed(cfg, 1) + jn, 1)
@@ -258,10 +275,7 @@ def ctpt_leg(torch, sfhe, W, count=32):
     Bm.close()
     ctx.close()
     torch.cuda.empty_cache()
-    return {"matmuls": len(jobs), "shapes_MKN_sparsity": [list(j) for j in jobs], "waves": len(waves),
-            "units": len(units), "products": int(products), "ms": total_ms,
-            "ctpt_mults_per_s": products / (total_ms / 1e3), "fused_launches": int(launches),
-            "host_wall_s": wall, "per_product_launch_sample": sample}
+    return sample
 
 
 def slots_leg(ctx, torch, A, Bm, sa, sb, chunk, sched="lazy"):
@@ -290,6 +304,9 @@ def slots_leg(ctx, torch, A, Bm, sa, sb, chunk, sched="lazy"):
     return out
 
 
+SERVING_POLICIES = [("fifo_1_stream", 1, 0), ("2_streams", 2, 0), ("2_streams_1_slot_each", 2, 1)]
+
+
 def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
     """The request loop over plaintext-weight products: encrypted MLP-layer
     requests (weights 128x784, 256x256 or 128x512, i.e. layers 784->128,
@@ -299,7 +316,10 @@ def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
     the encrypted activations come from a pool of pool_per_layer matrices per
     layer, encrypted before the run (the client's side; requests only read
     them).  The arrival rate is `load` times the service rate measured on one
-    request of each layer alone.  Latency is arrival to result, host clock."""
+    request of each layer alone.  Latency is arrival to result, host clock.
+    The same arrivals are served under each admission policy of
+    SERVING_POLICIES (server streams, running batches per stream); the first
+    is the reported one."""
     P = W.PARAMS["serving_n32768"]
     cfg = 5
     ctx = sfhe.Context(**P)
@@ -343,83 +363,105 @@ def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
     mean_service_s = float(np.mean(alone_ms)) * (8.5 / 8.0) / 1e3
     rate = load / mean_service_s
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
-    srv = sfhe.Server(ctx, budget)
-    tickets, done_at, results, sizes = {}, {}, {}, []
-    t0 = time.perf_counter()
-    nxt = 0
-    while len(done_at) < n_requests:
-        now = time.perf_counter() - t0
-        while nxt < n_requests and arrivals[nxt] <= now:
-            r = reqs[nxt]
-            tickets[nxt] = srv.submit(weights[(r["layer"], r["sp"])][1], r["EX"])
-            nxt += 1
-        srv.step()
-        for n, t in tickets.items():
-            if n in done_at:
-                continue
-            d, C, ms, bs = srv.poll(t)
-            if d:
-                done_at[n] = time.perf_counter() - t0
-                if n in (0, n_requests // 2, n_requests - 1):
-                    results[n] = C          # kept for the checks below
-                else:
-                    C.close()
-                sizes.append(bs)
-        if nxt < n_requests and not any(n not in done_at for n in tickets):
-            time.sleep(max(0.0, min(arrivals[nxt] - (time.perf_counter() - t0), 0.002)))
-        else:
-            time.sleep(0.0002)
-    makespan = max(done_at.values()) - arrivals[0]
-    st = srv.status()
-    # batches whose device-time interval intersects another batch's ran concurrently
-    iv = sorted(set(srv.intervals[t] for t in tickets.values()))
-    overl = sum(1 for x in range(len(iv)) if any(iv[x][0] < iv[y][1] and iv[y][0] < iv[x][1]
-                                               for y in range(len(iv)) if y != x))
-    busy = 0.0
-    cur0, cur1 = None, None
-    for a, b in iv:
-        if cur1 is None or a > cur1:
-            if cur1 is not None:
-                busy += cur1 - cur0
-            cur0, cur1 = a, b
-        else:
-            cur1 = max(cur1, b)
-    if cur1 is not None:
-        busy += cur1 - cur0
-    lat = np.array([(done_at[n] - arrivals[n]) * 1e3 for n in range(n_requests)])
-    products = st["products"]
-    # a result in the mix equals the same request alone, bit for bit
-    same = True
-    for n in (0, n_requests // 2, n_requests - 1):
+    # a result in the mix is compared with the same request alone, bit for bit
+    checked = (0, n_requests // 2, n_requests - 1)
+    solo_cts = {}
+    for n in checked:
         r = reqs[n]
         solo = sfhe.Server(ctx, budget)
         t = solo.submit(weights[(r["layer"], r["sp"])][1], r["EX"])
         solo.step()
         C1 = solo.poll(t, wait=True)[1]
-        for (i, j) in [(0, 0), (layers[r["layer"]][1] - 1, r["b"] - 1)]:
-            same = same and np.array_equal(ctx.export_ct(C1, i, j), ctx.export_ct(results[n], i, j))
+        solo_cts[n] = [ctx.export_ct(C1, i, j) for (i, j) in [(0, 0), (layers[r["layer"]][1] - 1, r["b"] - 1)]]
         C1.close()
         solo.close()
-    err = max(float(np.max(np.abs(ctx.decrypt(results[n]) - weights[(reqs[n]["layer"], reqs[n]["sp"])][0] @ reqs[n]["X"])))
-              for n in (0, n_requests - 1))
-    for C in results.values():
-        C.close()
-    srv.close()
+
+    def serve(n_streams, slots):
+        srv = sfhe.Server(ctx, budget, n_streams=n_streams, slots=slots)
+        tickets, done_at, results, sizes = {}, {}, {}, []
+        step_s, step_max = 0.0, 0.0
+        t0 = time.perf_counter()
+        nxt = 0
+        while len(done_at) < n_requests:
+            now = time.perf_counter() - t0
+            while nxt < n_requests and arrivals[nxt] <= now:
+                r = reqs[nxt]
+                tickets[nxt] = srv.submit(weights[(r["layer"], r["sp"])][1], r["EX"])
+                nxt += 1
+            ts = time.perf_counter()
+            srv.step()
+            dt = time.perf_counter() - ts
+            step_s += dt
+            step_max = max(step_max, dt)
+            for n, t in tickets.items():
+                if n in done_at:
+                    continue
+                d, C, ms, bs = srv.poll(t)
+                if d:
+                    done_at[n] = time.perf_counter() - t0
+                    if n in checked:
+                        results[n] = C          # kept for the checks below
+                    else:
+                        C.close()
+                    sizes.append(bs)
+            if nxt < n_requests and not any(n not in done_at for n in tickets):
+                time.sleep(max(0.0, min(arrivals[nxt] - (time.perf_counter() - t0), 0.002)))
+            else:
+                time.sleep(0.0002)
+        makespan = max(done_at.values()) - arrivals[0]
+        st = srv.status()
+        # batches whose device-time interval intersects another batch's ran concurrently
+        iv = sorted(set(srv.intervals[t] for t in tickets.values()))
+        overl = sum(1 for x in range(len(iv)) if any(iv[x][0] < iv[y][1] and iv[y][0] < iv[x][1]
+                                                   for y in range(len(iv)) if y != x))
+        busy = 0.0
+        cur0, cur1 = None, None
+        for a, b in iv:
+            if cur1 is None or a > cur1:
+                if cur1 is not None:
+                    busy += cur1 - cur0
+                cur0, cur1 = a, b
+            else:
+                cur1 = max(cur1, b)
+        if cur1 is not None:
+            busy += cur1 - cur0
+        lat = np.array([(done_at[n] - arrivals[n]) * 1e3 for n in range(n_requests)])
+        same = all(np.array_equal(ctx.export_ct(results[n], i, j), solo_cts[n][x])
+                   for n in checked
+                   for x, (i, j) in enumerate([(0, 0), (layers[reqs[n]["layer"]][1] - 1, reqs[n]["b"] - 1)]))
+        err = max(float(np.max(np.abs(ctx.decrypt(results[n]) -
+                                      weights[(reqs[n]["layer"], reqs[n]["sp"])][0] @ reqs[n]["X"])))
+                  for n in (0, n_requests - 1))
+        for C in results.values():
+            C.close()
+        srv.close()
+        return {"streams": n_streams, "slots_per_stream": slots,
+                "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+                "latency_ms_mean": float(lat.mean()), "makespan_s": makespan, "products": int(st["products"]),
+                "ctpt_mults_per_s": st["products"] / makespan, "batches": int(st["batches"]),
+                "mean_batch_size": float(np.mean(sizes)), "max_batch_size": int(max(sizes)),
+                "alone_equals_mix": bool(same), "max_abs_err_vs_fp64": err,
+                "batches_overlapping_another": overl, "device_busy_ms": busy,
+                "device_batch_ms_sum": float(sum(b - a for a, b in iv)),
+                "host_step_ms_sum": step_s * 1e3, "host_step_ms_max": step_max * 1e3}
+
+    policies = {}
+    for name, n_streams, slots in SERVING_POLICIES:
+        policies[name] = serve(n_streams, slots)
+        log("serving %s: p50 %.1f ms, p99 %.1f ms, %d batches, %d overlapping, host step %.0f ms" %
+            (name, policies[name]["latency_ms_p50"], policies[name]["latency_ms_p99"], policies[name]["batches"],
+             policies[name]["batches_overlapping_another"], policies[name]["host_step_ms_sum"]))
     for k in pool:
         pool[k][2].close()
     for k in weights:
         weights[k][1].close()
     ctx.close()
     torch.cuda.empty_cache()
-    return {"requests": n_requests, "load": load, "arrival_rate_per_s": rate, "budget_gib": budget / 2 ** 30,
-            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
-            "latency_ms_mean": float(lat.mean()), "makespan_s": makespan, "products": int(products),
-            "ctpt_mults_per_s": products / makespan, "batches": int(st["batches"]),
-            "mean_batch_size": float(np.mean(sizes)), "max_batch_size": int(max(sizes)),
-            "alone_equals_mix": bool(same), "max_abs_err_vs_fp64": err,
-            "batches_overlapping_another": overl, "device_busy_ms": busy,
-            "device_batch_ms_sum": float(sum(b - a for a, b in iv)), "streams": 4,
-            "ring": "N=2^15, 9 data + 3 special primes (12 limbs), dnum=3"}
+    out = {"requests": n_requests, "load": load, "arrival_rate_per_s": rate, "budget_gib": budget / 2 ** 30,
+           "policy": SERVING_POLICIES[0][0], "ring": "N=2^15, 9 data + 3 special primes (12 limbs), dnum=3"}
+    out.update(policies[SERVING_POLICIES[0][0]])
+    out["policies"] = policies
+    return out
 
 
 def cpu_thread_scaling(threads, target_s=8.0):
@@ -489,7 +531,7 @@ def main():
     ap.add_argument("--sparsity", type=float, default=0.5)
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--only", default="", help="comma list of extra legs to run (default all): "
-                    "s90,dense,ell,naive,per_product,both,sweep,slots,serve,ctpt,cpu,peaks,kstune")
+                    "s90,dense,ell,naive,per_product,both,sweep,slots,serve,ctpt,ctpt_launch,cpu,peaks,kstune")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--ctpt-count", type=int, default=32,
                     help="products in the uneven plaintext-weight batch (32 is the workload; fewer for profiling)")
@@ -625,16 +667,18 @@ def main():
 
     # the key-switch slice the tuner chose (at the first product) against
     # the untuned default of 2048 outputs per launch group
-    ks_slice, ks_us = ctx.ks_tuning()
-    ks_tuning = {"slice_in_use": ks_slice, "us_per_output_by_slice": {str(k): v for k, v in ks_us.items()}}
-    if run("kstune") and ks_slice not in (0, 2048):
-        ctx.set_ks_slice(2048)
+    ks_slice, ks_streams, ks_us, ks_us2 = ctx.ks_tuning()
+    ks_tuning = {"slice_in_use": ks_slice, "streams_in_use": ks_streams,
+                 "us_per_output_one_stream": {str(k): v for k, v in ks_us.items()},
+                 "us_per_output_two_streams": {str(k): v for k, v in ks_us2.items()}}
+    if run("kstune") and (ks_slice, ks_streams) != (2048, 1) and ks_slice != 0:
+        ctx.set_ks_slice(2048, 1)
         tt, _, _, _ = timed(ctx, torch, EA, EB, "lazy", max(2, min(args.steps, 5)), 1)
         ctx.set_ks_slice(-1)
-        ks_tuning["untuned_2048_ms_median"] = float(np.median(tt))
+        ks_tuning["untuned_2048_one_stream_ms_median"] = float(np.median(tt))
         ks_tuning["tuned_ms_median"] = float(np.median(times))
-        log("key-switch slice: tuned %d (%.2f ms/step) vs 2048 (%.2f ms/step)" %
-            (ks_slice, float(np.median(times)), float(np.median(tt))))
+        log("key switch: tuned %d x %d stream(s) (%.2f ms/step) vs 2048 x 1 (%.2f ms/step)" %
+            (ks_slice, ks_streams, float(np.median(times)), float(np.median(tt))))
     legs["lazy_csr_50"] = {"ms": ms, "ms_median": float(np.median(times)), "ms_min": float(np.min(times)),
                            "steps": len(times), "products": int(products), "ct_mults_per_s": value,
                            "keyswitches": int(st.keyswitches)}
@@ -704,8 +748,8 @@ def main():
     if run("serve"):
         log("serving: Poisson arrivals of encrypted MLP-layer requests")
         legs["serving"] = serving_leg(torch, sfhe, W)
-        log("serving: p50 %.1f ms, p99 %.1f ms, %.4g ct-pt mults/s, %d batches" %
-            (legs["serving"]["latency_ms_p50"], legs["serving"]["latency_ms_p99"],
+        log("serving (%s): p50 %.1f ms, p99 %.1f ms, %.4g ct-pt mults/s, %d batches" %
+            (legs["serving"]["policy"], legs["serving"]["latency_ms_p50"], legs["serving"]["latency_ms_p99"],
              legs["serving"]["ctpt_mults_per_s"], legs["serving"]["batches"]))
     if run("ctpt"):
         log("plaintext weights x encrypted values: uneven batch of 32 products")
@@ -713,6 +757,8 @@ def main():
         log("ctpt: %d products in %.1f ms, %.4g ct-pt mults/s" %
             (legs["ctpt_uneven_batch"]["products"], legs["ctpt_uneven_batch"]["ms"],
              legs["ctpt_uneven_batch"]["ctpt_mults_per_s"]))
+    if run("ctpt_launch"):
+        legs["ctpt_launch_forms"] = ctpt_launch_leg(torch, sfhe, W, args.ctpt_count)
 
     cpu = None
     if not args.no_cpu and run("cpu"):

@@ -294,10 +294,15 @@ int sfhe_export_stored(sfhe_ctx* ctx, const sfhe_mat* m, int64_t n, uint64_t* ou
  * cols) with the given encoding (zeros: elements equal to 0.0), scale
  * 2^log2_scale_w, 0 <= log2_scale_w <= 62, and |w| * 2^log2_scale_w below
  * 2^62 (else SFHE_E_INVALID_ARG).  The weights' residues stay in host
- * memory owned by the handle; no key is needed.  The handle is a left
- * operand of sfhe_matmul_plain only (sfhe_matmul, sfhe_decrypt_matrix and
- * sfhe_export_ct reject it with SFHE_E_UNSUPPORTED); sfhe_matrix_info reports
- * level L - 1, scale 2^log2_scale_w and zero device bytes. */
+ * memory owned by the handle, and their tile tables for the products (W's
+ * rows in tiles of 16; per tile, the columns k some row visits with the mask
+ * of those rows; per such entry and data prime, the 16 rows' weights) are
+ * built once here and kept in device memory owned by the handle, copied
+ * synchronously before the call returns.  No key is needed.  The handle is
+ * a left operand of sfhe_matmul_plain only (sfhe_matmul,
+ * sfhe_decrypt_matrix and sfhe_export_ct reject it with SFHE_E_UNSUPPORTED);
+ * sfhe_matrix_info reports level L - 1, scale 2^log2_scale_w and the tables'
+ * device bytes. */
 int sfhe_encode_matrix(sfhe_ctx* ctx, const double* vals, int32_t rows, int32_t cols, int64_t ld,
                        sfhe_encoding enc, int32_t log2_scale_w, sfhe_mat** out);
 
@@ -353,11 +358,15 @@ void sfhe_plain_graph_destroy(sfhe_plain_graph* graph);
  * device bytes they hold until they complete fit budget_bytes beside the
  * batches still running (per request: 2 (L) N words of sums and 2 (L - 1) N
  * of results per output, a rescale scratch for up to 2048 of its outputs and
- * its weight tables), and enqueues them as one fused sfhe_matmul_plain_batch
- * on the least busy of the server's n_streams streams (1 to 4, created by
- * the server at the default priority).  A batch admitted while others run
- * therefore starts at once and overlaps them on the device; its launches
- * first wait for the work enqueued on `stream` (the client stream, e.g. the
+ * its block descriptors; W's tile tables are W's own), and enqueues them as one fused sfhe_matmul_plain_batch
+ * on the stream, of the server's n_streams streams (1 to 4, created by the
+ * server at the default priority), with the fewest running batches.  With
+ * one stream the batches run in admission order; with several, a batch
+ * admitted while others run starts at once and overlaps them on the
+ * device.  With a slot limit (sfhe_server_set_slots), a stream that holds
+ * that many running batches takes no more, and while every stream is full
+ * requests stay queued and join the next batch.  A batch's launches first
+ * wait for the work enqueued on `stream` (the client stream, e.g. the
  * requests' encryptions) before the step.  A request's result is the same,
  * bit for bit, alone or in any batch.  The caller keeps W and X alive until
  * its request is done; a finished result belongs to the caller from
@@ -365,6 +374,9 @@ void sfhe_plain_graph_destroy(sfhe_plain_graph* graph);
  * on one server must not overlap. */
 typedef struct sfhe_server sfhe_server;
 int sfhe_server_create(sfhe_ctx* ctx, uint64_t budget_bytes, int32_t n_streams, void* stream, sfhe_server** out);
+/* at most per_stream running batches per server stream (0, the default: no
+ * limit); negative is SFHE_E_INVALID_ARG */
+int sfhe_server_set_slots(sfhe_server* srv, int32_t per_stream);
 /* the device bytes the server counts for request W X against its budget */
 int sfhe_server_request_bytes(const sfhe_ctx* ctx, const sfhe_mat* W, const sfhe_mat* X, uint64_t* bytes);
 /* queue W X; a request larger than the budget is SFHE_E_NOMEM */
@@ -441,19 +453,25 @@ int sfhe_ntt_tuning(const sfhe_ctx* ctx, int32_t inverse, int32_t* variant, doub
  * not apply to the ring); -1 returns to the measured choice. */
 int sfhe_set_ntt_variant(sfhe_ctx* ctx, int32_t inverse, int32_t variant);
 
-/* Key-switch slice tuning (the fused key switch and rescale at N = 2^14):
- * the outputs of a LAZY product are key-switched in slices, one launch of
- * each fused kernel per slice.  Small slices keep the working rows (about
- * 60 rows of N words per output) in the Infinity Cache, large ones fill the
- * GPU better; the first LAZY product of a context with at least 1024
- * outputs times every candidate (128 .. 4096 outputs) on its first outputs
- * and keeps the fastest.  *slice: the size in use (0: not tuned yet);
- * sizes[0..cap) / us_per_output[0..cap): the candidates and their measured
- * microseconds per output (-1: not measured). */
-int sfhe_ks_tuning(const sfhe_ctx* ctx, int32_t* slice, int32_t* sizes, double* us_per_output, int32_t cap);
-/* Use `slice` outputs per launch group (a power of two in [64, 4096]); 0
- * tunes again at the next LAZY product, -1 returns to the tuned size. */
-int sfhe_set_ks_slice(sfhe_ctx* ctx, int32_t slice);
+/* Key-switch tuning (the fused key switch and rescale at N = 2^14): the
+ * outputs of a LAZY product are key-switched in slices, one launch of each
+ * fused kernel per slice, on the call's stream or alternately on two side
+ * streams forked from it and joined back (so one slice's memory-bound base
+ * conversions overlap another's transforms).  The first LAZY product of a
+ * context with at least 1024 outputs times every one-stream candidate (128
+ * .. 4096 outputs per slice) on its first outputs, then the best slice and
+ * half of it on two streams, and keeps the fastest.  *slice, *streams: the
+ * setting in use (slice 0: not tuned yet); sizes[0..cap) /
+ * us_per_output[0..cap): the one-stream candidates and their measured
+ * microseconds per output (-1: not measured); sizes2[0..2) /
+ * us_per_output2[0..2): the same for the two-stream candidates.  Pointers
+ * other than slice may be NULL. */
+int sfhe_ks_tuning(const sfhe_ctx* ctx, int32_t* slice, int32_t* streams, int32_t* sizes, double* us_per_output,
+                   int32_t cap, int32_t* sizes2, double* us_per_output2);
+/* Use `slice` outputs per launch group (a power of two in [64, 4096]) on
+ * `streams` (1 or 2) key-switch streams; slice 0 tunes again at the next
+ * LAZY product, -1 returns to the tuned setting. */
+int sfhe_set_ks_slice(sfhe_ctx* ctx, int32_t slice, int32_t streams);
 
 /* In-place negacyclic NTT (inverse = 0) or inverse NTT (inverse = 1) of
  * `batch` groups of n_limbs rows laid out [batch][n_limbs][N]; row l of a

@@ -623,9 +623,15 @@ int sfhe_set_ntt_variant(sfhe_ctx* c, int32_t inverse, int32_t variant) {
   return SFHE_OK;
 }
 
-int sfhe_ks_tuning(const sfhe_ctx* c, int32_t* slice, int32_t* sizes, double* us_per_output, int32_t cap) {
+int sfhe_ks_tuning(const sfhe_ctx* c, int32_t* slice, int32_t* streams, int32_t* sizes, double* us_per_output,
+                   int32_t cap, int32_t* sizes2, double* us_per_output2) {
   if (!c || !slice) { set_error("NULL argument"); return SFHE_E_INVALID_ARG; }
   *slice = c->ks_slice;
+  if (streams) *streams = c->ks_streams;
+  for (int x = 0; x < 2; ++x) {
+    if (sizes2) sizes2[x] = (int32_t)c->ks_s2[x];
+    if (us_per_output2) us_per_output2[x] = c->ks_us2[x];
+  }
   for (int x = 0; x < kKsNumCandidates && x < cap; ++x) {
     if (sizes) sizes[x] = (int32_t)kKsCandidates[x];
     if (us_per_output) us_per_output[x] = c->ks_us[x];
@@ -633,14 +639,20 @@ int sfhe_ks_tuning(const sfhe_ctx* c, int32_t* slice, int32_t* sizes, double* us
   return SFHE_OK;
 }
 
-int sfhe_set_ks_slice(sfhe_ctx* c, int32_t slice) {
+int sfhe_set_ks_slice(sfhe_ctx* c, int32_t slice, int32_t streams) {
   if (!c) { set_error("NULL context"); return SFHE_E_INVALID_ARG; }
-  if (slice == -1) { c->ks_slice = c->ks_tuned_slice; return SFHE_OK; }
+  if (slice == -1) {
+    c->ks_slice = c->ks_tuned_slice;
+    c->ks_streams = c->ks_tuned_streams;
+    return SFHE_OK;
+  }
   if (slice != 0 && (slice < 64 || slice > 4096 || (slice & (slice - 1)))) {
     set_error("slice must be a power of two in [64, 4096], 0 (tune again) or -1 (the tuned choice)");
     return SFHE_E_INVALID_ARG;
   }
+  if (streams != 1 && streams != 2) { set_error("streams must be 1 or 2"); return SFHE_E_INVALID_ARG; }
   c->ks_slice = slice;
+  c->ks_streams = streams;
   return SFHE_OK;
 }
 
@@ -655,6 +667,11 @@ void sfhe_ctx_destroy(sfhe_ctx* c) {
   // work of any stream may still read the context's tables and keys
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+  for (int k = 0; k < 2; ++k) {
+    if (c->ks_side[k]) (void)hipStreamDestroy(c->ks_side[k]);
+    if (c->ks_join[k]) (void)hipEventDestroy(c->ks_join[k]);
+  }
+  if (c->ks_fork) (void)hipEventDestroy(c->ks_fork);
   if (c->tune_ev0) (void)hipEventDestroy(c->tune_ev0);
   if (c->tune_ev1) (void)hipEventDestroy(c->tune_ev1);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -770,7 +787,9 @@ int sfhe_matrix_info(const sfhe_mat* m, sfhe_mat_info* out) {
   out->n_ciphertexts = m->n_ct;
   out->nnz = m->nnz;
   out->ell_width = m->ell_w;
-  out->device_bytes = m->plain ? 0 : (uint64_t)m->n_ct * 2 * (m->level + 1) * m->ctx->N * sizeof(u64);
+  out->device_bytes = m->plain ? (uint64_t)(m->d_tstart.count + m->d_ek.count + m->d_emask.count) * sizeof(int) +
+                                     (uint64_t)(m->d_ew.count + m->d_ews.count) * sizeof(u64)
+                                : (uint64_t)m->n_ct * 2 * (m->level + 1) * m->ctx->N * sizeof(u64);
   out->slots = m->slots;
   return SFHE_OK;
 }
@@ -779,11 +798,51 @@ void sfhe_mat_destroy(sfhe_mat* m) { delete m; }
 
 }  // extern "C"
 
-// Key-switch slice tuning (N = 2^14, fused kernels): the key switch and
-// rescale of the first n outputs of a LAZY product's sums D are run once per
-// candidate slice size, each timed with an event pair on s, and the fastest
-// is kept in c->ks_slice; c->ks_us records microseconds per output.  Every
-// run writes the same ciphertexts, so *done = n outputs are finished.
+// Key switching of a run of outputs in slices: slice i goes to stream s
+// (nstr = 1) or alternately to the context's two side streams (nstr = 2),
+// forked from s after the work already on it and joined back into it, so
+// that one slice's memory-bound base conversions overlap the other's
+// transforms.  scratch holds nstr slices' working rows.
+static int ks_slices(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout ol, int64_t n, int64_t S, int nstr,
+                     u64* scratch, hipStream_t s) {
+  const int64_t words = keyswitch_rescale_n14_scratch_words(c, lev, S);
+  if (nstr == 2) {
+    if (!c->ks_side[0]) {
+      for (int k = 0; k < 2; ++k) {
+        SFHE_HIP(hipStreamCreateWithFlags(&c->ks_side[k], hipStreamNonBlocking));
+        SFHE_HIP(hipEventCreateWithFlags(&c->ks_join[k], hipEventDisableTiming));
+      }
+      SFHE_HIP(hipEventCreateWithFlags(&c->ks_fork, hipEventDisableTiming));
+    }
+    SFHE_HIP(hipEventRecord(c->ks_fork, s));
+    for (int k = 0; k < 2; ++k) SFHE_HIP(hipStreamWaitEvent(c->ks_side[k], c->ks_fork, 0));
+  }
+  int rc = SFHE_OK;
+  int64_t i = 0;
+  for (int64_t o0 = 0; o0 < n && !rc; o0 += S, ++i) {
+    OutLayout o = ol;
+    o.elem_base += o0;
+    const int k = nstr == 2 ? (int)(i & 1) : 0;
+    rc = keyswitch_rescale_n14(c, lev, D + o0 * dw, dw, o, std::min(S, n - o0), nstr == 2 ? c->ks_side[k] : s,
+                               scratch + k * words);
+  }
+  if (nstr == 2) {
+    // joined even after an error: s must not run ahead of the side streams
+    for (int k = 0; k < 2; ++k) {
+      SFHE_HIP(hipEventRecord(c->ks_join[k], c->ks_side[k]));
+      SFHE_HIP(hipStreamWaitEvent(s, c->ks_join[k], 0));
+    }
+  }
+  return rc;
+}
+
+// Key-switch tuning (N = 2^14, fused kernels): the key switch and rescale of
+// the first n outputs of a LAZY product's sums D are run for each candidate
+// slice size on one stream, then for the best slice and half of it on two
+// streams, each timed with an event pair on s; the fastest setting is kept
+// in c->ks_slice / c->ks_streams, and c->ks_us / c->ks_us2 record the
+// microseconds per output measured.  Every run writes the same ciphertexts,
+// so *done = n outputs are finished.
 static int tune_ks_slice(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout ol, int64_t n, hipStream_t s,
                          int64_t* done) {
   *done = 0;
@@ -791,35 +850,50 @@ static int tune_ks_slice(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayo
     SFHE_HIP(hipEventCreate(&c->tune_ev0));
     SFHE_HIP(hipEventCreate(&c->tune_ev1));
   }
+  const int64_t smax = std::min<int64_t>(n, kKsCandidates[kKsNumCandidates - 1]);
   DevBuf<u64> scr;
-  if (!scr.alloc(&c->alloc, (size_t)keyswitch_rescale_n14_scratch_words(c, lev, std::min<int64_t>(n, kKsCandidates[kKsNumCandidates - 1])))) {
+  if (!scr.alloc(&c->alloc, (size_t)keyswitch_rescale_n14_scratch_words(c, lev, smax))) {
     set_error("device allocation failed for the key-switch tuning scratch");
     return SFHE_E_NOMEM;
   }
-  double best = 0;
-  int best_s = 0;
-  for (int x = 0; x < kKsNumCandidates; ++x) {
-    c->ks_us[x] = -1;
-    const int64_t S = kKsCandidates[x];
-    if (S > n) continue;
+  // microseconds per output of n outputs in slices of S on nstr streams
+  auto measure = [&](int64_t S, int nstr, double* us) -> int {
     for (int rep = 0; rep < 2; ++rep) {   // the first run warms the caches and the code objects
       SFHE_HIP(hipEventRecord(c->tune_ev0, s));
-      for (int64_t o0 = 0; o0 < n; o0 += S) {
-        OutLayout o = ol;
-        o.elem_base += o0;
-        const int rc = keyswitch_rescale_n14(c, lev, D + o0 * dw, dw, o, std::min(S, n - o0), s, scr.ptr);
-        if (rc) return rc;
-      }
+      const int rc = ks_slices(c, lev, D, dw, ol, n, S, nstr, scr.ptr, s);
+      if (rc) return rc;
       SFHE_HIP(hipEventRecord(c->tune_ev1, s));
       SFHE_HIP(hipEventSynchronize(c->tune_ev1));
     }
     float ms = 0;
     SFHE_HIP(hipEventElapsedTime(&ms, c->tune_ev0, c->tune_ev1));
-    c->ks_us[x] = 1e3 * ms / (double)n;
+    *us = 1e3 * ms / (double)n;
+    return SFHE_OK;
+  };
+  double best = 0;
+  int best_s = 0, best_str = 1;
+  for (int x = 0; x < kKsNumCandidates; ++x) {
+    c->ks_us[x] = -1;
+    const int64_t S = kKsCandidates[x];
+    if (S > n) continue;
+    const int rc = measure(S, 1, &c->ks_us[x]);
+    if (rc) return rc;
     if (best_s == 0 || c->ks_us[x] < best) { best = c->ks_us[x]; best_s = (int)S; }
+  }
+  // two streams: two slices in flight share the one-stream scratch
+  c->ks_us2[0] = c->ks_us2[1] = -1;
+  c->ks_s2[0] = std::min<int64_t>(best_s, smax / 2);
+  c->ks_s2[1] = c->ks_s2[0] / 2;
+  for (int x = 0; x < 2; ++x) {
+    const int64_t S = c->ks_s2[x];
+    if (S < kKsCandidates[0] || 2 * S > n) continue;
+    const int rc = measure(S, 2, &c->ks_us2[x]);
+    if (rc) return rc;
+    if (c->ks_us2[x] < best) { best = c->ks_us2[x]; best_s = (int)S; best_str = 2; }
   }
   c->ks_slice = best_s;
   c->ks_tuned_slice = best_s;
+  c->ks_streams = c->ks_tuned_streams = best_str;
   *done = n;
   return SFHE_OK;
 }
@@ -838,6 +912,7 @@ struct LazyPrep {
   std::vector<Batch> batches;
   DevBuf<int> d_ts, d_ek, d_em, d_es, f_ts, f_ek, f_em, f_es, q_ts, q_ek, q_em, q_es, d_bs;
   DevBuf<u64> D, kss;
+  int kss_streams = 0;   // key-switch streams the scratch kss is sized for
   DevBuf<int64_t> d_empty;
   int64_t n_empty = 0, products = 0, keyswitches = 0, max_out = 0, ks_slice = 2048, dw = 0;
   int lev = 0, Nc = 0;
@@ -1010,31 +1085,31 @@ static int lazy_launch(sfhe_ctx* c, LazyPrep& P, hipStream_t s, bool events, boo
                          std::min<int64_t>(cnt, kKsCandidates[kKsNumCandidates - 1]), s, &o_start);
       if (c->ks_slice > 0) P.ks_slice = c->ks_slice;
     }
-    // the key-switch (and rescale) scratch of one slice, allocated once
+    // the key-switch (and rescale) scratch of one slice per key-switch
+    // stream, allocated once (under graph capture: one stream)
+    const int nstr = P.fused && events ? c->ks_streams : 1;
+    if (P.kss.ptr && nstr > P.kss_streams) P.kss.release();
     const int64_t sl = std::min(P.ks_slice, P.max_out);
     const int64_t ks_words = P.fused ? keyswitch_rescale_n14_scratch_words(c, lev, sl) : keyswitch_scratch_words(c, lev, sl);
     if (!rc && !P.kss.ptr) {
+      P.kss_streams = nstr;
       StreamScope scope_(c->alloc, s);
       // rescale_batch's scratch: the last prime's rows and the lifted rows
       const int64_t rs_words = P.fused ? 0 : sl * 2 * N * (1 + lev);
-      if (!P.kss.alloc(&c->alloc, (size_t)(ks_words + rs_words))) {
+      if (!P.kss.alloc(&c->alloc, (size_t)(nstr * ks_words + rs_words))) {
         rc = SFHE_E_NOMEM;
         set_error("device allocation failed for the key-switch scratch");
       }
     }
-    for (int64_t o0 = o_start; o0 < cnt && !rc; o0 += P.ks_slice) {
+    if (P.fused && !rc && o_start < cnt) {   // fused transforms (key switch and rescale together)
+      const OutLayout ol{out->data.ptr, 0, true, out->n_ct, (int64_t)bt.r0 * Nc + o_start};
+      StepTimer tm(c, s, events ? kCatKeyswitch : -1);
+      rc = ks_slices(c, lev, P.D.ptr + o_start * dw, dw, ol, cnt - o_start, P.ks_slice, nstr, P.kss.ptr, s);
+    }
+    for (int64_t o0 = o_start; o0 < cnt && !rc && !P.fused; o0 += P.ks_slice) {
       const int64_t n = std::min(P.ks_slice, cnt - o0);
       u64* Ds = P.D.ptr + o0 * dw;
       const OutLayout ol{out->data.ptr, 0, true, out->n_ct, (int64_t)bt.r0 * Nc + o0};
-      if (P.fused) {   // fused transforms (key switch and rescale together)
-        if (events) {
-          StepTimer tm(c, s, kCatKeyswitch);
-          rc = keyswitch_rescale_n14(c, lev, Ds, dw, ol, n, s, P.kss.ptr);
-        } else {
-          rc = keyswitch_rescale_n14(c, lev, Ds, dw, ol, n, s, P.kss.ptr);
-        }
-        continue;
-      }
       {
         StepTimer tm(c, s, events ? kCatKeyswitch : -1);
         rc = keyswitch_batch(c, lev, Ds + (int64_t)2 * nl * N, dw, Ds, dw, true, n, s, nullptr, P.kss.ptr);
@@ -1246,6 +1321,71 @@ int sfhe_matmul(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule
   GUARD_END
 }
 
+}  // extern "C"
+
+// The tile tables of plaintext weights W, built once when W is encoded and
+// kept on the device beside it: W's rows in tiles of 16, each tile's entries
+// (k, mask of the tile rows that visit k) in ascending k, and per entry and
+// data prime the 16 rows' weights (0 where the row does not visit k): the
+// residue's fp64 bits below 2^42, else the residue with its Shoup companion.
+static int plain_tables(sfhe_ctx* c, sfhe_mat* W) {
+  const int M = W->rows, K = W->cols, L = c->L;
+  const int ntile = (M + 15) / 16;
+  std::vector<int> tstart, ek, emask, kmask(K);
+  std::vector<u64> ew, ews;
+  std::vector<int64_t> kslot((size_t)K * 16);
+  std::vector<std::pair<int, int64_t>> pairs;
+  W->w_pairs = 0;
+  for (int g = 0; g < ntile; ++g) {
+    std::fill(kmask.begin(), kmask.end(), 0);
+    for (int r = 0; r < 16 && g * 16 + r < M; ++r) {
+      row_pairs(W, g * 16 + r, pairs);
+      W->w_pairs += (int64_t)pairs.size();
+      for (auto& pr : pairs) {
+        kmask[pr.first] |= 1 << r;
+        kslot[(size_t)pr.first * 16 + r] = pr.second;
+      }
+    }
+    tstart.push_back((int)ek.size());
+    for (int k = 0; k < K; ++k) {
+      if (!kmask[k]) continue;
+      ek.push_back(k);
+      emask.push_back(kmask[k]);
+      for (int l = 0; l < L; ++l) {
+        const u64 q = c->primes[l];
+        for (int r = 0; r < 16; ++r) {
+          const u64 w = (kmask[k] >> r) & 1 ? W->w_res[(size_t)kslot[(size_t)k * 16 + r] * L + l] : 0;
+          if (q < (1ull << 42)) {
+            const double wd = (double)w;
+            u64 bits;
+            memcpy(&bits, &wd, sizeof(bits));
+            ew.push_back(bits);
+            ews.push_back(0);
+          } else {
+            ew.push_back(w);
+            ews.push_back(hostmath::shoup(w, q));
+          }
+        }
+      }
+    }
+  }
+  tstart.push_back((int)ek.size());
+  if (ek.size() > (size_t)0x7FFFFFFF / 16) { set_error("plaintext weights: too many tile entries"); return SFHE_E_INVALID_ARG; }
+  // synchronous copies: the tables are complete when the call returns
+  auto put = [&](auto& buf, const auto& v) -> bool {
+    if (!buf.alloc(&c->alloc, v.size())) return false;
+    return v.empty() || hipMemcpy(buf.ptr, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice) == hipSuccess;
+  };
+  if (!put(W->d_tstart, tstart) || !put(W->d_ek, ek) || !put(W->d_emask, emask) || !put(W->d_ew, ew) ||
+      !put(W->d_ews, ews)) {
+    set_error("device allocation or copy failed for the weight tables");
+    return SFHE_E_NOMEM;
+  }
+  return SFHE_OK;
+}
+
+extern "C" {
+
 int sfhe_encode_matrix(sfhe_ctx* c, const double* vals, int32_t rows, int32_t cols, int64_t ld, sfhe_encoding enc,
                        int32_t log2_scale_w, sfhe_mat** out) {
   GUARD_BEGIN
@@ -1282,7 +1422,10 @@ int sfhe_encode_matrix(sfhe_ctx* c, const double* vals, int32_t rows, int32_t co
       m->w_res[(size_t)st.first * L + l] = r;
     }
   }
-  *out = m;
+  std::unique_ptr<sfhe_mat> keep(m);
+  const int rc = plain_tables(c, m);
+  if (rc) return rc;
+  *out = keep.release();
   return SFHE_OK;
   GUARD_END
 }
@@ -1310,16 +1453,14 @@ static int64_t plain_scratch_words(const sfhe_ctx* c, int64_t max_outputs) {
 
 // device bytes a plaintext-weight product holds until it completes: its
 // outputs' sums (2 (lev + 1) N words each) and results (2 lev N words each),
-// a rescale scratch for one slice of its outputs, and at most its share of
-// the batch tables (per tile entry: the k, the row mask and 16 weights with
-// Shoup companions per prime; per tile: the start and 4-column descriptors)
+// a rescale scratch for one slice of its outputs, and its block descriptors
+// (one per tile and group of 4 columns) and job record; W's tile tables are
+// W's own, held from its encoding on
 static uint64_t plain_bytes(const sfhe_ctx* c, const sfhe_mat* W, const sfhe_mat* B) {
   const int lev = c->L - 1, nl = lev + 1;
   const uint64_t outs = (uint64_t)W->rows * B->cols;
   const uint64_t tiles = (uint64_t)(W->rows + 15) / 16;
-  const uint64_t entries = tiles * (uint64_t)W->cols;
-  const uint64_t tables = entries * (2 * sizeof(int) + (uint64_t)nl * 16 * 2 * sizeof(u64)) +
-                          tiles * (sizeof(int) + (uint64_t)((B->cols + 3) / 4) * sizeof(int4)) + sizeof(PlainJob);
+  const uint64_t tables = tiles * (uint64_t)((B->cols + 3) / 4) * sizeof(int4) + sizeof(PlainJob);
   return outs * (uint64_t)(2 * nl + 2 * lev) * c->N * sizeof(u64) +
          (uint64_t)plain_scratch_words(c, (int64_t)outs) * sizeof(u64) + tables;
 }
@@ -1333,8 +1474,7 @@ struct PlainPrep {
   std::vector<sfhe_mat*> C;
   std::vector<const sfhe_mat*> B;
   std::vector<PlainJob> jobs;
-  DevBuf<u64> D, ew, ews, pw, pws, scratch;
-  DevBuf<int> ts, ek, em;
+  DevBuf<u64> D, pw, pws, scratch;
   DevBuf<int4> desc;
   DevBuf<PlainJob> d_jobs;
   int n_desc = 0;
@@ -1362,61 +1502,23 @@ static int plain_prepare(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, 
   P.B.assign(Bm, Bm + count);
   const int N = c->N, lev = c->L - 1, nl = lev + 1;
   const int64_t dw = (int64_t)2 * nl * N;   // words per output sum
-  // host tables: tiles of 16 rows per job, their entries (k, row mask) and
-  // the weights of each entry, row and prime
+  // per job: its outputs' place in D and W's tile tables; per block group:
+  // (job, tile, column group)
   P.jobs.resize(count);
   std::vector<int4> desc;
-  std::vector<int> tstart, ek, emask;
-  std::vector<u64> ew, ews;
   std::vector<std::pair<int, int64_t>> pairs;
   int64_t outs = 0, products = 0;
-  int tiles = 0;
   for (int n = 0; n < count; ++n) {
     const sfhe_mat *W = Wm[n], *B = Bm[n];
-    const int M = W->rows, K = W->cols, Nc = B->cols;
-    P.jobs[n] = PlainJob{B->data.ptr, B->n_ct, Nc, M, tiles, outs};
+    const int M = W->rows, Nc = B->cols;
+    P.jobs[n] = PlainJob{B->data.ptr, B->n_ct, Nc, M, W->d_tstart.ptr, W->d_ek.ptr, W->d_emask.ptr,
+                         W->d_ew.ptr, W->d_ews.ptr, outs};
     const int ntile = (M + 15) / 16, ncg = (Nc + 3) / 4;
-    std::vector<int> kmask(K);
-    std::vector<int64_t> kslot((size_t)K * 16);
-    for (int g = 0; g < ntile; ++g) {
-      std::fill(kmask.begin(), kmask.end(), 0);
-      for (int r = 0; r < 16 && g * 16 + r < M; ++r) {
-        row_pairs(W, g * 16 + r, pairs);
-        products += (int64_t)pairs.size() * Nc;
-        for (auto& pr : pairs) {
-          kmask[pr.first] |= 1 << r;
-          kslot[(size_t)pr.first * 16 + r] = pr.second;
-        }
-      }
-      tstart.push_back((int)ek.size());
-      for (int k = 0; k < K; ++k) {
-        if (!kmask[k]) continue;
-        ek.push_back(k);
-        emask.push_back(kmask[k]);
-        for (int l = 0; l < nl; ++l) {
-          const u64 q = c->primes[l];
-          for (int r = 0; r < 16; ++r) {
-            const u64 w = (kmask[k] >> r) & 1 ? W->w_res[(size_t)kslot[(size_t)k * 16 + r] * c->L + l] : 0;
-            if (q < (1ull << 42)) {
-              const double wd = (double)w;
-              u64 bits;
-              memcpy(&bits, &wd, sizeof(bits));
-              ew.push_back(bits);
-              ews.push_back(0);
-            } else {
-              ew.push_back(w);
-              ews.push_back(hostmath::shoup(w, q));
-            }
-          }
-        }
-      }
+    for (int g = 0; g < ntile; ++g)
       for (int h = 0; h < ncg; ++h) desc.push_back(make_int4(n, g, h, 0));
-      ++tiles;
-    }
+    products += W->w_pairs * Nc;
     outs += (int64_t)M * Nc;
   }
-  tstart.push_back((int)ek.size());
-  if (ek.size() > (size_t)0x7FFFFFFF / 16) { set_error("plaintext-weight product: too many entries"); return SFHE_E_INVALID_ARG; }
   P.n_desc = (int)desc.size();
   P.products = products;
   P.outs = outs;
@@ -1436,9 +1538,8 @@ static int plain_prepare(sfhe_ctx* c, int32_t count, const sfhe_mat* const* Wm, 
     o->nnz = o->n_ct;
     if (!o->data.alloc(&c->alloc, (size_t)o->n_ct * 2 * lev * N)) { set_error("device allocation failed for a result"); return SFHE_E_NOMEM; }
   }
-  if (!P.D.alloc(&c->alloc, (size_t)std::max<int64_t>(outs, 1) * dw) || !upload(c, P.ts, tstart, s) ||
-      !upload(c, P.ek, ek, s) || !upload(c, P.em, emask, s) || !upload(c, P.ew, ew, s) || !upload(c, P.ews, ews, s) ||
-      !upload(c, P.desc, desc, s) || !upload(c, P.d_jobs, P.jobs, s) ||
+  if (!P.D.alloc(&c->alloc, (size_t)std::max<int64_t>(outs, 1) * dw) || !upload(c, P.desc, desc, s) ||
+      !upload(c, P.d_jobs, P.jobs, s) ||
       !P.scratch.alloc(&c->alloc, (size_t)plain_scratch_words(c, max_outs))) {
     set_error("device allocation failed (the sums of every output are held at once)");
     return SFHE_E_NOMEM;
@@ -1478,7 +1579,7 @@ static int plain_launch(sfhe_ctx* c, const PlainPrep& P, hipStream_t s) {
   const int64_t dw = (int64_t)2 * nl * N;
   int rc = SFHE_OK;
   if (P.launch == SFHE_PLAIN_FUSED) {
-    PlainBatch pb{P.d_jobs.ptr, P.desc.ptr, P.n_desc, P.ts.ptr, P.ek.ptr, P.em.ptr, P.ew.ptr, P.ews.ptr, nl, P.D.ptr};
+    PlainBatch pb{P.d_jobs.ptr, P.desc.ptr, P.n_desc, nl, P.D.ptr};
     rc = launch_plain_batch(c, pb, s);
   } else {
     rc = launch_zero(P.D.ptr, std::max<int64_t>(P.outs, 1) * dw, s);
@@ -1772,12 +1873,15 @@ void sfhe_plain_graph_destroy(sfhe_plain_graph* G) { delete G; }
 // order; each step first retires the batches whose end event has passed,
 // then admits queued requests while the device bytes they hold until they
 // complete (sums, results, rescale scratch, tables) fit the budget, and
-// enqueues them as one fused batch on the least busy of the server's
-// streams (at most kServerStreams, the hardware queues of a process).  A
-// batch admitted while others run starts at once on another stream, so
-// batches overlap on the device; its launches first wait for the work the
-// caller enqueued on the client stream before the step (the requests'
-// encryptions).
+// enqueues them as one fused batch on the server stream (at most
+// kServerStreams, the hardware queues of a process) with the fewest running
+// batches.  With one stream, batches run in admission order; with several,
+// a batch admitted while others run starts at once on its own stream and
+// overlaps them on the device.  With a slot limit, a stream holding that
+// many running batches takes no more, and while every stream is full,
+// arriving requests wait on the host and join the next batch.  A batch's
+// launches first wait for the work the caller enqueued on the client stream
+// before the step (the requests' encryptions).
 constexpr int kServerStreams = 4;
 
 struct sfhe_server {
@@ -1785,6 +1889,7 @@ struct sfhe_server {
   hipStream_t client = nullptr;           // the caller's stream (inputs are ready in its order)
   std::vector<hipStream_t> streams;       // the server's own, default priority
   std::vector<int> busy;                  // running batches per stream
+  int slots = 0;                          // running batches a stream may hold (0: no limit)
   hipEvent_t epoch = nullptr;             // device-time origin of the batch intervals
   uint64_t budget = 0, in_flight = 0;
   struct Req {
@@ -1897,6 +2002,12 @@ int sfhe_server_step(sfhe_server* v, int32_t* admitted) {
   *admitted = 0;
   int rc = v->retire(false);
   if (rc) return rc;
+  // the stream with the fewest running batches; at the slot limit the
+  // requests wait and join the next batch
+  int sx = 0;
+  for (int x = 1; x < (int)v->streams.size(); ++x)
+    if (v->busy[x] < v->busy[sx]) sx = x;
+  if (v->slots > 0 && v->busy[sx] >= v->slots) return SFHE_OK;
   std::vector<const sfhe_mat*> Ws, Xs;
   sfhe_server::Run run;
   while (!v->queue.empty() && v->in_flight + run.bytes + v->queue.front().bytes <= v->budget) {
@@ -1908,10 +2019,7 @@ int sfhe_server_step(sfhe_server* v, int32_t* admitted) {
     v->queue.pop_front();
   }
   if (Ws.empty()) return SFHE_OK;
-  // the least busy stream; its launches wait for the client stream's work
-  int sx = 0;
-  for (int x = 1; x < (int)v->streams.size(); ++x)
-    if (v->busy[x] < v->busy[sx]) sx = x;
+  // the batch's launches wait for the client stream's work
   run.stream = sx;
   hipStream_t bs = v->streams[sx];
   run.C.assign(Ws.size(), nullptr);
@@ -1980,6 +2088,14 @@ int sfhe_server_poll(sfhe_server* v, int64_t ticket, int32_t wait, int32_t* is_d
   if (start_ms) *start_ms = it->second.t0;
   if (end_ms) *end_ms = it->second.t1;
   v->done.erase(it);
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_server_set_slots(sfhe_server* v, int32_t per_stream) {
+  GUARD_BEGIN
+  if (!v || per_stream < 0) { set_error("NULL server or negative slot limit"); return SFHE_E_INVALID_ARG; }
+  v->slots = per_stream;
   return SFHE_OK;
   GUARD_END
 }

@@ -101,24 +101,23 @@ __global__ void __launch_bounds__(64 * kPlainCols) ctpt_block_kernel(PlainBatch 
   // B word of stored ciphertext e, poly p: Bl[e * 64 + p * pstride] (chunked layout)
   const u64* Bl = J.B + ((int64_t)l * nchunk + (t >> 6)) * 2 * J.nB * 64 + lane;
   const int64_t pstride = J.nB * 64;
-  const int tile = J.tile0 + g;
-  const int e0 = pb.tstart[tile], e1 = pb.tstart[tile + 1];
+  const int e0 = J.tstart[g], e1 = J.tstart[g + 1];
   typename Ar::Acc acc0[kPlainTileRows], acc1[kPlainTileRows];
 #pragma unroll
   for (int r = 0; r < kPlainTileRows; ++r) acc0[r] = acc1[r] = Ar::zero();
   if (e0 < e1) {
-    int k = pb.ek[e0];
+    int k = J.ek[e0];
     u64 nb0 = Bl[((int64_t)k * J.Nc + j) * 64], nb1 = Bl[((int64_t)k * J.Nc + j) * 64 + pstride];
     int cnt = 0;
     for (int e = e0; e < e1; ++e) {
       const typename Ar::In b0 = Ar::in(nb0), b1 = Ar::in(nb1);
-      const int mask = pb.emask[e];
+      const int mask = J.emask[e];
       const int en = e + 1 < e1 ? e + 1 : e;
-      k = pb.ek[en];
+      k = J.ek[en];
       nb0 = Bl[((int64_t)k * J.Nc + j) * 64];
       nb1 = Bl[((int64_t)k * J.Nc + j) * 64 + pstride];
-      const u64* wv = pb.ew + ((int64_t)e * pb.nl + l) * kPlainTileRows;
-      const u64* wsv = pb.ews + ((int64_t)e * pb.nl + l) * kPlainTileRows;
+      const u64* wv = J.ew + ((int64_t)e * pb.nl + l) * kPlainTileRows;
+      const u64* wsv = J.ews + ((int64_t)e * pb.nl + l) * kPlainTileRows;
 #pragma unroll
       for (int r = 0; r < kPlainTileRows; ++r) {
         if ((mask >> r) & 1) {

@@ -143,6 +143,14 @@ struct sfhe_ctx {
   int ks_slice = 0, ks_tuned_slice = 0;
   double ks_us[6] = {-1, -1, -1, -1, -1, -1};
   hipEvent_t tune_ev0 = nullptr, tune_ev1 = nullptr;
+  // key switching on one stream or on two side streams (forked from and
+  // joined into the call's stream): in use, as tuned, the two-stream slices
+  // measured and their microseconds per output
+  int ks_streams = 1, ks_tuned_streams = 1;
+  int64_t ks_s2[2] = {0, 0};
+  double ks_us2[2] = {-1, -1};
+  hipStream_t ks_side[2] = {nullptr, nullptr};
+  hipEvent_t ks_fork = nullptr, ks_join[2] = {nullptr, nullptr};
   // keys
   bool has_keys = false;
   sfhe::DevBuf<sfhe::u64> d_s;           // secret, NTT domain [nb][N]
@@ -185,6 +193,10 @@ struct sfhe_mat {
   // each stored weight per data prime, host side, [n_ct][L]
   bool plain = false;
   std::vector<uint64_t> w_res;
+  // and its tile tables on the device (the layout of PlainJob's)
+  int64_t w_pairs = 0;                   // stored weights outside ELL padding
+  sfhe::DevBuf<int> d_tstart, d_ek, d_emask;
+  sfhe::DevBuf<sfhe::u64> d_ew, d_ews;
   // several values per ciphertext (Sec. 3.2): stored value v sits in slot
   // v mod slots of ciphertext v / slots; n_ct = ceil(n_vals / slots)
   int slots = 1;
@@ -288,26 +300,24 @@ int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& t
 int tensor_fp_prime_count(const sfhe_ctx* c);
 
 // ---- plaintext weights times encrypted values (ctpt.hip) ----
-// one matmul W B of a batch: W's tiles of 16 rows are tile0 .. tile0 +
-// ceil(rows / 16) - 1 of the batch's tile arrays, its outputs d0 ..
-// d0 + rows * Nc - 1 of D (row-major)
+// one matmul W B of a batch: W's tile tables (held by W, built when it was
+// encoded) and its outputs d0 .. d0 + rows * Nc - 1 of D (row-major)
 struct PlainJob {
-  const u64* B;      // encrypted K x Nc dense matrix, chunked layout, nB stored ciphertexts
+  const u64* B;          // encrypted K x Nc dense matrix, chunked layout, nB stored ciphertexts
   int64_t nB;
   int Nc, rows;
-  int tile0;
+  const int* tstart;     // [tiles + 1] entry range of each 16-row tile of W
+  const int* ek;         // k of each entry (ascending within a tile)
+  const int* emask;      // bit r: tile row r visits k
+  const u64* ew;         // [entry][L][16] weight of each tile row: the residue, as fp64 bits below 2^42
+  const u64* ews;        // [entry][L][16] Shoup companions (primes of 2^42 and above)
   int64_t d0;
 };
 struct PlainBatch {
   const PlainJob* jobs;
   const int4* desc;      // per block group (job, tile within the job, column group of 4, 0)
   int n_desc;
-  const int* tstart;     // [tiles + 1] entry range of each tile
-  const int* ek;         // k of each entry (ascending within a tile)
-  const int* emask;      // bit r: tile row r visits k
-  const u64* ew;         // [entry][nl][16] weight of each tile row: the residue, as fp64 bits below 2^42
-  const u64* ews;        // [entry][nl][16] Shoup companions (primes of 2^42 and above)
-  int nl;                // primes of B and of the weight tables
+  int nl;                // primes of B and of the weight tables (L: B at the top level)
   u64* D;                // [output][2][nl][N] sums, NTT domain
 };
 // every product of the batch, in one launch per arithmetic (fp64, integer)

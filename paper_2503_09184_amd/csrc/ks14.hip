@@ -20,21 +20,22 @@
 //  K3a (b, p)   the last prime of the key-switched sum, in coefficients:
 //               r = iNTT(acc_lev P^-1 + d_lev) - z_lev P^-1 with
 //               z_i = sum_k yP_k [P/p_k]_{q_i}.
-//  Lift (b, p, i, x)  w_i = z_i P^-1 + [centered r]_{q_i} for i < lev
-//               (element-wise).
-//  K3b (b, p, i), i < lev:  C_i = (acc_i P^-1 + d_i - NTT(w_i)) q_lev^-1.
+//  K3b (b, p, i), i < lev:  C_i = (acc_i P^-1 + d_i - NTT(w_i)) q_lev^-1,
+//               with the lift w_i = z_i P^-1 + [centered r]_{q_i} computed
+//               as the row is loaded.
 //
 // Every identity is exact modular arithmetic, so the result is the same, bit
 // for bit, as key switching with centered fast base conversions followed by
 // an exactly rounded rescale.  Per output this takes 4 L + 4 + (the base
 // conversions') transforms -- 32 at L = 5, alpha = 3, dnum = 2 -- instead of
-// the 42 of the separate steps.  The transform kernels only load, transform
-// and store with light arithmetic on either side; the two base conversions,
-// whose sums over primes would not fit beside a row in registers, are
-// element-wise kernels of their own.
+// the 42 of the separate steps.  The transform kernels load, transform and
+// store with light arithmetic on either side; ModUp's base conversion, whose
+// rows are each read by several target primes' transforms spread over the
+// chip, is an element-wise kernel of its own, while ModDown's (the lift)
+// is taken by K3b as it loads.
 //
 // Without the rescale (a rotation's key switch: D = (c0, 0, c1) after the
-// automorphism) K3a is skipped, the lift gives w_i = z_i P^-1 for every
+// automorphism) K3a is skipped, the lift is w_i = z_i P^-1 for every
 // i <= lev and K3b writes acc_i P^-1 + d_i - NTT(w_i) itself.
 //
 // Each transform block has 512 threads and 66.5 KiB of LDS, two blocks per
@@ -69,7 +70,6 @@ struct Ks14Args {
   u64* part;             // [n][alpha][2][N]    key products on the special primes so far, NTT domain
   u64* yP;               // [n][2][alpha][N]    ModDown inputs, coefficients
   u64* r;                // [n][2][N]           last prime of the key-switched sum, coefficients
-  u64* w;                // [n][2][lev][N]      rescale inputs of the remaining primes, coefficients
   const u64* rlk;        // [dnum][2][nb][N]
   const u64* rlk_s;      // Shoup companions of rlk
   const ModUpConst* mu;  // [dnum] at this level
@@ -368,57 +368,78 @@ __global__ void __launch_bounds__(n14::kThreads, 4) ks14_k3a_kernel(Ks14Args a, 
 }
 
 // ---------------------------------------------------------------- Lift
-// grid (N / kEwSpan, 2 n rows), rows = lev with the rescale (RS), else
-// lev + 1: block row (b * 2 + p) * rows + i.  Without the rescale w_i is
-// z_i P^-1 alone.
-template <int ALPHA, bool RS>
-__global__ void __launch_bounds__(kEwThreads) ks14_lift_kernel(Ks14Args a, DevParams dp) {
-  const int x0 = blockIdx.x * kEwSpan + threadIdx.x;
-  const int lev = a.lev, rows = RS ? lev : lev + 1;
-  const int bp = blockIdx.y / rows, i = blockIdx.y % rows;   // bp = b * 2 + p
-  const u64 ql = dp.pr[lev].q;
-  const PrimeDev& P = dp.pr[i];
-  const u64 q = P.q;
-  const u64 Pi = a.md->Pinv[i], Pis = a.md->Pinv_s[i];
+// w_i at the positions pos_a(t, u) of thread t, taken while K3b loads its
+// row: z_i P^-1, plus the centered last prime r reduced mod q_i with the
+// rescale (RS).  The lift reads the same ALPHA + 1 coefficient rows of (b, p)
+// for every target prime i; K3b's blocks of one (b, p) run back to back on
+// one XCD, so those rows come from its L2 after the first block.
+template <int ALPHA>
+struct LiftConsts {
+  const u64 *yb, *rb;            // yP rows and r row of (b, p)
+  u64 q, ql, Pi, Pis, mu_hi, mu_lo;
   u64 cv[ALPHA], cs[ALPHA], ph[ALPHA];
+};
+
+template <int ALPHA, bool RS>
+__device__ __forceinline__ u64 lift_one(const LiftConsts<ALPHA>& lc, int x) {
+  const u64 q = lc.q;
+  u64 z = 0, above = 0;   // centered conversion: residues above (p_k - 1) / 2 stand for y - p_k
 #pragma unroll
   for (int k = 0; k < ALPHA; ++k) {
-    cv[k] = a.md->conv[k][i];
-    cs[k] = a.md->conv_s[k][i];
-    ph[k] = (dp.pr[dp.L + k].q - 1) / 2;
+    const u64 y = lc.yb[(int64_t)k * kN + x];
+    z = add_mod(z, mul_shoup(y, lc.cv[k], lc.cs[k], q), q);
+    above += y > lc.ph[k];
   }
-  const u64* yb = a.yP + (int64_t)bp * ALPHA * kN + x0;
-  const u64* rb = a.r + (int64_t)bp * kN + x0;
-  u64* o = a.w + (int64_t)blockIdx.y * kN + x0;
-#pragma unroll
-  for (int m = 0; m < kEwPer; ++m) {
-    u64 z = 0, above = 0;   // centered conversion: residues above (p_k - 1) / 2 stand for y - p_k
-#pragma unroll
-    for (int k = 0; k < ALPHA; ++k) {
-      const u64 y = yb[(int64_t)k * kN + m * kEwThreads];
-      z = add_mod(z, mul_shoup(y, cv[k], cs[k], q), q);
-      above += y > ph[k];
-    }
-    const u64 zp = sub_mod(mul_shoup(z, Pi, Pis, q), above, q);
-    if (!RS) {
-      o[m * kEwThreads] = zp;
-      continue;
-    }
-    // centered lift of the last prime, reduced mod q_i
-    const u64 c = rb[m * kEwThreads];
-    const bool neg = c > (ql - 1) / 2;
-    const u64 mag = neg ? ql - c : c;
-    u64 r = mag < q ? mag : reduce_wide(U128{mag, 0}, q, P.mu_hi, P.mu_lo);
+  u64 w = sub_mod(mul_shoup(z, lc.Pi, lc.Pis, q), above, q);
+  if (RS) {   // centered lift of the last prime, reduced mod q_i
+    const u64 c = lc.rb[x];
+    const bool neg = c > (lc.ql - 1) / 2;
+    const u64 mag = neg ? lc.ql - c : c;
+    u64 r = reduce_wide(U128{mag, 0}, q, lc.mu_hi, lc.mu_lo);
     r = (neg && r) ? q - r : r;
-    o[m * kEwThreads] = add_mod(zp, r, q);
+    w = add_mod(w, r, q);
   }
+  return w;
+}
+
+// register U and the ones after it, unrolled at compile time (a loop this
+// long is not always unrolled, and a run-time index would put v in scratch)
+template <int U, int ALPHA, bool RS, typename Ar>
+__device__ __forceinline__ void lift_steps(const Ar& ar, typename Ar::Val (&v)[32], const LiftConsts<ALPHA>& lc, int t) {
+  if constexpr (U < 32) {
+    v[U] = ar.in(lift_one<ALPHA, RS>(lc, pos_a(t, U)));
+    group_fence<4>(U);
+    lift_steps<U + 1, ALPHA, RS>(ar, v, lc, t);
+  }
+}
+
+template <int ALPHA, bool RS, typename Ar>
+__device__ __forceinline__ void load_lift(const Ar& ar, typename Ar::Val (&v)[32], const Ks14Args& a,
+                                          const DevParams& dp, int bp, int i, int t) {
+  LiftConsts<ALPHA> lc;
+  const PrimeDev& P = dp.pr[i];
+  lc.yb = a.yP + (int64_t)bp * ALPHA * kN;
+  lc.rb = a.r + (int64_t)bp * kN;
+  lc.q = P.q;
+  lc.ql = dp.pr[a.lev].q;
+  lc.Pi = a.md->Pinv[i];
+  lc.Pis = a.md->Pinv_s[i];
+  lc.mu_hi = P.mu_hi;
+  lc.mu_lo = P.mu_lo;
+#pragma unroll
+  for (int k = 0; k < ALPHA; ++k) {
+    lc.cv[k] = a.md->conv[k][i];
+    lc.cs[k] = a.md->conv_s[k][i];
+    lc.ph[k] = (dp.pr[dp.L + k].q - 1) / 2;
+  }
+  lift_steps<0, ALPHA, RS>(ar, v, lc, t);
 }
 
 // ---------------------------------------------------------------- K3b
 // RS: C_i = (acc_i P^-1 + d_i - NTT(w_i)) q_lev^-1 for i < lev; else the
 // key-switched sum itself, acc_i P^-1 + d_i - NTT(w_i) for i <= lev (limb-major
 // output rows only)
-template <typename Ar, bool RS>
+template <int ALPHA, typename Ar, bool RS>
 __device__ __forceinline__ void k3b_body(const Ks14Args& a, const DevParams& dp, const OutLayout& ol, int b, int p, int i,
                                          void* lds) {
   typedef typename Ar::Val Val;
@@ -429,7 +450,7 @@ __device__ __forceinline__ void k3b_body(const Ks14Args& a, const DevParams& dp,
   const u64 Pi = a.md->Pinv[i], Pis = a.md->Pinv_s[i];
   Val v[32];
   const int rows = RS ? lev : lev + 1;
-  load_a(ar, v, a.w + (((int64_t)b * 2 + p) * rows + i) * kN, t);
+  load_lift<ALPHA, RS>(ar, v, a, dp, b * 2 + p, i, t);
   n14::forward(ar, v, reinterpret_cast<Val*>(lds), t);
   const u64* acc = a.accQ + (((int64_t)b * 2 + p) * a.nl + i) * kN;
   const u64* d = a.D + (int64_t)b * a.dw + (int64_t)(p * a.nl + i) * kN;
@@ -467,17 +488,20 @@ __device__ __forceinline__ void k3b_body(const Ks14Args& a, const DevParams& dp,
   }
 }
 
-template <bool RS>
+// blocks (b, p, i), i fastest, in XCD ranges: the target primes of one
+// (b, p) share the lift's source rows through one L2
+template <int ALPHA, bool RS>
 __global__ void __launch_bounds__(n14::kThreads, 4) ks14_k3b_kernel(Ks14Args a, OutLayout ol, DevParams dp) {
   extern __shared__ u64 lds[];
   const int rows = RS ? a.lev : a.lev + 1;
-  const int b = blockIdx.x / (2 * rows);
-  const int rem = blockIdx.x % (2 * rows);
+  const int w = xcd_range_index(blockIdx.x, gridDim.x);
+  const int b = w / (2 * rows);
+  const int rem = w % (2 * rows);
   const int p = rem / rows, i = rem % rows;
   if (dp.pr[i].q < (1ull << 42))
-    k3b_body<NttFp, RS>(a, dp, ol, b, p, i, lds);
+    k3b_body<ALPHA, NttFp, RS>(a, dp, ol, b, p, i, lds);
   else
-    k3b_body<NttInt, RS>(a, dp, ol, b, p, i, lds);
+    k3b_body<ALPHA, NttInt, RS>(a, dp, ol, b, p, i, lds);
 }
 
 template <int NT>
@@ -509,8 +533,8 @@ int launch_ks14(sfhe_ctx* c, const Ks14Args& a, int ndig, OutLayout out, int64_t
   if (!attr) {
     const void* fns[4] = {reinterpret_cast<const void*>(&ks14_k1_kernel),
                           reinterpret_cast<const void*>(&ks14_k3a_kernel<ALPHA>),
-                          reinterpret_cast<const void*>(&ks14_k3b_kernel<true>),
-                          reinterpret_cast<const void*>(&ks14_k3b_kernel<false>)};
+                          reinterpret_cast<const void*>(&ks14_k3b_kernel<ALPHA, true>),
+                          reinterpret_cast<const void*>(&ks14_k3b_kernel<ALPHA, false>)};
     for (const void* f : fns) SFHE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
@@ -528,20 +552,14 @@ int launch_ks14(sfhe_ctx* c, const Ks14Args& a, int ndig, OutLayout out, int64_t
     default: rc = launch_k2<4>(c, a, n, lds, s); break;
   }
   if (rc) return rc;
-  if (!rescale) {   // the key-switched sum itself: no last-prime transform, no lift
-    hipLaunchKernelGGL((ks14_lift_kernel<ALPHA, false>), dim3(kN / kEwSpan, (unsigned)(n * 2 * nl)), dim3(kEwThreads), 0, s,
-                       a, c->dp);
-    SFHE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(ks14_k3b_kernel<false>, dim3((unsigned)(n * 2 * nl)), blk, lds, s, a, out, c->dp);
+  if (!rescale) {   // the key-switched sum itself: no last-prime transform
+    hipLaunchKernelGGL((ks14_k3b_kernel<ALPHA, false>), dim3((unsigned)(n * 2 * nl)), blk, lds, s, a, out, c->dp);
     SFHE_HIP(hipGetLastError());
     return SFHE_OK;
   }
   hipLaunchKernelGGL(ks14_k3a_kernel<ALPHA>, dim3((unsigned)(n * 2)), blk, lds, s, a, c->dp);
   SFHE_HIP(hipGetLastError());
-  hipLaunchKernelGGL((ks14_lift_kernel<ALPHA, true>), dim3(kN / kEwSpan, (unsigned)(n * 2 * lev)), dim3(kEwThreads), 0, s, a,
-                     c->dp);
-  SFHE_HIP(hipGetLastError());
-  hipLaunchKernelGGL(ks14_k3b_kernel<true>, dim3((unsigned)(n * 2 * lev)), blk, lds, s, a, out, c->dp);
+  hipLaunchKernelGGL((ks14_k3b_kernel<ALPHA, true>), dim3((unsigned)(n * 2 * lev)), blk, lds, s, a, out, c->dp);
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;
 }
@@ -671,8 +689,8 @@ int rescale_n14(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout out, i
 }
 
 // rows of each working buffer per output, in allocation order: y, ext,
-// accQ, part, yP, r, w
-static void ks14_rows(const sfhe_ctx* c, int lev, bool rescale, int64_t rows[7]) {
+// accQ, part, yP, r
+static void ks14_rows(const sfhe_ctx* c, int lev, bool rescale, int64_t rows[6]) {
   const int nl = lev + 1, ne = nl + c->alpha;
   int next = 0;
   for (int j = 0; j < c->dnum; ++j) {
@@ -685,14 +703,13 @@ static void ks14_rows(const sfhe_ctx* c, int lev, bool rescale, int64_t rows[7])
   rows[2] = 2 * nl;
   rows[3] = 2 * c->alpha;
   rows[4] = 2 * c->alpha;
-  rows[5] = 2;
-  rows[6] = 2 * (rescale ? lev : nl);
+  rows[5] = rescale ? 2 : 0;
 }
 
 int64_t keyswitch_rescale_n14_scratch_words(const sfhe_ctx* c, int lev, int64_t n) {
-  int64_t rows[7], t = 0;
+  int64_t rows[6], t = 0;
   ks14_rows(c, lev, true, rows);
-  for (int x = 0; x < 7; ++x) t += rows[x];
+  for (int x = 0; x < 6; ++x) t += rows[x];
   return t * n * kN;
 }
 
@@ -720,11 +737,11 @@ static int ks14_run(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout ou
     return SFHE_E_INVALID_ARG;
   }
   // working rows: from the caller's scratch (ks14_rows order), else allocated
-  int64_t rows[7];
+  int64_t rows[6];
   ks14_rows(c, lev, rescale, rows);
-  DevBuf<u64> bufs[7];
-  u64* ptr[7];
-  for (int x = 0; x < 7; ++x) {
+  DevBuf<u64> bufs[6];
+  u64* ptr[6];
+  for (int x = 0; x < 6; ++x) {
     if (scratch) {
       ptr[x] = scratch;
       scratch += (size_t)n * rows[x] * kN;
@@ -746,7 +763,6 @@ static int ks14_run(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayout ou
   a.part = ptr[3];
   a.yP = ptr[4];
   a.r = ptr[5];
-  a.w = ptr[6];
   a.rlk = key;
   a.rlk_s = key_s;
   a.mu = c->d_modup.ptr + (size_t)lev * c->dnum;

@@ -33,7 +33,7 @@ EXPORTED = [
     "sfhe_server_destroy", "sfhe_plain_graph_create", "sfhe_plain_graph_launch", "sfhe_plain_graph_result",
     "sfhe_plain_graph_destroy", "sfhe_encrypt_matrix_slots", "sfhe_matmul_slots", "sfhe_export_stored",
     "sfhe_rotate", "sfhe_ntt_tuning", "sfhe_set_ntt_variant", "sfhe_keyswitch_noalloc",
-    "sfhe_probe_valu", "sfhe_server_request_bytes", "sfhe_ks_tuning", "sfhe_set_ks_slice",
+    "sfhe_probe_valu", "sfhe_server_request_bytes", "sfhe_server_set_slots", "sfhe_ks_tuning", "sfhe_set_ks_slice",
     "sfhe_matmul_graph_create", "sfhe_matmul_graph_launch", "sfhe_matmul_graph_result", "sfhe_matmul_graph_destroy",
 ]
 
@@ -127,6 +127,7 @@ def lib():
         L.sfhe_matmul_plain_batch.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp,
                                               ctypes.POINTER(vp)]
         L.sfhe_server_create.argtypes = [vp, u64, i32, vp, ctypes.POINTER(vp)]
+        L.sfhe_server_set_slots.argtypes = [vp, i32]
         L.sfhe_server_submit.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
         L.sfhe_server_request_bytes.argtypes = [vp, vp, vp, ctypes.POINTER(u64)]
         L.sfhe_server_step.argtypes = [vp, ctypes.POINTER(i32)]
@@ -155,9 +156,10 @@ def lib():
         L.sfhe_rotate.argtypes = [vp, i32, vp, vp, i32, i32, vp]
         L.sfhe_ntt_tuning.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), i32]
         L.sfhe_set_ntt_variant.argtypes = [vp, i32, i32]
-        L.sfhe_ks_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
-                                     i32]
-        L.sfhe_set_ks_slice.argtypes = [vp, i32]
+        L.sfhe_ks_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                     ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32),
+                                     ctypes.POINTER(ctypes.c_double)]
+        L.sfhe_set_ks_slice.argtypes = [vp, i32, i32]
         _lib = L
     return _lib
 
@@ -277,13 +279,21 @@ class MatmulGraph:
 class Server:
     """The library's request loop over plaintext-weight products (a handle)."""
 
-    def __init__(self, ctx, budget_bytes, stream=None, n_streams=4):
+    def __init__(self, ctx, budget_bytes, stream=None, n_streams=1, slots=0):
+        """n_streams: the server's streams (1: batches run in admission
+        order); slots: running batches a stream may hold (0: no limit)."""
         self.ctx = ctx
         h = ctypes.c_void_p()
         _check(lib().sfhe_server_create(ctx._h, ctypes.c_uint64(int(budget_bytes)), int(n_streams),
                                         _stream_handle(stream), ctypes.byref(h)))
         self._h = h
+        if slots:
+            self.set_slots(slots)
         self.intervals = {}   # ticket -> (start_ms, end_ms) of its batch on the device
+
+    def set_slots(self, per_stream):
+        """at most per_stream running batches per server stream (0: no limit)"""
+        _check(lib().sfhe_server_set_slots(self._h, int(per_stream)))
 
     def request_bytes(self, W, X):
         """Device bytes counted for request W X against the budget."""
@@ -359,7 +369,7 @@ class Context:
                 # bound now: at interpreter exit the torch module's attributes
                 # may be gone before the context is destroyed
                 t_alloc = torch.cuda.caching_allocator_alloc
-                t_free = torch.cuda.caching_allocator_delete
+                t_free = torch._C._cuda_cudaCachingAllocator_raw_delete
 
                 def user_alloc(nbytes, stream):
                     return t_alloc(int(nbytes), dev, int(stream))
@@ -519,15 +529,18 @@ class Context:
         return self.NTT_DESIGNS[v.value], {n: us[i] for i, n in enumerate(self.NTT_DESIGNS) if us[i] >= 0}
 
     def ks_tuning(self):
-        """(slice in use, {candidate slice: measured us per output})."""
-        sl = ctypes.c_int32()
-        sizes = (ctypes.c_int32 * 6)()
-        us = (ctypes.c_double * 6)()
-        _check(lib().sfhe_ks_tuning(self._h, ctypes.byref(sl), sizes, us, 6))
-        return sl.value, {int(sizes[x]): float(us[x]) for x in range(6)}
+        """(slice in use, streams in use, {one-stream slice: us per output},
+        {two-stream slice: us per output})."""
+        sl, st = ctypes.c_int32(), ctypes.c_int32()
+        sizes, sizes2 = (ctypes.c_int32 * 6)(), (ctypes.c_int32 * 2)()
+        us, us2 = (ctypes.c_double * 6)(), (ctypes.c_double * 2)()
+        _check(lib().sfhe_ks_tuning(self._h, ctypes.byref(sl), ctypes.byref(st), sizes, us, 6, sizes2, us2))
+        return (sl.value, st.value, {int(sizes[x]): float(us[x]) for x in range(6)},
+                {int(sizes2[x]): float(us2[x]) for x in range(2)})
 
-    def set_ks_slice(self, slice_):
-        _check(lib().sfhe_set_ks_slice(self._h, int(slice_)))
+    def set_ks_slice(self, slice_, streams=1):
+        """slice_ -1: back to the tuned setting; 0: tune again."""
+        _check(lib().sfhe_set_ks_slice(self._h, int(slice_), int(streams)))
 
     def set_ntt_design(self, inverse, design):
         """Force a design by name, or None for the measured choice."""

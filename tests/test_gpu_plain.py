@@ -139,7 +139,11 @@ def test_plain_errors(torch_cuda):
     with pytest.raises(sfhe.SfheError) as e:
         ctx.encode_weights(np.full((2, 2), 2.0 ** 30), "dense", 40)
     assert e.value.code == -1
-    assert Wp.info().device_bytes == 0
+    # the tile tables: per 16-row tile its entries' k and row mask, per entry
+    # and data prime 16 weights and 16 Shoup companions (4 x 3 weights: one tile)
+    Wd = W.sparse_matrix(4, 3, 0.5, 7)
+    kk = int(np.count_nonzero(np.any(Wd != 0.0, axis=0)))
+    assert ctx.encode_weights(Wd, "csr", 40).info().device_bytes == (2 + 2 * kk) * 4 + kk * ctx.L * 16 * 2 * 8
 
 
 @pytest.mark.parametrize("sparsity", [0.5, 0.9])

@@ -103,12 +103,60 @@ def test_serving_rejects_oversized_requests(torch_cuda):
     assert need > _bytes(ctx, 20, 3)                         # scratch and tables are counted too
     srv = sfhe.Server(ctx, need)
     with pytest.raises(sfhe.SfheError) as e:
+        srv.set_slots(-1)
+    assert e.value.code == -1
+    with pytest.raises(sfhe.SfheError) as e:
         srv.submit(reqs[2][2], reqs[2][3])                   # 33 x 5 outputs
     assert e.value.code == -7
     t = srv.submit(reqs[0][2], reqs[0][3])                   # exactly the budget
     assert srv.step() == 1
     assert srv.poll(t, wait=True)[0]
     srv.close()
+
+
+def test_serving_policies_fifo_and_slot_limit(torch_cuda):
+    """One stream: batches run in admission order (their device-time
+    intervals do not intersect and follow the tickets).  Two streams with one
+    slot each: never more than two batches running, requests that find both
+    streams busy wait and join a later batch.  Every result equals the
+    request alone."""
+    from paper_2503_09184_amd import sfhe
+    ctx, _ = pair(HYB_SMALL, 21)
+    reqs = _requests(ctx)
+    alone = []
+    for n, (Wt, X, Wp, EX) in enumerate(reqs):
+        srv = sfhe.Server(ctx, 1 << 40)
+        t = srv.submit(Wp, EX)
+        srv.step()
+        alone.append(_cts(ctx, srv.poll(t, wait=True)[1], REQS[n][0], REQS[n][2]))
+        srv.close()
+    for n_streams, slots in ((1, 0), (2, 1)):
+        note("serving policy %d streams, %d slots" % (n_streams, slots))
+        srv = sfhe.Server(ctx, 1 << 40, n_streams=n_streams, slots=slots)
+        tickets = []
+        for Wt, X, Wp, EX in reqs:
+            tickets.append(srv.submit(Wp, EX))
+            srv.step()                                           # one request per step while a slot is free
+            assert srv.status()["running"] <= (n_streams * slots if slots else len(tickets))
+        results = {}
+        for _ in range(1000):
+            srv.step()
+            assert srv.status()["running"] <= (n_streams * slots if slots else len(tickets))
+            for n, t in enumerate(tickets):
+                if n not in results:
+                    done, C, _, _ = srv.poll(t)
+                    if done:
+                        results[n] = C
+            if len(results) == len(tickets):
+                break
+        assert len(results) == len(tickets)
+        if n_streams == 1:
+            iv = [srv.intervals[t] for t in tickets]
+            assert all(iv[x][1] <= iv[x + 1][0] + 1e-3 or iv[x] == iv[x + 1] for x in range(len(iv) - 1)), iv
+        for n, (M, K, b, s) in enumerate(REQS):
+            for x, y in zip(_cts(ctx, results[n], M, b), alone[n]):
+                assert np.array_equal(x, y), (n_streams, slots, n)
+        srv.close()
 
 
 # (M, K, b, weight sparsity) of the requests at the serving ring
@@ -141,7 +189,7 @@ def test_serving_ring_n32768_mix_equals_alone_and_oracle(torch_cuda):
         C.close()
         srv.close()
     budget = 3 * max(_counted(srv, r) for r in reqs)
-    srv = sfhe.Server(ctx, budget)
+    srv = sfhe.Server(ctx, budget, n_streams=2)
     tickets = [srv.submit(reqs[0][2], reqs[0][3])]
     assert srv.step() == 1
     tickets += [srv.submit(Wp, EX) for (_, _, Wp, EX) in reqs[1:]]
