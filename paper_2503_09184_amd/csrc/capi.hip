@@ -253,6 +253,10 @@ static int build_tables(sfhe_ctx* c) {
       d.Pinv[i] = invmod(P, qi);
       d.Pinv_s[i] = shoup(d.Pinv[i], qi);
       d.Pq[i] = P;
+      for (int k = 0; k < al; ++k) {
+        d.convp[k][i] = mulmod(d.conv[k][i], d.Pinv[i], qi);
+        d.convp_s[k][i] = shoup(d.convp[k][i], qi);
+      }
     }
     RescaleConst& rc = rs[lev];
     for (int i = 0; i < lev; ++i) {

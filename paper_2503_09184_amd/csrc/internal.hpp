@@ -41,6 +41,7 @@ struct ModDownConst {
   u64 pinv[kMaxDigit], pinv_s[kMaxDigit];            // (P/p_k)^-1 mod p_k
   u64 pinv_n[kMaxDigit], pinv_n_s[kMaxDigit];        // (P/p_k)^-1 N^-1 mod p_k
   u64 conv[kMaxDigit][kMaxBasis], conv_s[kMaxDigit][kMaxBasis];   // [P/p_k]_{q_i}
+  u64 convp[kMaxDigit][kMaxBasis], convp_s[kMaxDigit][kMaxBasis]; // [P/p_k]_{q_i} P^-1 mod q_i
   u64 Pinv[kMaxBasis], Pinv_s[kMaxBasis];            // P^-1 mod q_i
   u64 Pq[kMaxBasis];                                 // P mod q_i
 };

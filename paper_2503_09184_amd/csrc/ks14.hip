@@ -310,19 +310,34 @@ __global__ void __launch_bounds__(256) ks14_k2own_kernel(Ks14Args a, DevParams d
 
 // ---------------------------------------------------------------- K3a
 // z P^-1 mod q_i at one position (yb = yP rows of (b, p) at it), z = sum_k
-// yP_k [P/p_k]_{q_i} with yP_k centered: the uncentered sum times P^-1, minus
-// the count of yP_k above (p_k - 1) / 2
+// yP_k [P/p_k]_{q_i} with yP_k centered: the uncentered sum with P^-1 folded
+// into the constants, minus the count of yP_k above (p_k - 1) / 2 (each such
+// term stands for yP_k - p_k, and p_k [P/p_k] P^-1 = 1)
 template <int ALPHA>
-__device__ __forceinline__ u64 moddown_zp(const u64* yb, const ModDownConst* md, int i, u64 q, u64 Pi, u64 Pis,
-                                          const DevParams& dp) {
+__device__ __forceinline__ u64 moddown_zp(const u64* yb, const ModDownConst* md, int i, u64 q, const DevParams& dp) {
   u64 z = 0, neg = 0;
 #pragma unroll
   for (int k = 0; k < ALPHA; ++k) {
     const u64 y = yb[(int64_t)k * kN];
-    z = add_mod(z, mul_shoup(y, md->conv[k][i], md->conv_s[k][i], q), q);
+    z = add_mod(z, mul_shoup(y, md->convp[k][i], md->convp_s[k][i], q), q);
     neg += y > (dp.pr[dp.L + k].q - 1) / 2;
   }
-  return sub_mod(mul_shoup(z, Pi, Pis, q), neg, q);
+  return sub_mod(z, neg, q);
+}
+
+// K3a's epilogue for register U and the ones after it, unrolled at compile
+// time (a loop of this length is not always unrolled, and a run-time index
+// would put v in scratch)
+template <int U, int ALPHA, typename Ar>
+__device__ __forceinline__ void k3a_out(const Ar& ar, const typename Ar::Val (&v)[32], const u64* yb, u64* o,
+                                        const ModDownConst* md, int lev, const PrimeDev& P, const DevParams& dp, int tt) {
+  if constexpr (U < 32) {
+    const int x = pos_a(tt, U);
+    const u64 z = moddown_zp<ALPHA>(yb + x, md, lev, P.q, dp);
+    o[x] = sub_mod(ar.out_inv(v[U], P), z, P.q);
+    group_fence<4>(U);
+    k3a_out<U + 1, ALPHA>(ar, v, yb, o, md, lev, P, dp, tt);
+  }
 }
 
 // instantiated per alpha: a run-time trip count inside the unrolled
@@ -348,13 +363,7 @@ __device__ __forceinline__ void k3a_body(const Ks14Args& a, const DevParams& dp,
   const int tt = after(t, v[15], v[31]);
   u64* o = a.r + ((int64_t)b * 2 + p) * kN;
   const u64* yb = a.yP + ((int64_t)b * 2 + p) * ALPHA * kN;
-#pragma unroll
-  for (int u = 0; u < 32; ++u) {
-    const int x = pos_a(tt, u);
-    const u64 z = moddown_zp<ALPHA>(yb + x, a.md, lev, q, Pi, Pis, dp);
-    o[x] = sub_mod(ar.out_inv(v[u], P), z, q);
-    group_fence<4>(u);
-  }
+  k3a_out<0, ALPHA>(ar, v, yb, o, a.md, lev, P, dp, tt);
 }
 
 template <int ALPHA>
@@ -376,8 +385,8 @@ __global__ void __launch_bounds__(n14::kThreads, 4) ks14_k3a_kernel(Ks14Args a, 
 template <int ALPHA>
 struct LiftConsts {
   const u64 *yb, *rb;            // yP rows and r row of (b, p)
-  u64 q, ql, Pi, Pis, mu_hi, mu_lo;
-  u64 cv[ALPHA], cs[ALPHA], ph[ALPHA];
+  u64 q, ql, mu_hi, mu_lo;
+  u64 cv[ALPHA], cs[ALPHA], ph[ALPHA];   // [P/p_k]_{q_i} P^-1 with companions; (p_k - 1) / 2
 };
 
 template <int ALPHA, bool RS>
@@ -390,7 +399,7 @@ __device__ __forceinline__ u64 lift_one(const LiftConsts<ALPHA>& lc, int x) {
     z = add_mod(z, mul_shoup(y, lc.cv[k], lc.cs[k], q), q);
     above += y > lc.ph[k];
   }
-  u64 w = sub_mod(mul_shoup(z, lc.Pi, lc.Pis, q), above, q);
+  u64 w = sub_mod(z, above, q);
   if (RS) {   // centered lift of the last prime, reduced mod q_i
     const u64 c = lc.rb[x];
     const bool neg = c > (lc.ql - 1) / 2;
@@ -422,14 +431,12 @@ __device__ __forceinline__ void load_lift(const Ar& ar, typename Ar::Val (&v)[32
   lc.rb = a.r + (int64_t)bp * kN;
   lc.q = P.q;
   lc.ql = dp.pr[a.lev].q;
-  lc.Pi = a.md->Pinv[i];
-  lc.Pis = a.md->Pinv_s[i];
   lc.mu_hi = P.mu_hi;
   lc.mu_lo = P.mu_lo;
 #pragma unroll
   for (int k = 0; k < ALPHA; ++k) {
-    lc.cv[k] = a.md->conv[k][i];
-    lc.cs[k] = a.md->conv_s[k][i];
+    lc.cv[k] = a.md->convp[k][i];
+    lc.cs[k] = a.md->convp_s[k][i];
     lc.ph[k] = (dp.pr[dp.L + k].q - 1) / 2;
   }
   lift_steps<0, ALPHA, RS>(ar, v, lc, t);
