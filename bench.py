@@ -632,7 +632,7 @@ def main():
         r = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK / 1e12, "unit": "T VALU-op/s",
              "frac": achieved / (VALU_PEAK / 1e12), "ms": ks_ms, "keyswitches": int(keyswitches),
              "butterflies": float(keyswitches) * KS_BUTTERFLIES_PER_TRANSFORM * (KS_INT_TRANSFORMS + KS_FP_TRANSFORMS),
-             "kernels": "ks14_k1/bconv/k2/k3a/lift/k3b (fused key switch and rescale, N = 2^14)"}
+             "kernels": "ks14_k1/bconv/k2/k3a/k3b (fused key switch and rescale, the lift taken by k3b; N = 2^14)"}
         if peaks:
             # the integer butterflies are bound by the 32-bit/64-bit integer
             # products, the fp64 ones by fp64 issue: the measured peak is the

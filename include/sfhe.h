@@ -106,10 +106,14 @@ typedef struct {
  * stream (or to other streams once that stream has passed the point of the
  * free).  Temporaries of a call are taken and given back on the call's
  * stream; a matrix's ciphertexts on the stream of the call that made it,
- * given back by sfhe_mat_destroy.  A matrix read by work on another stream
- * must not be destroyed before that work has ended.  Without hooks the
- * library takes its blocks from a stream-ordered memory pool of its own
- * (hipMallocFromPoolAsync / hipFreeAsync on the same streams). */
+ * given back by sfhe_mat_destroy, so that stream must still exist then (a
+ * server's results are handed over to its client stream).  A matrix read
+ * by work on another stream must not be destroyed before that work has
+ * ended.  Without hooks the library takes its blocks from a stream-ordered
+ * memory pool of its own (hipMallocFromPoolAsync / hipFreeAsync on the same
+ * streams); a block whose free has completed may go to any stream, and when
+ * the pool cannot serve a request it waits for the device, gives its free
+ * blocks back and tries once more. */
 typedef struct {
   void* (*alloc)(size_t bytes, void* stream, void* user);
   void (*free)(void* ptr, size_t bytes, void* stream, void* user);
@@ -370,7 +374,9 @@ void sfhe_plain_graph_destroy(sfhe_plain_graph* graph);
  * requests' encryptions) before the step.  A request's result is the same,
  * bit for bit, alone or in any batch.  The caller keeps W and X alive until
  * its request is done; a finished result belongs to the caller from
- * sfhe_server_poll on (its memory was taken on the batch's stream).  Calls
+ * sfhe_server_poll on (its memory was taken on the batch's stream and is
+ * given back, when the caller frees it, in the client stream's order, so it
+ * may outlive the server).  Calls
  * on one server must not overlap. */
 typedef struct sfhe_server sfhe_server;
 int sfhe_server_create(sfhe_ctx* ctx, uint64_t budget_bytes, int32_t n_streams, void* stream, sfhe_server** out);

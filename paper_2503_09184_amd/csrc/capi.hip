@@ -24,11 +24,18 @@ void* Alloc::get(size_t bytes) {
   if (bytes == 0) return nullptr;
   if (has_hooks) return hooks.alloc(bytes, (void*)cur, hooks.user);
   void* p = nullptr;
-  if (hipMallocFromPoolAsync(&p, bytes, pool, cur) != hipSuccess) {
-    (void)hipGetLastError();
-    return nullptr;
-  }
-  return p;
+  if (hipMallocFromPoolAsync(&p, bytes, pool, cur) == hipSuccess) return p;
+  (void)hipGetLastError();
+  // the pool keeps freed blocks, which may be too small or pieces of the
+  // device's memory that a large request needs whole: once the device has
+  // drained (every pending free completed), give them all back and try once
+  // more
+  p = nullptr;
+  if (hipDeviceSynchronize() == hipSuccess && hipMemPoolTrimTo(pool, 0) == hipSuccess &&
+      hipMallocFromPoolAsync(&p, bytes, pool, cur) == hipSuccess)
+    return p;
+  (void)hipGetLastError();
+  return nullptr;
 }
 void Alloc::put(void* p, size_t bytes, hipStream_t s) {
   if (!p) return;
@@ -571,6 +578,15 @@ int sfhe_ctx_create(const sfhe_params* p, const sfhe_device_hooks* hooks, sfhe_c
     if (e == hipSuccess) {
       uint64_t keep = UINT64_MAX;
       e = hipMemPoolSetAttribute(c->alloc.pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    // a block whose free has completed may be taken by any stream (streams
+    // come and go: a server's, a caller's side streams); blocks freed by work
+    // still in flight are reused only in that work's order
+    const hipMemPoolAttr reuse[3] = {hipMemPoolReuseFollowEventDependencies, hipMemPoolReuseAllowOpportunistic,
+                                     hipMemPoolReuseAllowInternalDependencies};
+    for (int x = 0; x < 3 && e == hipSuccess; ++x) {
+      int on = 1;
+      e = hipMemPoolSetAttribute(c->alloc.pool, reuse[x], &on);
     }
     if (e != hipSuccess) {
       set_error(std::string("device memory pool: ") + hipGetErrorString(e));
@@ -2086,7 +2102,11 @@ int sfhe_server_poll(sfhe_server* v, int64_t ticket, int32_t wait, int32_t* is_d
   }
   if (it == v->done.end()) return SFHE_OK;
   *is_done = 1;
+  // the result is the caller's from here on: its memory goes back, when the
+  // caller frees it, in the client stream's order (the batch has ended, and
+  // the server's stream may be gone by then)
   *C = it->second.C;
+  (*C)->data.st = v->client;
   if (batch_ms) *batch_ms = it->second.ms;
   if (batch_size) *batch_size = it->second.batch_size;
   if (start_ms) *start_ms = it->second.t0;

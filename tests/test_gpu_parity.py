@@ -252,6 +252,22 @@ def test_matmul_mixed_prime_sizes_all_outputs(torch_cuda, sched):
     _all_outputs_equal(ctx, C, cts, 6, 5, sched)
 
 
+@pytest.mark.parametrize("q_bits", [[40, 60, 60], [60, 40, 40]])
+def test_fused_rescale_target_arithmetic_n14(torch_cuda, q_bits):
+    """N = 2^14 (the fused key switch and rescale) with the lift's two cases
+    for a 40-bit target prime: the centered last prime already below the
+    target ([60, 40, 40]) and above it, reduced first ([40, 60, 60]: a 60-bit
+    last prime); both schedules, every output bit-exact against the oracle."""
+    P = dict(log_n=14, q_bits=q_bits, p_bits=[60, 60], dnum=2)
+    ctx, orc = pair(P, 19)
+    A, B = W.operands(3, 5, 2, 0.4, 43)
+    for sched in ("lazy", "per_product"):
+        note("fused rescale targets %s %s" % (q_bits, sched))
+        C = ctx.matmul(ctx.encrypt(A, "csr", 9, 0), ctx.encrypt(B, "dense", 10, 1), sched)
+        cts, _, _ = orc.matmul(A, B, "csr", sched, 9, 10, threads=8)
+        _all_outputs_equal(ctx, C, cts, 3, 2, sched)
+
+
 @pytest.mark.parametrize("q_bits", [[61, 59, 40], [60, 60, 40]])
 def test_long_rows_fold_the_sums(torch_cuda, q_bits):
     """K = 600 dense: every lazy sum crosses the fold points of the tensor

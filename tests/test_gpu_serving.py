@@ -159,6 +159,32 @@ def test_serving_policies_fifo_and_slot_limit(torch_cuda):
         srv.close()
 
 
+@pytest.mark.parametrize("torch_allocator", [True, False])
+def test_results_outlive_the_server(torch_cuda, torch_allocator):
+    """A result polled from a server stays valid after the server (and its
+    streams) is destroyed, and is freed afterwards, with torch's allocator
+    and with the library's own stream-ordered pool; servers created one after
+    another reuse the memory of the results freed in between."""
+    from paper_2503_09184_amd import sfhe
+    ctx = sfhe.Context(**HYB_SMALL, torch_allocator=torch_allocator)
+    ctx.keygen(21)
+    reqs = _requests(ctx)
+    keep = []
+    for rep in range(3):
+        note("result outlives server %s %d" % (torch_allocator, rep))
+        srv = sfhe.Server(ctx, 1 << 40, n_streams=2)
+        t = srv.submit(reqs[0][2], reqs[0][3])
+        assert srv.step() == 1
+        done, C, _, _ = srv.poll(t, wait=True)
+        assert done
+        srv.close()
+        keep.append((C, _cts(ctx, C, REQS[0][0], REQS[0][2])))
+    for C, cts in keep:
+        assert all(np.array_equal(x, y) for x, y in zip(_cts(ctx, C, REQS[0][0], REQS[0][2]), keep[0][1]))
+        C.close()
+    torch_cuda.cuda.synchronize()
+
+
 # (M, K, b, weight sparsity) of the requests at the serving ring
 REQS15 = [(48, 14, 8, 0.5), (5, 7, 1, 0.75), (12, 14, 3, 0.9), (3, 14, 2, 0.0), (20, 7, 4, 0.5)]
 
