@@ -933,6 +933,7 @@ struct LazyPrep {
   DevBuf<int> d_ts, d_ek, d_em, d_es, f_ts, f_ek, f_em, f_es, q_ts, q_ek, q_em, q_es, d_bs;
   DevBuf<u64> D, kss;
   int kss_streams = 0;   // key-switch streams the scratch kss is sized for
+  int64_t kss_slice = 0; // and its slice size
   DevBuf<int64_t> d_empty;
   int64_t n_empty = 0, products = 0, keyswitches = 0, max_out = 0, ks_slice = 2048, dw = 0;
   int lev = 0, Nc = 0;
@@ -1108,11 +1109,12 @@ static int lazy_launch(sfhe_ctx* c, LazyPrep& P, hipStream_t s, bool events, boo
     // the key-switch (and rescale) scratch of one slice per key-switch
     // stream, allocated once (under graph capture: one stream)
     const int nstr = P.fused && events ? c->ks_streams : 1;
-    if (P.kss.ptr && nstr > P.kss_streams) P.kss.release();
     const int64_t sl = std::min(P.ks_slice, P.max_out);
+    if (P.kss.ptr && (nstr > P.kss_streams || sl > P.kss_slice)) P.kss.release();
     const int64_t ks_words = P.fused ? keyswitch_rescale_n14_scratch_words(c, lev, sl) : keyswitch_scratch_words(c, lev, sl);
     if (!rc && !P.kss.ptr) {
       P.kss_streams = nstr;
+      P.kss_slice = sl;
       StreamScope scope_(c->alloc, s);
       // rescale_batch's scratch: the last prime's rows and the lifted rows
       const int64_t rs_words = P.fused ? 0 : sl * 2 * N * (1 + lev);

@@ -306,6 +306,46 @@ def test_one_by_one(torch_cuda):
         assert np.array_equal(ctx.export_ct(C, 0, 0), cts[0])
 
 
+def test_key_switch_slices_and_streams_give_identical_products(torch_cuda):
+    """N = 2^14, 40 x 24 x 26 (1040 outputs: the first LAZY product of a
+    fresh context tunes the key-switch slices): the tuned setting and fixed
+    slices of 128, 256 and 2048 outputs on one stream and on two give the
+    same ciphertexts; the tuner's report is consistent; bad settings are
+    refused."""
+    from paper_2503_09184_amd import sfhe
+    P = W.PARAMS["realistic_n16384"]
+    ctx = sfhe.Context(**P)
+    ctx.keygen(W.key_seed(3))
+    A, B = W.operands(40, 24, 26, 0.5, 7300)
+    EA, EB = ctx.encrypt(A, "csr", 7301, 0), ctx.encrypt(B, "dense", 7302, 1)
+    sl, st, us1, us2 = ctx.ks_tuning()
+    assert sl == 0                                           # not tuned yet
+    note("ks tuned product")
+    C = ctx.matmul(EA, EB, "lazy")
+    ref = [ctx.export_ct(C, i, j) for i in range(40) for j in range(26)]
+    C.close()
+    sl, st, us1, us2 = ctx.ks_tuning()
+    assert st in (1, 2) and sl >= 64
+    assert all(v > 0 for k, v in us1.items() if k <= 1040) and all(v < 0 for k, v in us1.items() if k > 1040)
+    assert (sl, st) in [(k, 1) for k, v in us1.items() if v > 0] + [(k, 2) for k, v in us2.items() if v > 0]
+    for setting in ((128, 1), (256, 2), (2048, 1), (2048, 2), (-1, 1)):
+        note("ks setting %s" % (setting,))
+        ctx.set_ks_slice(*setting)
+        C = ctx.matmul(EA, EB, "lazy")
+        got = [ctx.export_ct(C, i, j) for i in range(40) for j in range(26)]
+        C.close()
+        assert all(np.array_equal(x, y) for x, y in zip(got, ref)), setting
+    assert ctx.ks_tuning()[:2] == (sl, st)                  # -1: back to the tuned setting
+    for bad in ((100, 1), (8192, 1), (32, 1), (256, 3), (256, 0)):
+        with pytest.raises(sfhe.SfheError) as e:
+            ctx.set_ks_slice(*bad)
+        assert e.value.code == -1
+    assert np.max(np.abs(ctx.decrypt(ctx.matmul(EA, EB, "lazy")) - A @ B)) < 1e-6
+    for m in (EA, EB):
+        m.close()
+    ctx.close()
+
+
 def test_errors_are_reported(torch_cuda):
     from paper_2503_09184_amd import sfhe
     ctx, _ = pair(SINGLE_SMALL, 3)
