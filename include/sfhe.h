@@ -195,7 +195,11 @@ int sfhe_encrypt_matrix(sfhe_ctx* ctx, const double* vals, int32_t rows, int32_t
  * Sec. 3.3.2); a DENSE B multiplies every k of A's row.  The result is a DENSE
  * matrix one level lower with scale^2 / q_level.  Outputs with no product
  * are trivial zero ciphertexts.  The device time is reported by
- * sfhe_last_stats. */
+ * sfhe_last_stats.  All work is ordered on `stream`: at N = 2^14 the LAZY
+ * key switch may run its slices on two side streams of the context, forked
+ * from `stream` after the tensor step and joined back into it before the
+ * call's last launch (sfhe_ks_tuning); so calls of one context on several
+ * streams do not overlap their key switches. */
 int sfhe_matmul(sfhe_ctx* ctx, const sfhe_mat* A, const sfhe_mat* B, sfhe_schedule sched,
                 void* stream, sfhe_mat** C);
 

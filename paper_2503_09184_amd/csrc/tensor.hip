@@ -87,7 +87,7 @@ struct ArithFp {   // q < 2^42: fp64 residues, Karatsuba middle term
   }
   static constexpr int kFold = 1024;   // each product adds < 1.5 q to a sum: stay below 2^53
   static constexpr int kGroup = 4;     // rows whose operands are read from LDS together
-  __device__ void fold(Acc& a) const {
+  __device__ void fold(Acc& a, int = 0) const {
     a.d0 = fp_fold(a.d0, q, qinv);
     a.d2 = fp_fold(a.d2, q, qinv);
     a.ss = fp_fold(a.ss, q, qinv);
@@ -131,7 +131,7 @@ struct ArithInt {   // q < 2^61: 128-bit integer sums, Karatsuba middle term
   }
   static constexpr int kFold = 16;     // 16 terms below 2^124 (plus a residue) stay below 2^128
   static constexpr int kGroup = 4;
-  __device__ void fold(Acc& a) const {
+  __device__ void fold(Acc& a, int = 0) const {
     a.d0 = U128{reduce_wide(a.d0, q, mu_hi, mu_lo), 0};
     a.d2 = U128{reduce_wide(a.d2, q, mu_hi, mu_lo), 0};
     a.ss = U128{reduce_wide(a.ss, q, mu_hi, mu_lo), 0};
@@ -153,8 +153,10 @@ struct ArithInt {   // q < 2^61: 128-bit integer sums, Karatsuba middle term
 // back: carries move up (L into M, M into H), and since 2^60 = c (mod q),
 // H 2^60 = (H mod 2^32) c + t 2^32 with t = (H >> 32) c < 2^52, of which
 // (H mod 2^32) c goes into L, (t mod 2^28) 4 into M and t >> 28 stays in H.
-// Afterwards L < 2^53, M < 2^31, H < 2^24, and kFold more entries add at most
-// 16 partials below 2^60 - 2^31 to a sum: every sum stays below 2^64.
+// Afterwards L < 2^53, M < 2^31, H < 2^24.  An entry adds at most 4 partials
+// below 2^60 - 2^31 to a sum of d1 (two products) and at most 2 to one of d0
+// or d2, so d1 is folded every kFold = 4 entries and d0, d2 every 8: no sum
+// takes more than 16 partials between folds, and every sum stays below 2^64.
 __device__ __forceinline__ u32 lo32(u64 x) { return (u32)x; }
 __device__ __forceinline__ u32 hi32(u64 x) { return (u32)(x >> 32); }
 __device__ __forceinline__ u64 madw(u32 a, u32 b, u64 acc) { return (u64)a * b + acc; }
@@ -187,7 +189,7 @@ struct ArithInt60 {
     mac1(a.d1, a1, b0);
     mac1(a.d2, a1, b1);
   }
-  static constexpr int kFold = 4;   // entries between folds (each adds at most 4 partials to a sum)
+  static constexpr int kFold = 4;   // entries between folds of d1 (twice that for d0 and d2)
   static constexpr int kGroup = 2;
   __device__ void fold1(Sums& s) const {
     s.M += s.L >> 30;
@@ -197,10 +199,13 @@ struct ArithInt60 {
     s.M = (s.M & 0x3fffffffull) + ((t & 0xfffffffull) << 2);
     s.H = t >> 28;
   }
-  __device__ void fold(Acc& a) const {
-    fold1(a.d0);
+  // the n-th fold since the start: d1 every time, d0 and d2 every other time
+  __device__ void fold(Acc& a, int n = 0) const {
     fold1(a.d1);
-    fold1(a.d2);
+    if ((n & 1) == 0) {
+      fold1(a.d0);
+      fold1(a.d2);
+    }
   }
   // L + M 2^30 + H 2^60 (after a fold) as 128 bits, reduced
   __device__ u64 residue(const Sums& s) const {
@@ -579,7 +584,7 @@ __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const 
     compute1(pb.b00, pb.b01, pb.m0, bf, 0);
     compute1(pb.b10, pb.b11, pb.m1, bf, 1);
   };
-  int cnt = 0;
+  int cnt = 0, nfold = 0;
   for (int sg = e0; sg < e1; sg += kSegEntries) {
     const int n = min(kSegEntries, e1 - sg);
     __syncthreads();   // the previous segment's entries are no longer read
@@ -611,8 +616,9 @@ __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const 
       cnt += 4;
       if (cnt >= Arith::kFold) {
         cnt = 0;
+        ++nfold;
 #pragma unroll
-        for (int r = 0; r < TR; ++r) ar.fold(acc[r]);
+        for (int r = 0; r < TR; ++r) ar.fold(acc[r], nfold);
       }
     }
   }
