@@ -448,9 +448,6 @@ def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
     policies = {}
     for name, n_streams, slots in SERVING_POLICIES:
         policies[name] = serve(n_streams, slots)
-        # blocks cached for the closed server's streams go back before the next policy
-        torch.cuda.synchronize()
-        torch.cuda.empty_cache()
         log("serving %s: p50 %.1f ms, p99 %.1f ms, %d batches, %d overlapping, host step %.0f ms" %
             (name, policies[name]["latency_ms_p50"], policies[name]["latency_ms_p99"], policies[name]["batches"],
              policies[name]["batches_overlapping_another"], policies[name]["host_step_ms_sum"]))
