@@ -107,7 +107,8 @@ typedef struct {
  * free).  Temporaries of a call are taken and given back on the call's
  * stream; a matrix's ciphertexts on the stream of the call that made it,
  * given back by sfhe_mat_destroy, so that stream must still exist then (a
- * server's results are handed over to its client stream).  A matrix read
+ * server takes every block of a batch on its client stream, and gives the
+ * ones that are not results back there once the batch has ended).  A matrix read
  * by work on another stream must not be destroyed before that work has
  * ended.  Without hooks the library takes its blocks from a stream-ordered
  * memory pool of its own (hipMallocFromPoolAsync / hipFreeAsync on the same
@@ -378,10 +379,13 @@ void sfhe_plain_graph_destroy(sfhe_plain_graph* graph);
  * requests' encryptions) before the step.  A request's result is the same,
  * bit for bit, alone or in any batch.  The caller keeps W and X alive until
  * its request is done; a finished result belongs to the caller from
- * sfhe_server_poll on (its memory was taken on the batch's stream and is
- * given back, when the caller frees it, in the client stream's order, so it
- * may outlive the server).  Calls
- * on one server must not overlap. */
+ * sfhe_server_poll on.  Every block of a batch (results, sums, scratch,
+ * descriptors) is taken in the client stream's order before the batch's
+ * stream waits for that stream, so all server streams draw on one stream's
+ * blocks; the blocks that are not results go back, in the same order, when
+ * a step or poll finds the batch ended, and a result goes back there when
+ * the caller frees it (so it may outlive the server).  Calls on one server
+ * must not overlap. */
 typedef struct sfhe_server sfhe_server;
 int sfhe_server_create(sfhe_ctx* ctx, uint64_t budget_bytes, int32_t n_streams, void* stream, sfhe_server** out);
 /* at most per_stream running batches per server stream (0, the default: no

@@ -1922,6 +1922,7 @@ struct sfhe_server {
   struct Run {
     std::vector<int64_t> tickets;
     std::vector<sfhe_mat*> C;
+    std::unique_ptr<PlainPrep> prep;      // the batch's sums, scratch and tables, freed at retirement
     hipEvent_t start = nullptr, end = nullptr;
     uint64_t bytes = 0;
     int64_t products = 0;
@@ -1955,6 +1956,7 @@ struct sfhe_server {
       in_flight -= r.bytes;
       products += r.products;
       --busy[r.stream];
+      r.prep.reset();   // the batch has ended: its blocks go back in the client stream's order
       (void)hipEventDestroy(r.start);
       (void)hipEventDestroy(r.end);
       it = running.erase(it);
@@ -2041,7 +2043,6 @@ int sfhe_server_step(sfhe_server* v, int32_t* admitted) {
     v->queue.pop_front();
   }
   if (Ws.empty()) return SFHE_OK;
-  // the batch's launches wait for the client stream's work
   run.stream = sx;
   hipStream_t bs = v->streams[sx];
   run.C.assign(Ws.size(), nullptr);
@@ -2051,20 +2052,35 @@ int sfhe_server_step(sfhe_server* v, int32_t* admitted) {
     set_error("event creation failed");
     rc = SFHE_E_DEVICE;
   }
-  if (!rc && (hipEventRecord(ready, v->client) != hipSuccess || hipStreamWaitEvent(bs, ready, 0) != hipSuccess)) {
+  // Every block of the batch is taken in the client stream's order, and the
+  // batch's own stream waits for the client stream after that, so blocks that
+  // the client's earlier work used are safe to reuse.  The results pass to the
+  // caller; the other blocks are given back at retirement, when the batch has
+  // ended.  With several server streams all of them thus draw on one stream's
+  // cached blocks.
+  run.prep.reset(new PlainPrep());
+  if (!rc) {
+    StreamScope scope_(v->c->alloc, v->client);
+    rc = plain_prepare(v->c, (int32_t)Ws.size(), Ws.data(), Xs.data(), SFHE_PLAIN_FUSED, v->client, *run.prep);
+  }
+  if (!rc && (hipEventRecord(ready, v->client) != hipSuccess || hipStreamWaitEvent(bs, ready, 0) != hipSuccess ||
+              hipEventRecord(run.start, bs) != hipSuccess)) {
     set_error("stream ordering failed");
     rc = SFHE_E_DEVICE;
   }
-  int64_t launches = 0, outs = 0;
-  {
+  if (!rc) {
     StreamScope scope_(v->c->alloc, bs);
-    if (!rc)
-      rc = plain_enqueue(v->c, (int32_t)Ws.size(), Ws.data(), Xs.data(), SFHE_PLAIN_FUSED, bs, run.C.data(), run.start,
-                         &run.products, &launches, &outs);
+    rc = plain_launch(v->c, *run.prep, bs);
   }
   if (!rc && hipEventRecord(run.end, bs) != hipSuccess) { set_error("event record failed"); rc = SFHE_E_DEVICE; }
   if (ready) (void)hipEventDestroy(ready);
+  if (!rc) {
+    run.products = run.prep->products;
+    run.prep->release(run.C.data());
+  }
   if (rc) {
+    (void)hipStreamSynchronize(bs);
+    run.prep.reset();
     // the requests stay queued, in order, for a later step
     for (size_t x = Ws.size(); x-- > 0;) v->queue.push_front(sfhe_server::Req{run.tickets[x], Ws[x], Xs[x], plain_bytes(v->c, Ws[x], Xs[x])});
     for (auto* m : run.C) delete m;
@@ -2104,11 +2120,10 @@ int sfhe_server_poll(sfhe_server* v, int64_t ticket, int32_t wait, int32_t* is_d
   }
   if (it == v->done.end()) return SFHE_OK;
   *is_done = 1;
-  // the result is the caller's from here on: its memory goes back, when the
-  // caller frees it, in the client stream's order (the batch has ended, and
-  // the server's stream may be gone by then)
+  // the result is the caller's from here on: its memory was taken, and goes
+  // back when the caller frees it, in the client stream's order (the batch
+  // has ended; the server's streams may be gone by then)
   *C = it->second.C;
-  (*C)->data.st = v->client;
   if (batch_ms) *batch_ms = it->second.ms;
   if (batch_size) *batch_size = it->second.batch_size;
   if (start_ms) *start_ms = it->second.t0;
