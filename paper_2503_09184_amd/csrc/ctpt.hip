@@ -79,7 +79,8 @@ struct PlainInt {
 // two words of B[k][j] for its lane's coefficient (512 contiguous bytes per
 // wave and poly) once and multiplies them into the accumulators of the tile
 // rows in the mask; the 16 weights of the entry and prime are scalars, read
-// from the weight table, so a row test is a scalar branch.  B for the next
+// from the weight table in whole 32-byte loads, so a row test is a scalar
+// branch.  B for the next
 // entry is loaded before the current entry's products (the last entry's
 // next load repeats it, so every iteration issues the same loads).
 template <typename Ar>
@@ -116,13 +117,29 @@ __global__ void __launch_bounds__(64 * kPlainCols) ctpt_block_kernel(PlainBatch 
       k = J.ek[en];
       nb0 = Bl[((int64_t)k * J.Nc + j) * 64];
       nb1 = Bl[((int64_t)k * J.Nc + j) * 64 + pstride];
-      const u64* wv = J.ew + ((int64_t)e * pb.nl + l) * kPlainTileRows;
-      const u64* wsv = J.ews + ((int64_t)e * pb.nl + l) * kPlainTileRows;
+      // the entry's 16 weights (and companions) in whole 32-byte scalar
+      // loads, waited for once: read one by one inside the row branches, each
+      // visited row waited for its own scalar load
+      const ulonglong4* wv = reinterpret_cast<const ulonglong4*>(J.ew + ((int64_t)e * pb.nl + l) * kPlainTileRows);
+      const ulonglong4* wsv = reinterpret_cast<const ulonglong4*>(J.ews + ((int64_t)e * pb.nl + l) * kPlainTileRows);
+      u64 wr[kPlainTileRows], wsr[kPlainTileRows];
+#pragma unroll
+      for (int g4 = 0; g4 < kPlainTileRows / 4; ++g4) {
+        const ulonglong4 a4 = wv[g4], s4 = wsv[g4];
+        wr[4 * g4] = a4.x;
+        wr[4 * g4 + 1] = a4.y;
+        wr[4 * g4 + 2] = a4.z;
+        wr[4 * g4 + 3] = a4.w;
+        wsr[4 * g4] = s4.x;
+        wsr[4 * g4 + 1] = s4.y;
+        wsr[4 * g4 + 2] = s4.z;
+        wsr[4 * g4 + 3] = s4.w;
+      }
 #pragma unroll
       for (int r = 0; r < kPlainTileRows; ++r) {
         if ((mask >> r) & 1) {
-          ar.mac(acc0[r], b0, wv[r], wsv[r]);
-          ar.mac(acc1[r], b1, wv[r], wsv[r]);
+          ar.mac(acc0[r], b0, wr[r], wsr[r]);
+          ar.mac(acc1[r], b1, wr[r], wsr[r]);
         }
       }
       if (++cnt >= Ar::kFold) {
