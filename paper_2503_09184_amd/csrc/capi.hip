@@ -922,15 +922,15 @@ static int tune_ks_slice(sfhe_ctx* c, int lev, const u64* D, int64_t dw, OutLayo
 // Everything the LAZY product's launches read or write, prepared before
 // them, so that the launches alone can also be captured into a graph: the
 // result, the tile lists of every batch (one per tile height: kTileRows for
-// the 128-bit integer kernel, kTileRowsFp for the fp64 column kernel,
-// kTileRowsInt60 for the carry-save column kernel), the lazy sums D, the
-// key-switch scratch, the B slot table and the outputs with no product.
+// the 128-bit integer kernel, kColTileRows for the fp64 and carry-save column
+// kernels), the lazy sums D, the key-switch scratch, the B slot table and the
+// outputs with no product.
 struct LazyPrep {
-  struct Batch { int r0, nr, t0, nt, f0, fnt, q0, qnt; };
+  struct Batch { int r0, nr, t0, nt, q0, qnt; };
   sfhe_mat* out = nullptr;
   const sfhe_mat *A = nullptr, *B = nullptr;
   std::vector<Batch> batches;
-  DevBuf<int> d_ts, d_ek, d_em, d_es, f_ts, f_ek, f_em, f_es, q_ts, q_ek, q_em, q_es, d_bs;
+  DevBuf<int> d_ts, d_ek, d_em, d_es, q_ts, q_ek, q_em, q_es, d_bs;
   DevBuf<u64> D, kss;
   int kss_streams = 0;   // key-switch streams the scratch kss is sized for
   int64_t kss_slice = 0; // and its slice size
@@ -978,10 +978,10 @@ static int lazy_prepare(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, hipSt
     int TR;
     std::vector<int> tstart, ek, emask, eslot;
   };
-  Tiles ti{kTileRows, {}, {}, {}, {}}, tf{kTileRowsFp, {}, {}, {}, {}}, tq{kTileRowsInt60, {}, {}, {}, {}};
+  Tiles ti{kTileRows, {}, {}, {}, {}}, tq{kColTileRows, {}, {}, {}, {}};
   std::vector<std::pair<int, int64_t>> pairs;
   std::vector<int> kmask(A->cols);
-  std::vector<int> kslot((size_t)A->cols * std::max(kTileRows, std::max(kTileRowsFp, kTileRowsInt60)));
+  std::vector<int> kslot((size_t)A->cols * std::max(kTileRows, kColTileRows));
   // tiles of rows r0 .. r0 + nr - 1 into T; returns the tile count
   auto add_tiles = [&](Tiles& T, int r0, int nr) {
     const int TR = T.TR;
@@ -1010,9 +1010,8 @@ static int lazy_prepare(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, hipSt
     if (visits[i] == 0) { ++i; continue; }
     int nr = 0;
     while (i + nr < M && nr < rb && visits[i + nr] > 0) ++nr;
-    LazyPrep::Batch bt{i, nr, (int)ti.tstart.size(), 0, (int)tf.tstart.size(), 0, (int)tq.tstart.size(), 0};
+    LazyPrep::Batch bt{i, nr, (int)ti.tstart.size(), 0, (int)tq.tstart.size(), 0};
     bt.nt = add_tiles(ti, i, nr);
-    bt.fnt = add_tiles(tf, i, nr);
     bt.qnt = add_tiles(tq, i, nr);
     P.batches.push_back(bt);
     for (int r = 0; r < nr; ++r) P.products += visits[i + r] * (int64_t)Nc;
@@ -1020,7 +1019,6 @@ static int lazy_prepare(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, hipSt
     i += nr;
   }
   ti.tstart.push_back((int)ti.ek.size());
-  tf.tstart.push_back((int)tf.ek.size());
   tq.tstart.push_back((int)tq.ek.size());
   if (P.bsp) {   // products: the visited k whose B_kj is stored
     P.products = 0;
@@ -1033,8 +1031,7 @@ static int lazy_prepare(sfhe_ctx* c, const sfhe_mat* A, const sfhe_mat* B, hipSt
   }
   for (auto& bt : P.batches) P.max_out = std::max<int64_t>(P.max_out, (int64_t)bt.nr * Nc);
   if (!upload(c, P.d_ts, ti.tstart, s) || !upload(c, P.d_ek, ti.ek, s) || !upload(c, P.d_em, ti.emask, s) ||
-      !upload(c, P.d_es, ti.eslot, s) || !upload(c, P.f_ts, tf.tstart, s) || !upload(c, P.f_ek, tf.ek, s) ||
-      !upload(c, P.f_em, tf.emask, s) || !upload(c, P.f_es, tf.eslot, s) || !upload(c, P.q_ts, tq.tstart, s) ||
+      !upload(c, P.d_es, ti.eslot, s) || !upload(c, P.q_ts, tq.tstart, s) ||
       !upload(c, P.q_ek, tq.ek, s) || !upload(c, P.q_em, tq.emask, s) || !upload(c, P.q_es, tq.eslot, s) ||
       (P.bsp && !upload(c, P.d_bs, bslot, s)) || !upload(c, P.d_empty, empty, s) ||
       !P.D.alloc(&c->alloc, (size_t)std::max<int64_t>(P.max_out, 1) * dw)) {
@@ -1069,20 +1066,13 @@ static int lazy_launch(sfhe_ctx* c, LazyPrep& P, hipStream_t s, bool events, boo
     tl.nB = P.B->n_ct;
     tl.bslot = P.bsp ? P.d_bs.ptr : nullptr;
     tl.tile_rows = kTileRows;
-    TileList tlf = tl;
-    tlf.tstart = P.f_ts.ptr + bt.f0;
-    tlf.ek = P.f_ek.ptr;
-    tlf.emask = P.f_em.ptr;
-    tlf.eslot = P.f_es.ptr;
-    tlf.n_row_tiles = bt.fnt;
-    tlf.tile_rows = kTileRowsFp;
     TileList tlq = tl;
     tlq.tstart = P.q_ts.ptr + bt.q0;
     tlq.ek = P.q_ek.ptr;
     tlq.emask = P.q_em.ptr;
     tlq.eslot = P.q_es.ptr;
     tlq.n_row_tiles = bt.qnt;
-    tlq.tile_rows = kTileRowsInt60;
+    tlq.tile_rows = kColTileRows;
     const int64_t cnt = (int64_t)bt.nr * Nc;
     if (events) {
       StepTimer tm(c, s, kCatTensor);
@@ -1091,10 +1081,10 @@ static int lazy_launch(sfhe_ctx* c, LazyPrep& P, hipStream_t s, bool events, boo
       hipEvent_t f0 = c->prof_event(), f1 = c->prof_event();
       if (f0 && f1) c->prof_cat.push_back(kCatTensorFp);
       else f0 = f1 = nullptr;
-      rc = launch_tensor_tiles(c, tl, tlf, tlq, P.A->data.ptr, P.B->data.ptr, P.D.ptr, s, f0, f1);
+      rc = launch_tensor_tiles(c, tl, tlq, P.A->data.ptr, P.B->data.ptr, P.D.ptr, s, f0, f1);
       if (f0) ++*tensor_fp_launches;
     } else {
-      rc = launch_tensor_tiles(c, tl, tlf, tlq, P.A->data.ptr, P.B->data.ptr, P.D.ptr, s);
+      rc = launch_tensor_tiles(c, tl, tlq, P.A->data.ptr, P.B->data.ptr, P.D.ptr, s);
     }
     ++*tensor_launches;
     int64_t o_start = 0;

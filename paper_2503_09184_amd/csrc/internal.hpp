@@ -272,11 +272,11 @@ int launch_tensor_gather(const sfhe_ctx* c, int lev, const u64* A, int64_t nA, c
 // (ascending), a bit mask of the tile rows that visit it and, per tile row,
 // the A ciphertext slot (or -1).
 constexpr int kTileRows = 16;
-// rows per tile of the column kernels (every wave owns all rows of one
-// column): fp64 residues (3 sums per output) and the carry-save sums of the
-// primes 2^60 - c (9 sums per output)
-constexpr int kTileRowsFp = 8;
-constexpr int kTileRowsInt60 = 4;
+// rows per tile of the column kernels (every wave owns all rows of its
+// columns): the fp64 residues (3 sums per output, two columns per wave) and
+// the carry-save sums of the primes 2^60 - c (9 sums per output, one column
+// per wave) share one tile list
+constexpr int kColTileRows = 4;
 struct TileList {
   const int* tstart;
   const int* ek;
@@ -292,12 +292,10 @@ struct TileList {
 };
 // D[pos * Nc + j][3][L][N] = sum over the visited k of tensor(A[row pos, k], B[k, j]);
 // the fp64 kernel's launch is bracketed by fp_start / fp_stop when non-null
-// tl: tiles of kTileRows rows (the 128-bit integer kernel); tl_fp: tiles of
-// kTileRowsFp rows (the fp64 column kernel); tl_i60: tiles of kTileRowsInt60
-// rows (the carry-save column kernel of the primes 2^60 - c)
-int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& tl_fp, const TileList& tl_i60,
-                        const u64* A, const u64* B, u64* D, hipStream_t s, hipEvent_t fp_start = nullptr,
-                        hipEvent_t fp_stop = nullptr);
+// tl: tiles of kTileRows rows (the 128-bit integer kernel); tl_cols: tiles of
+// kColTileRows rows (the column kernels: fp64 and carry-save)
+int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& tl_cols, const u64* A, const u64* B,
+                        u64* D, hipStream_t s, hipEvent_t fp_start = nullptr, hipEvent_t fp_stop = nullptr);
 int tensor_fp_prime_count(const sfhe_ctx* c);
 
 // ---- plaintext weights times encrypted values (ctpt.hip) ----

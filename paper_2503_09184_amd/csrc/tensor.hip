@@ -436,35 +436,39 @@ __global__ void __launch_bounds__(512, 4) tensor_block_kernel(TileList tl, const
   }
 }
 
-// Column kernel (the fp64 primes): 8 waves share one 64-coefficient chunk of
-// one prime, a tile of TR output rows and 8 columns, and wave w owns column w
-// of the block for all TR rows.  Per visited k every wave multiplies the same
-// rows (those the tile's entry mask marks), so the waves reach each barrier
-// together: none idles while another works through more rows, which is what
-// a split of the rows among waves costs at unstructured sparsity.
+// Column kernel (the fp64 primes and the primes 2^60 - c): 8 waves share one
+// 64-coefficient chunk of one prime, a tile of TR output rows and 8 CPW
+// columns, and wave w owns columns w, w + 8, ... of the block for all TR
+// rows.  Per visited k every wave multiplies the same rows (those the tile's
+// entry mask marks), so the waves reach each barrier together: none idles
+// while another works through more rows, which is what a split of the rows
+// among waves costs at unstructured sparsity.  With CPW = 2 a row's A values,
+// read once from LDS, serve two columns, and an entry's per-wave work (its
+// mask and slots, its B words and their conversion) is spread over twice the
+// products of a tile half as tall.
 //
 // Entries go in pairs.  The A values of the rows that visit the pair's two k
 // (with a0 + a1, the Karatsuba operand, formed once by the staging wave:
 // wave w stages row w) are staged through LDS, double-buffered, with one
-// barrier per pair.  B needs no exchange: wave w is the only user of column
-// w, so it loads B[k][j] straight into registers.  Global loads run one pair
-// (two entries) ahead.  The tile list has TR rows per tile (eslot
+// barrier per pair.  B needs no exchange: a wave is the only user of its
+// columns, so it loads B[k][j] straight into registers.  Global loads run one
+// pair (two entries) ahead.  The tile list has TR rows per tile (eslot
 // [entries][TR]).
-template <int TR>
+template <int TR, int CPW>
 struct ColsEntry {
   static constexpr int kAV = 2 * TR / kWavesPerBlock < 2 ? 2 : 2 * TR / kWavesPerBlock;   // A values (row, poly) a staging wave loads
   u64 a[kAV];
-  u64 b0, b1;
+  u64 b0[CPW], b1[CPW];
   int mask;
-  bool bact;
+  bool bact[CPW];
 };
 
-template <typename Arith, int TR, bool BSP>
+template <typename Arith, int TR, int CPW, bool BSP>
 __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const u64* A, const u64* B, u64* D,
                                                             FpLimbs fl, DevParams dp) {
   typedef typename Arith::Val Val;
-  constexpr int kCols = kWavesPerBlock;
-  constexpr int kAV = ColsEntry<TR>::kAV;
+  constexpr int kCols = kWavesPerBlock * CPW;
+  constexpr int kAV = ColsEntry<TR, CPW>::kAV;
   constexpr int kAR = kAV < 2 ? 1 : kAV / 2;         // rows each staging wave stages
   constexpr int kStagers = TR / kAR;                 // waves that stage A rows
   constexpr int kNV = Arith::kSum ? 3 : 2;           // staged values per row
@@ -496,36 +500,48 @@ __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const 
   const u64* Ab = A + cidx * 2 * tl.nA * 64 + lane;
   const u64* Bb = B + cidx * 2 * tl.nB * 64 + lane;
   const int64_t pA = tl.nA * 64, pB = tl.nB * 64;
-  const int j = h * kCols + wave;                    // this wave's column
-  const bool jin = j < Nc;
+  int jc[CPW];                                       // this wave's columns
+  bool jinc[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    jc[c] = h * kCols + c * kWavesPerBlock + wave;
+    jinc[c] = jc[c] < Nc;
+  }
+  const bool jin = jinc[0];
   const bool stager = wave < kStagers;
   const int arow = stager ? wave * kAR : 0;          // first row this wave stages
-  typename Arith::Acc acc[TR];
+  typename Arith::Acc acc[TR][CPW];
 #pragma unroll
-  for (int r = 0; r < TR; ++r) Arith::zero(acc[r]);
+  for (int r = 0; r < TR; ++r)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) Arith::zero(acc[r][c]);
 
-  typedef ColsEntry<TR> Entry;
+  typedef ColsEntry<TR, CPW> Entry;
   struct Pair {
     Entry e[2];
   };
   const int e0 = tl.tstart[g], e1 = tl.tstart[g + 1];
   auto fetch = [&](int x, int xend, Entry& st) {
     st.mask = 0;
-    st.bact = false;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) st.bact[c] = false;
     if (x >= xend) return;
     const int2 km = s_km[x];
     const int k = __builtin_amdgcn_readfirstlane(km.x);
     st.mask = __builtin_amdgcn_readfirstlane(km.y);
-    st.bact = jin;
-    if (jin) {
-      int64_t bsl = (int64_t)k * Nc + j;
-      if constexpr (BSP) {
-        bsl = tl.bslot[(int64_t)k * Nc + j];
-        st.bact = bsl >= 0;
-      }
-      if (st.bact) {
-        st.b0 = Bb[bsl * 64];
-        st.b1 = Bb[bsl * 64 + pB];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      st.bact[c] = jinc[c];
+      if (jinc[c]) {
+        int64_t bsl = (int64_t)k * Nc + jc[c];
+        if constexpr (BSP) {
+          bsl = tl.bslot[(int64_t)k * Nc + jc[c]];
+          st.bact[c] = bsl >= 0;
+        }
+        if (st.bact[c]) {
+          st.b0[c] = Bb[bsl * 64];
+          st.b1[c] = Bb[bsl * 64 + pB];
+        }
       }
     }
     if (!stager) return;
@@ -553,36 +569,49 @@ __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const 
   // what a pair's products need besides LDS: the B words and the row masks
   // (zero for an entry whose B_kj is zero or whose column is outside B)
   struct PairB {
-    u64 b00, b01, b10, b11;
-    int m0, m1;
+    u64 b0[2][CPW], b1[2][CPW];
+    int m[2][CPW];
   };
   auto take_b = [&](const Pair& pr) {
     PairB q;
-    q.b00 = pr.e[0].b0;
-    q.b01 = pr.e[0].b1;
-    q.b10 = pr.e[1].b0;
-    q.b11 = pr.e[1].b1;
-    q.m0 = pr.e[0].bact ? pr.e[0].mask : 0;
-    q.m1 = pr.e[1].bact ? pr.e[1].mask : 0;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        q.b0[x][c] = pr.e[x].b0[c];
+        q.b1[x][c] = pr.e[x].b1[c];
+        q.m[x][c] = pr.e[x].bact[c] ? pr.e[x].mask : 0;
+      }
     return q;
   };
-  // the products of one entry of a pair (B from registers, A from LDS)
-  auto compute1 = [&](u64 ub0, u64 ub1, int m, int bf, int ep) {
-    if (!m) return;
-    const Val b0 = Arith::load(ub0), b1 = Arith::load(ub1);
-    const Val bs = Arith::sum(b0, b1);
+  // the products of one entry of a pair (B from registers, A from LDS, read
+  // once per row for the wave's CPW columns)
+  auto compute1 = [&](const PairB& pb, int x, int bf) {
+    int mu = 0;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) mu |= pb.m[x][c];
+    if (!mu) return;
+    Val b0[CPW], b1[CPW], bs[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      b0[c] = Arith::load(pb.b0[x][c]);
+      b1[c] = Arith::load(pb.b1[x][c]);
+      bs[c] = Arith::sum(b0[c], b1[c]);
+    }
 #pragma unroll
     for (int r = 0; r < TR; ++r) {
-      if ((m >> r) & 1) {
-        const Val a0 = sa[bf][ep][r][0][lane], a1 = sa[bf][ep][r][1][lane];
-        const Val as = sa[bf][ep][r][kNV - 1][lane];
-        ar.mac(acc[r], a0, a1, as, b0, b1, bs);
+      if ((mu >> r) & 1) {
+        const Val a0 = sa[bf][x][r][0][lane], a1 = sa[bf][x][r][1][lane];
+        const Val as = sa[bf][x][r][kNV - 1][lane];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+          if ((pb.m[x][c] >> r) & 1) ar.mac(acc[r][c], a0, a1, as, b0[c], b1[c], bs[c]);
       }
     }
   };
   auto compute = [&](const PairB& pb, int bf) {
-    compute1(pb.b00, pb.b01, pb.m0, bf, 0);
-    compute1(pb.b10, pb.b11, pb.m1, bf, 1);
+    compute1(pb, 0, bf);
+    compute1(pb, 1, bf);
   };
   int cnt = 0, nfold = 0;
   for (int sg = e0; sg < e1; sg += kSegEntries) {
@@ -618,21 +647,27 @@ __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const 
         cnt = 0;
         ++nfold;
 #pragma unroll
-        for (int r = 0; r < TR; ++r) ar.fold(acc[r], nfold);
+        for (int r = 0; r < TR; ++r)
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) ar.fold(acc[r][c], nfold);
       }
     }
   }
   if (!jin) return;
 #pragma unroll
-  for (int r = 0; r < TR; ++r) {
-    const int pos = g * TR + r;
-    if (pos >= tl.rows) continue;
-    u64* dp_ = D + ((int64_t)pos * Nc + j) * (int64_t)3 * L * N + (int64_t)l * N + tbase + lane;
-    u64 d0, d1, d2;
-    ar.final(acc[r], d0, d1, d2);
-    dp_[0] = d0;
-    dp_[(int64_t)L * N] = d1;
-    dp_[(int64_t)2 * L * N] = d2;
+  for (int c = 0; c < CPW; ++c) {
+    if (!jinc[c]) continue;
+#pragma unroll
+    for (int r = 0; r < TR; ++r) {
+      const int pos = g * TR + r;
+      if (pos >= tl.rows) continue;
+      u64* dp_ = D + ((int64_t)pos * Nc + jc[c]) * (int64_t)3 * L * N + (int64_t)l * N + tbase + lane;
+      u64 d0, d1, d2;
+      ar.final(acc[r][c], d0, d1, d2);
+      dp_[0] = d0;
+      dp_[(int64_t)L * N] = d1;
+      dp_[(int64_t)2 * L * N] = d2;
+    }
   }
 }
 
@@ -681,16 +716,16 @@ static int launch_block(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl
   return SFHE_OK;
 }
 
-template <typename Arith, int TR, bool BSP>
+template <typename Arith, int TR, int CPW, bool BSP>
 static int launch_cols(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl, const u64* A, const u64* B, u64* D,
                        hipStream_t s) {
   if (fl.n == 0) return SFHE_OK;
   if (tl.tile_rows != TR) { set_error("tensor: tile list of another height"); return SFHE_E_INVALID_ARG; }
   TileList t2 = tl;
-  t2.n_col_tiles = (tl.Nc + kWavesPerBlock - 1) / kWavesPerBlock;
+  t2.n_col_tiles = (tl.Nc + kWavesPerBlock * CPW - 1) / (kWavesPerBlock * CPW);
   const int64_t blocks = (int64_t)fl.n * (c->N / 64) * tl.n_row_tiles * t2.n_col_tiles;
   if (blocks > 0x7FFFFFFF) { set_error("tensor: grid too large"); return SFHE_E_INVALID_ARG; }
-  hipLaunchKernelGGL((tensor_cols_kernel<Arith, TR, BSP>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, t2, A, B,
+  hipLaunchKernelGGL((tensor_cols_kernel<Arith, TR, CPW, BSP>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, t2, A, B,
                      D, fl, c->dp);
   SFHE_HIP(hipGetLastError());
   return SFHE_OK;
@@ -702,8 +737,8 @@ int tensor_fp_prime_count(const sfhe_ctx* c) {
   return n;
 }
 
-int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& tl_fp, const TileList& tl_i60,
-                        const u64* A, const u64* B, u64* D, hipStream_t s, hipEvent_t fp_start, hipEvent_t fp_stop) {
+int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& tl_cols, const u64* A, const u64* B,
+                        u64* D, hipStream_t s, hipEvent_t fp_start, hipEvent_t fp_stop) {
   if (tl.rows <= 0) return SFHE_OK;
   // primes below 2^42 use the fp64 residue arithmetic, the others 128-bit integers
   FpLimbs ffp{}, fint{}, f60{};
@@ -719,15 +754,15 @@ int launch_tensor_tiles(const sfhe_ctx* c, const TileList& tl, const TileList& t
   }
   if (fp_start) SFHE_HIP(hipEventRecord(fp_start, s));
   const bool bsp = tl.bslot != nullptr;
-  int rc = bsp ? launch_cols<ArithFp, kTileRowsFp, true>(c, tl_fp, ffp, A, B, D, s)
-               : launch_cols<ArithFp, kTileRowsFp, false>(c, tl_fp, ffp, A, B, D, s);
+  int rc = bsp ? launch_cols<ArithFp, kColTileRows, 2, true>(c, tl_cols, ffp, A, B, D, s)
+               : launch_cols<ArithFp, kColTileRows, 2, false>(c, tl_cols, ffp, A, B, D, s);
   if (fp_stop) SFHE_HIP(hipEventRecord(fp_stop, s));
   if (!rc)
     rc = bsp ? launch_block<ArithInt, 4, 1, true>(c, tl, fint, A, B, D, s)
              : launch_block<ArithInt, 4, 1, false>(c, tl, fint, A, B, D, s);
   if (!rc)
-    rc = bsp ? launch_cols<ArithInt60, kTileRowsInt60, true>(c, tl_i60, f60, A, B, D, s)
-             : launch_cols<ArithInt60, kTileRowsInt60, false>(c, tl_i60, f60, A, B, D, s);
+    rc = bsp ? launch_cols<ArithInt60, kColTileRows, 1, true>(c, tl_cols, f60, A, B, D, s)
+             : launch_cols<ArithInt60, kColTileRows, 1, false>(c, tl_cols, f60, A, B, D, s);
   return rc;
 }
 
