@@ -238,6 +238,27 @@ def test_matmul_ragged_hybrid_all_outputs(torch_cuda, enc, sched):
     assert np.max(np.abs(dec - A @ B)) < 1e-6
 
 
+@pytest.mark.parametrize("shape", [(11, 17, 29), (6, 9, 16)])
+def test_column_tiles_ragged_all_outputs(torch_cuda, shape):
+    """The fp64 column kernel takes 4-row tiles and 16 columns per block (two
+    per wave: w and w + 8): 11 x 17 x 29 leaves a last row tile of 3 rows and
+    a last column tile of 13 columns, so some waves hold one valid column of
+    their two; 6 x 9 x 16 is one full column tile over a ragged row tile.
+    Every output of the lazy product matches the oracle bit for bit."""
+    M, K, Nc = shape
+    ctx, orc = pair(HYB_SMALL, 21)
+    A, B = W.operands(M, K, Nc, 0.45, 7700 + M)
+    note("column tiles %dx%dx%d" % shape)
+    EA = ctx.encrypt(A, "csr", 1777, 0)
+    EB = ctx.encrypt(B, "dense", 1778, 1)
+    C = ctx.matmul(EA, EB, "lazy")
+    cts, _, _ = orc.matmul(A, B, "csr", "lazy", 1777, 1778, threads=_threads())
+    _all_outputs_equal(ctx, C, cts, M, Nc, "column tiles")
+    assert np.max(np.abs(ctx.decrypt(C) - A @ B)) < 1e-6
+    for m in (C, EA, EB):
+        m.close()
+
+
 @pytest.mark.parametrize("sched", ["lazy", "per_product"])
 def test_matmul_mixed_prime_sizes_all_outputs(torch_cuda, sched):
     """61-, 50- and 41-bit data primes: the 61- and 50-bit primes take the
