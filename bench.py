@@ -304,7 +304,10 @@ def slots_leg(ctx, torch, A, Bm, sa, sb, chunk, sched="lazy"):
     return out
 
 
-SERVING_POLICIES = [("fifo_1_stream", 1, 0), ("2_streams", 2, 0), ("2_streams_1_slot_each", 2, 1)]
+# (name, server streams, running batches per stream (0: no limit), batch
+# byte limit as a fraction of the budget (0: none))
+SERVING_POLICIES = [("fifo_1_stream", 1, 0, 0.0), ("2_streams", 2, 0, 0.0), ("2_streams_1_slot_each", 2, 1, 0.0),
+                    ("2_streams_half_budget_batches", 2, 0, 0.5)]
 
 
 def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
@@ -318,8 +321,8 @@ def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
     them).  The arrival rate is `load` times the service rate measured on one
     request of each layer alone.  Latency is arrival to result, host clock.
     The same arrivals are served under each admission policy of
-    SERVING_POLICIES (server streams, running batches per stream); the first
-    is the reported one."""
+    SERVING_POLICIES (server streams, running batches per stream, batch byte
+    limit); the first is the reported one."""
     P = W.PARAMS["serving_n32768"]
     cfg = 5
     ctx = sfhe.Context(**P)
@@ -376,8 +379,8 @@ def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
         C1.close()
         solo.close()
 
-    def serve(n_streams, slots):
-        srv = sfhe.Server(ctx, budget, n_streams=n_streams, slots=slots)
+    def serve(n_streams, slots, cap_frac):
+        srv = sfhe.Server(ctx, budget, n_streams=n_streams, slots=slots, batch_bytes=int(budget * cap_frac))
         tickets, done_at, results, sizes = {}, {}, {}, []
         step_s, step_max = 0.0, 0.0
         t0 = time.perf_counter()
@@ -435,7 +438,7 @@ def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
         for C in results.values():
             C.close()
         srv.close()
-        return {"streams": n_streams, "slots_per_stream": slots,
+        return {"streams": n_streams, "slots_per_stream": slots, "batch_bytes_limit": int(budget * cap_frac),
                 "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
                 "latency_ms_mean": float(lat.mean()), "makespan_s": makespan, "products": int(st["products"]),
                 "ctpt_mults_per_s": st["products"] / makespan, "batches": int(st["batches"]),
@@ -446,8 +449,8 @@ def serving_leg(torch, sfhe, W, n_requests=96, load=0.8, pool_per_layer=2):
                 "host_step_ms_sum": step_s * 1e3, "host_step_ms_max": step_max * 1e3}
 
     policies = {}
-    for name, n_streams, slots in SERVING_POLICIES:
-        policies[name] = serve(n_streams, slots)
+    for name, n_streams, slots, cap_frac in SERVING_POLICIES:
+        policies[name] = serve(n_streams, slots, cap_frac)
         log("serving %s: p50 %.1f ms, p99 %.1f ms, %d batches, %d overlapping, host step %.0f ms" %
             (name, policies[name]["latency_ms_p50"], policies[name]["latency_ms_p99"], policies[name]["batches"],
              policies[name]["batches_overlapping_another"], policies[name]["host_step_ms_sum"]))

@@ -391,6 +391,12 @@ int sfhe_server_create(sfhe_ctx* ctx, uint64_t budget_bytes, int32_t n_streams, 
 /* at most per_stream running batches per server stream (0, the default: no
  * limit); negative is SFHE_E_INVALID_ARG */
 int sfhe_server_set_slots(sfhe_server* srv, int32_t per_stream);
+/* at most max_bytes (as sfhe_server_request_bytes counts them) in one batch
+ * (0, the default: no limit); a request larger than the limit runs as a
+ * batch of its own.  With a limit of budget_bytes / n_streams every server
+ * stream can hold a running batch at once, so batches overlap on the device
+ * even when the requests alone would fill the budget. */
+int sfhe_server_set_batch_bytes(sfhe_server* srv, uint64_t max_bytes);
 /* the device bytes the server counts for request W X against its budget */
 int sfhe_server_request_bytes(const sfhe_ctx* ctx, const sfhe_mat* W, const sfhe_mat* X, uint64_t* bytes);
 /* queue W X; a request larger than the budget is SFHE_E_NOMEM */

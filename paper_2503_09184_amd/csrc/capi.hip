@@ -1902,6 +1902,7 @@ struct sfhe_server {
   std::vector<hipStream_t> streams;       // the server's own, default priority
   std::vector<int> busy;                  // running batches per stream
   int slots = 0;                          // running batches a stream may hold (0: no limit)
+  uint64_t batch_cap = 0;                 // bytes one batch may hold (0: no limit)
   hipEvent_t epoch = nullptr;             // device-time origin of the batch intervals
   uint64_t budget = 0, in_flight = 0;
   struct Req {
@@ -2024,7 +2025,11 @@ int sfhe_server_step(sfhe_server* v, int32_t* admitted) {
   if (v->slots > 0 && v->busy[sx] >= v->slots) return SFHE_OK;
   std::vector<const sfhe_mat*> Ws, Xs;
   sfhe_server::Run run;
-  while (!v->queue.empty() && v->in_flight + run.bytes + v->queue.front().bytes <= v->budget) {
+  // requests join the batch in order while they fit the budget beside the
+  // running batches and, with a cap, the batch's own limit (a request larger
+  // than the cap forms a batch of its own)
+  while (!v->queue.empty() && v->in_flight + run.bytes + v->queue.front().bytes <= v->budget &&
+         (v->batch_cap == 0 || run.bytes == 0 || run.bytes + v->queue.front().bytes <= v->batch_cap)) {
     const sfhe_server::Req& q = v->queue.front();
     Ws.push_back(q.W);
     Xs.push_back(q.X);
@@ -2127,6 +2132,14 @@ int sfhe_server_set_slots(sfhe_server* v, int32_t per_stream) {
   GUARD_BEGIN
   if (!v || per_stream < 0) { set_error("NULL server or negative slot limit"); return SFHE_E_INVALID_ARG; }
   v->slots = per_stream;
+  return SFHE_OK;
+  GUARD_END
+}
+
+int sfhe_server_set_batch_bytes(sfhe_server* v, uint64_t max_bytes) {
+  GUARD_BEGIN
+  if (!v) { set_error("NULL server"); return SFHE_E_INVALID_ARG; }
+  v->batch_cap = max_bytes;
   return SFHE_OK;
   GUARD_END
 }

@@ -33,7 +33,8 @@ EXPORTED = [
     "sfhe_server_destroy", "sfhe_plain_graph_create", "sfhe_plain_graph_launch", "sfhe_plain_graph_result",
     "sfhe_plain_graph_destroy", "sfhe_encrypt_matrix_slots", "sfhe_matmul_slots", "sfhe_export_stored",
     "sfhe_rotate", "sfhe_ntt_tuning", "sfhe_set_ntt_variant", "sfhe_keyswitch_noalloc",
-    "sfhe_probe_valu", "sfhe_server_request_bytes", "sfhe_server_set_slots", "sfhe_ks_tuning", "sfhe_set_ks_slice",
+    "sfhe_probe_valu", "sfhe_server_request_bytes", "sfhe_server_set_slots", "sfhe_server_set_batch_bytes",
+    "sfhe_ks_tuning", "sfhe_set_ks_slice",
     "sfhe_matmul_graph_create", "sfhe_matmul_graph_launch", "sfhe_matmul_graph_result", "sfhe_matmul_graph_destroy",
 ]
 
@@ -128,6 +129,7 @@ def lib():
                                               ctypes.POINTER(vp)]
         L.sfhe_server_create.argtypes = [vp, u64, i32, vp, ctypes.POINTER(vp)]
         L.sfhe_server_set_slots.argtypes = [vp, i32]
+        L.sfhe_server_set_batch_bytes.argtypes = [vp, ctypes.c_uint64]
         L.sfhe_server_submit.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
         L.sfhe_server_request_bytes.argtypes = [vp, vp, vp, ctypes.POINTER(u64)]
         L.sfhe_server_step.argtypes = [vp, ctypes.POINTER(i32)]
@@ -279,9 +281,10 @@ class MatmulGraph:
 class Server:
     """The library's request loop over plaintext-weight products (a handle)."""
 
-    def __init__(self, ctx, budget_bytes, stream=None, n_streams=1, slots=0):
+    def __init__(self, ctx, budget_bytes, stream=None, n_streams=1, slots=0, batch_bytes=0):
         """n_streams: the server's streams (1: batches run in admission
-        order); slots: running batches a stream may hold (0: no limit)."""
+        order); slots: running batches a stream may hold (0: no limit);
+        batch_bytes: bytes one batch may hold (0: no limit)."""
         self.ctx = ctx
         h = ctypes.c_void_p()
         _check(lib().sfhe_server_create(ctx._h, ctypes.c_uint64(int(budget_bytes)), int(n_streams),
@@ -289,11 +292,17 @@ class Server:
         self._h = h
         if slots:
             self.set_slots(slots)
+        if batch_bytes:
+            self.set_batch_bytes(batch_bytes)
         self.intervals = {}   # ticket -> (start_ms, end_ms) of its batch on the device
 
     def set_slots(self, per_stream):
         """at most per_stream running batches per server stream (0: no limit)"""
         _check(lib().sfhe_server_set_slots(self._h, int(per_stream)))
+
+    def set_batch_bytes(self, max_bytes):
+        """at most max_bytes in one batch (0: no limit)"""
+        _check(lib().sfhe_server_set_batch_bytes(self._h, ctypes.c_uint64(int(max_bytes))))
 
     def request_bytes(self, W, X):
         """Device bytes counted for request W X against the budget."""

@@ -159,6 +159,50 @@ def test_serving_policies_fifo_and_slot_limit(torch_cuda):
         srv.close()
 
 
+def test_batch_byte_limit(torch_cuda):
+    """With a batch limit of about two requests' bytes, every batch holds at
+    most what fits the limit (a request larger than it runs alone), the
+    requests still run in ticket order on one stream, and every result equals
+    the request alone."""
+    from paper_2503_09184_amd import sfhe
+    ctx, _ = pair(HYB_SMALL, 21)
+    reqs = _requests(ctx)
+    probe = sfhe.Server(ctx, 1 << 40)
+    sizes = [_counted(probe, r) for r in reqs]
+    probe.close()
+    cap = sorted(sizes)[len(sizes) // 2] * 2
+    alone = []
+    for n, (Wt, X, Wp, EX) in enumerate(reqs):
+        srv = sfhe.Server(ctx, 1 << 40)
+        t = srv.submit(Wp, EX)
+        srv.step()
+        alone.append(_cts(ctx, srv.poll(t, wait=True)[1], REQS[n][0], REQS[n][2]))
+        srv.close()
+    note("serving batch limit %d bytes" % cap)
+    srv = sfhe.Server(ctx, 1 << 40, batch_bytes=cap)
+    tickets = [srv.submit(Wp, EX) for Wt, X, Wp, EX in reqs]
+    while srv.status()["queued"]:
+        srv.step()
+    results, batch_of = {}, {}
+    for n, t in enumerate(tickets):
+        done, C, _, bs = srv.poll(t, wait=True)
+        assert done
+        results[n] = C
+        batch_of[n] = srv.intervals[t]
+    groups = {}
+    for n, iv in batch_of.items():
+        groups.setdefault(iv, []).append(n)
+    assert len(groups) > 1
+    for members in groups.values():
+        assert len(members) == 1 or sum(sizes[n] for n in members) <= cap, (members, cap)
+        assert members == list(range(members[0], members[0] + len(members)))   # consecutive tickets
+    for n, (M, K, b, s) in enumerate(REQS):
+        for x, y in zip(_cts(ctx, results[n], M, b), alone[n]):
+            assert np.array_equal(x, y), n
+    assert sfhe.lib().sfhe_server_set_batch_bytes(None, 5) == -1           # SFHE_E_INVALID_ARG
+    srv.close()
+
+
 @pytest.mark.parametrize("torch_allocator", [True, False])
 def test_results_outlive_the_server(torch_cuda, torch_allocator):
     """A result polled from a server stays valid after the server (and its
