@@ -202,6 +202,29 @@ __device__ __forceinline__ void k2_products(const Ar& ar, typename Ar::Val (&v)[
   }
 }
 
+// a special prime's key products from two transformed digits: X0 (the first
+// digit, stored in o0 by this thread at the same positions) and X1 (in v):
+// s_p = X0 rlk_{j0},p + X1 rlk_{j1},p; s_0 stays in v for the inverse
+// transform, s_1 goes to o1.  The two digits' partial sums never make a round
+// trip through memory; only X0 does.
+template <typename Ar>
+__device__ __forceinline__ void k2_products_two(const Ar& ar, typename Ar::Val (&v)[32], const KeyRows& k0,
+                                                const KeyRows& k1, const u64* x0, u64* o1, u64 q, int t) {
+  const int tt = after(t, v[15], v[31]);
+#pragma unroll
+  for (int r = 0; r < 32; ++r) {
+    const int x = pos_c(tt, r);
+    const u64 X1 = ar.fwd_res(v[r]);
+    const u64 X0 = x0[x];
+    const u64 s0 = add_mod(mul_shoup(X0, k0.k[x], k0.ks[x], q), mul_shoup(X1, k1.k[x], k1.ks[x], q), q);
+    const u64 s1 = add_mod(mul_shoup(X0, k0.k[k0.next + x], k0.ks[k0.next + x], q),
+                           mul_shoup(X1, k1.k[k1.next + x], k1.ks[k1.next + x], q), q);
+    v[r] = ar.in(s0);
+    o1[x] = s1;
+    group_fence<2>(r);
+  }
+}
+
 // step IT of the digit loop of k2_body, unrolled at compile time
 template <int IT, int NT, bool SPECIAL, typename Ar>
 __device__ __forceinline__ void k2_steps(const Ar& ar, typename Ar::Val (&v)[32], typename Ar::Val* sh, const Ks14Args& a,
@@ -223,8 +246,11 @@ __device__ __forceinline__ void k2_steps(const Ar& ar, typename Ar::Val (&v)[32]
 // for a data prime, part for a special one), the same words the same thread
 // wrote before, so no synchronisation is needed.  The digit holding a data
 // prime e needs no transform and is folded into the last pass.  For a special
-// prime the last pass keeps acc_0 in registers for the inverse transform.  NT
-// is a template argument so that no transform sits inside a run-time loop.
+// prime the last pass keeps acc_0 in registers for the inverse transform; with
+// two digits the first digit's transformed row is kept instead of its two key
+// products (one row written and read back instead of two), and both digits'
+// products are formed in the second pass.  NT is a template argument so that
+// no transform sits inside a run-time loop.
 template <int NT, bool SPECIAL, typename Ar>
 __device__ __forceinline__ void k2_body(const Ks14Args& a, const DevParams& dp, int b, int e, void* lds) {
   typedef typename Ar::Val Val;
@@ -250,7 +276,27 @@ __device__ __forceinline__ void k2_body(const Ks14Args& a, const DevParams& dp, 
   const u64* d2e = a.D + (int64_t)b * a.dw + (int64_t)(2 * a.nl + (SPECIAL ? 0 : re)) * kN;
   const Ar ar(P, false);
   Val v[32];
-  k2_steps<0, NT, SPECIAL>(ar, v, sh, a, js, b, e, ne, re, nb, okrow, d2e, o0, o1, q, t);
+  if constexpr (SPECIAL && NT == 2) {
+    // the first digit's transform is kept (one row) until the second's is done
+    load_a(ar, v, a.ext + ((int64_t)b * a.next + ext_slot(a.mu, ne, js[0], e)) * kN, t);
+    n14::forward(ar, v, sh, t);
+    {
+      const int tt = after(t, v[15], v[31]);
+#pragma unroll
+      for (int r = 0; r < 32; ++r) {
+        o0[pos_c(tt, r)] = ar.fwd_res(v[r]);
+        group_fence<8>(r);
+      }
+    }
+    load_a(ar, v, a.ext + ((int64_t)b * a.next + ext_slot(a.mu, ne, js[1], e)) * kN, t);
+    n14::forward(ar, v, sh, t);
+    const int64_t kr0 = ((int64_t)js[0] * 2 * nb + re) * kN, kr1 = ((int64_t)js[1] * 2 * nb + re) * kN;
+    const KeyRows K0{a.rlk + kr0, a.rlk_s + kr0, nullptr, nullptr, (int64_t)nb * kN};
+    const KeyRows K1{a.rlk + kr1, a.rlk_s + kr1, nullptr, nullptr, (int64_t)nb * kN};
+    k2_products_two(ar, v, K0, K1, o0, o1, q, t);
+  } else {
+    k2_steps<0, NT, SPECIAL>(ar, v, sh, a, js, b, e, ne, re, nb, okrow, d2e, o0, o1, q, t);
+  }
   if (!SPECIAL) return;
   // special prime p_k: both sums back to coefficients, times (P/p_k)^-1 N^-1
   const Ar ai(P, true);
