@@ -463,6 +463,23 @@ struct ColsEntry {
   bool bact[CPW];
 };
 
+// B's words go through a raw buffer resource: a wave-uniform base and byte
+// offset in scalar registers and the lane's byte offset in one vector
+// register set up once, so a load takes no vector address arithmetic (one
+// (prime, chunk) slice of B is below 2^31 bytes).  The base is read through
+// readfirstlane so that the resource is known to be uniform.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slice_rsrc(const u64* base, int64_t bytes) {
+  const u64 p = (u64)base;
+  const u64 pu = ((u64)(u32)__builtin_amdgcn_readfirstlane((int)(p >> 32)) << 32) |
+                 (u32)__builtin_amdgcn_readfirstlane((int)(u32)p);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)pu, (short)0, __builtin_amdgcn_readfirstlane((int)bytes), 0x00020000);
+}
+__device__ __forceinline__ u64 slice_load(__amdgpu_buffer_rsrc_t r, unsigned lane_off, int off) {
+  const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, off, 0);
+  return ((u64)v.y << 32) | v.x;
+}
+
 template <typename Arith, int TR, int CPW, bool BSP>
 __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const u64* A, const u64* B, u64* D,
                                                             FpLimbs fl, DevParams dp) {
@@ -498,8 +515,10 @@ __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const 
   const int Nc = tl.Nc;
   const int64_t cidx = (int64_t)l * (N >> 6) + (tbase >> 6);
   const u64* Ab = A + cidx * 2 * tl.nA * 64 + lane;
-  const u64* Bb = B + cidx * 2 * tl.nB * 64 + lane;
-  const int64_t pA = tl.nA * 64, pB = tl.nB * 64;
+  const __amdgpu_buffer_rsrc_t rB = slice_rsrc(B + cidx * 2 * tl.nB * 64, (int64_t)tl.nB * 1024);
+  const unsigned loff = (unsigned)lane * 8u;
+  const int pBb = (int)tl.nB * 512;   // byte offset of poly 1
+  const int64_t pA = tl.nA * 64;
   int jc[CPW];                                       // this wave's columns
   bool jinc[CPW];
 #pragma unroll
@@ -539,8 +558,8 @@ __global__ void __launch_bounds__(512, 4) tensor_cols_kernel(TileList tl, const 
           st.bact[c] = bsl >= 0;
         }
         if (st.bact[c]) {
-          st.b0[c] = Bb[bsl * 64];
-          st.b1[c] = Bb[bsl * 64 + pB];
+          st.b0[c] = slice_load(rB, loff, (int)bsl * 512);
+          st.b1[c] = slice_load(rB, loff, (int)bsl * 512 + pBb);
         }
       }
     }
@@ -721,6 +740,8 @@ static int launch_cols(const sfhe_ctx* c, const TileList& tl, const FpLimbs& fl,
                        hipStream_t s) {
   if (fl.n == 0) return SFHE_OK;
   if (tl.tile_rows != TR) { set_error("tensor: tile list of another height"); return SFHE_E_INVALID_ARG; }
+  // B's words are addressed by 32-bit byte offsets within one (prime, chunk) slice
+  if (tl.nB * 1024 > 0x7FFFFFFF) { set_error("tensor: right operand too large"); return SFHE_E_INVALID_ARG; }
   TileList t2 = tl;
   t2.n_col_tiles = (tl.Nc + kWavesPerBlock * CPW - 1) / (kWavesPerBlock * CPW);
   const int64_t blocks = (int64_t)fl.n * (c->N / 64) * tl.n_row_tiles * t2.n_col_tiles;
