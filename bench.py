@@ -766,7 +766,7 @@ def main():
     cpu = None
     if not args.no_cpu and run("cpu"):
         affinity = len(os.sched_getaffinity(0))
-        # a one-GPU machine's CPU share is 16 threads, whatever the affinity mask shows
+        # at most 16 threads: the host cores that go with one GPU, whatever the affinity mask shows
         threads = max(1, min(affinity, 16))
         log("cpu baseline: oracle on %d threads (%d in the affinity mask)" % (threads, affinity))
         cpu = cpu_baseline(P, A, Bm, cfg_id, threads)
